@@ -1,0 +1,222 @@
+"""Throughput benchmark on one MI355X.
+
+Workload (many independent streams of every generator): for each of the 11
+generators, 65536 streams with ids drawn uniformly from [0, 10^19) are
+initialised by block splitting (stream id = default state jumped id * L
+outputs) and each stream then generates 16384 32-bit words -- 2^30 words per
+generator.  One step = stream initialisation + generation for all 11
+generators.  Inputs (ids) and outputs stay in HBM.
+
+Prints one JSON line: whole-step throughput in numbers/s, per-generator
+figures, the roofline of the kernel that takes most of the step, and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit lane ops/s: 256 CUs x 64 lanes x 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--streams", type=int, default=65536)
+    ap.add_argument("--words", type=int, default=16384)
+    ap.add_argument("--gens", type=str, default="all")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dtype-sweep", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_1307_5869_amd import prand as P
+    from paper_1307_5869_amd import workloads as W
+
+    if not os.path.exists(P.LIB_PATH):
+        raise SystemExit("libprand.so is not built: python -m paper_1307_5869_amd.build")
+    gens = list(range(P.NUM_GENERATORS)) if args.gens == "all" else [int(g) for g in args.gens.split(",")]
+    S, N = args.streams, args.words
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0)
+    stream = torch.cuda.current_stream()
+    ids = {g: torch.from_numpy(W.stream_ids(S, g).view(np.int64)).to(dev) for g in gens}
+    sb_max = max(P.state_bytes(g) for g in gens)
+    states = torch.empty(S * sb_max, dtype=torch.uint8, device=dev)
+    out = torch.empty(S * N, dtype=torch.int32, device=dev)
+    # (gen, phase) -> list of (start, end) events
+    ev = {}
+
+    def step(record):
+        for g in gens:
+            e0 = torch.cuda.Event(enable_timing=True) if record else None
+            e1 = torch.cuda.Event(enable_timing=True) if record else None
+            e2 = torch.cuda.Event(enable_timing=True) if record else None
+            if record:
+                e0.record(stream)
+            ctx.init_streams_dev(g, P.SEQ_DEFAULT, None, ids[g], S, states, stream)
+            if record:
+                e1.record(stream)
+            ctx.generate_streams(g, states, S, N, P.U32, out, stream)
+            if record:
+                e2.record(stream)
+                ev.setdefault((g, "init"), []).append((e0, e1))
+                ev.setdefault((g, "gen"), []).append((e1, e2))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    numbers = len(gens) * S * N
+    value = numbers * args.steps / wall
+
+    def avg_ms(key):
+        return float(np.mean([a.elapsed_time(b) for a, b in ev[key]]))
+
+    per_gen = {}
+    for g in gens:
+        ti, tg = avg_ms((g, "init")), avg_ms((g, "gen"))
+        per_gen[P.NAMES[g]] = {"init_ms": round(ti, 4), "gen_u32_ms": round(tg, 4),
+                               "gen_u32_numbers_per_s": S * N / (tg * 1e-3),
+                               "streams_init_per_s": S / (ti * 1e-3)}
+    # dominant kernel of the step
+    key = max(ev, key=avg_ms)
+    g, phase = key
+    t = avg_ms(key) * 1e-3
+    if phase == "gen":
+        sb = P.state_bytes(g)
+        if g in (P.MT19937, P.MRG32K3A, P.LFSR113):
+            traffic = S * N * 4 + 2 * S * sb     # outputs + state read/write
+            roof = {"kernel": f"{P.NAMES[g]} generate", "bound": "hbm", "achieved": traffic / t / 1e9,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        else:
+            ops = S * N * 32 * 6                 # element-steps x 6 ops (2 mul, sub, 2 reduce, cmp)
+            roof = {"kernel": f"{P.NAMES[g]} generate", "bound": "alu", "achieved": ops / t / 1e12,
+                    "peak": VALU_PEAK_TOPS, "unit": "Tops/s"}
+    else:
+        if g == P.MT19937:
+            # XOR-sum: per stream, one polynomial per set bit of the id, each
+            # costing (set coefficients ~ 19937/2) x 624 word XORs
+            idv = W.stream_ids(S, g)
+            apps = int(sum(bin(int(x)).count("1") for x in idv))
+            ops = apps * (19937 // 2) * 624
+            roof = {"kernel": "MT19937 jump", "bound": "alu", "achieved": ops / t / 1e12, "peak": VALU_PEAK_TOPS,
+                    "unit": "Tops/s"}
+        else:
+            sb = P.state_bytes(g)
+            roof = {"kernel": f"{P.NAMES[g]} jump", "bound": "hbm", "achieved": 2 * S * sb / t / 1e9,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["avg_ms"] = t * 1e3
+    roof["traffic"] = None
+
+    extra = {}
+    if not args.no_dtype_sweep:
+        # outside the timed region: every dtype for every generator, one launch each
+        big = torch.empty(S * N * 2, dtype=torch.int32, device=dev)
+        for g in gens:
+            ctx.init_streams_dev(g, P.SEQ_DEFAULT, None, ids[g], S, states, stream)
+            r = {}
+            for dt, name in ((P.U32, "u32"), (P.F32, "f32"), (P.F64, "f64")):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                ctx.generate_streams(g, states, S, N, dt, big, stream)
+                b.record(stream)
+                b.synchronize()
+                ms = a.elapsed_time(b)
+                es = 8 if dt == P.F64 else 4
+                r[name] = {"ms": round(ms, 4), "numbers_per_s": S * N / (ms * 1e-3),
+                           "write_GBs": S * N * es / (ms * 1e-3) / 1e9}
+            extra[P.NAMES[g]] = r
+        del big
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(gens, S, N)
+
+    line = {
+        "metric": "uniform numbers/sec per generator (bit-exact); batched vs plain; serve p99 ms",
+        "value": value,
+        "unit": "numbers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(gens)} generators x {S} streams (block-split, ids uniform in [0,1e19)) "
+                               f"x {N} u32 words; step = stream init + generation",
+                   "streams_per_generator": S, "words_per_stream": N, "generators": [P.NAMES[g] for g in gens],
+                   "parallelism": "1 GPU"},
+        "roofline": roof,
+        "per_generator": per_gen,
+        "dtype_sweep": extra,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(gens, S, N):
+    """The oracle (single-threaded C, untuned) on host threads over streams:
+    per generator a sample of streams is initialised by block splitting and
+    generates N words; the full workload's CPU time is scaled from it."""
+    from oracle import Oracle
+    from paper_1307_5869_amd import workloads as W
+
+    O = Oracle()
+    O.mt_charpoly()   # one-time polynomial set-up, not part of the timing
+    cores = min(16, os.cpu_count() or 1)
+    total_cpu_s = 0.0
+    sample_desc = []
+    for g in gens:
+        ns = 2 * cores if g == 0 else 8 * cores
+        sid = W.stream_ids(S, g)[:ns]
+        bufs = [np.empty(N, dtype=np.uint32) for _ in range(ns)]
+
+        def work(k0):
+            for k in range(k0, ns, cores):
+                st = O.init_stream(g, 0, int(sid[k]))
+                O.generate_into(g, st, 0, bufs[k])
+
+        th = [threading.Thread(target=work, args=(c,)) for c in range(cores)]
+        t0 = time.perf_counter()
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        dt = time.perf_counter() - t0
+        total_cpu_s += dt * S / ns
+        sample_desc.append(f"{ns}")
+    value = len(gens) * S * N / total_cpu_s
+    return {"value": value, "unit": "numbers/s", "cores": cores, "kind": "oracle",
+            "sample": f"per generator the first k streams of the workload (k = {','.join(sample_desc)}), "
+                      f"init + {N} words each, {cores} threads over streams; scaled to {S} streams"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * prand.h -- C ABI of an MI355X (gfx950) library for bulk parallel uniform
+ * pseudorandom number generation with the eleven generators of Barash &
+ * Shchur, "PRAND: GPU accelerated parallel random number generation library",
+ * Comput. Phys. Commun. 185 (2014) 1343.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns int: PRAND_OK (0) on success, a negative
+ *    PRAND_E* code on failure; prand_strerror() names a code.  No C++
+ *    exception crosses this boundary.  On failure nothing has been enqueued
+ *    and no state has been modified, except PRAND_EHIP, which reports a HIP
+ *    runtime error (prand_last_hip_error() gives the hipError_t value).
+ *  - "h_" pointers are host memory, "d_" pointers are device memory of the
+ *    context's device.  The caller owns every state and output buffer; the
+ *    context owns only its constant tables.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Functions taking
+ *    only device buffers are asynchronous: they enqueue kernels on `stream`
+ *    and return.  Functions taking a host state block until the state has
+ *    been updated (the paper's host interface, section "Function call
+ *    interface").
+ *  - A generator state is a plain-old-data blob of prand_state_bytes(gen)
+ *    bytes, little-endian, with the same layout on host and device, so it can
+ *    be copied between them freely (paper, section "Function call
+ *    interface": states may be advanced on the CPU and continued on the GPU):
+ *      MT19937   uint32 mt[624], uint32 index (0..624), uint32 pad[3]
+ *      MRG32K3A  uint32 x_n, x_{n-1}, x_{n-2} (mod m1), y_n, y_{n-1}, y_{n-2} (mod m2)
+ *      LFSR113   uint32 z[4]
+ *      GM/GQ     uint64 xprev[32], uint64 xcur[32] (elements >= s are 0),
+ *                uint32 word offset inside the current 8-step block (GQ58.3
+ *                only, else 0), uint32 pad
+ *  - Outputs: word i of a stream is the i-th 32-bit output; PRAND_F32 stores
+ *    (w >> 8) * 2^-24, PRAND_F64 stores w * 2^-32, except MRG32K3A whose
+ *    PRAND_F64 stores z * RN(1/(m1+1)) in (0,1) (the generator's usual
+ *    normalisation).  Many-stream outputs are row-major: out[stream][i].
+ *  - Distances ("skip ahead", block lengths) count 32-bit outputs, given as
+ *    little-endian uint64 limbs; up to 8 limbs (2^512).
+ */
+#ifndef PRAND_H
+#define PRAND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The generators of the paper's Table 2 ("Parameters of the generators"). */
+enum prand_gen {
+  PRAND_MT19937 = 0,   /* Matsumoto-Nishimura Mersenne twister, period 2^19937-1 */
+  PRAND_MRG32K3A = 1,  /* L'Ecuyer's combined MRG, matrices A, B of the MRG32K3A jump section */
+  PRAND_LFSR113 = 2,   /* four combined shift registers, relations lfsrRel1/lfsrOutput */
+  PRAND_GM19 = 3,      /* torus-map ensembles, recurrence rec1 with (k, q, g, v) of Table 2 */
+  PRAND_GM29 = 4,
+  PRAND_GM31 = 5,
+  PRAND_GM55 = 6,
+  PRAND_GM61 = 7,
+  PRAND_GQ58X1 = 8,
+  PRAND_GQ58X3 = 9,    /* 36 output bits per step: 9 words per 8 steps */
+  PRAND_GQ58X4 = 10
+};
+#define PRAND_NUM_GENERATORS 11
+
+enum prand_dtype { PRAND_U32 = 0, PRAND_F32 = 1, PRAND_F64 = 2 };
+
+/* Stream-initialising functions of the paper's Table 4 ("Initialization of
+   pseudorandom streams"): rng_init_sequence_, rng_init_short_sequence_,
+   rng_init_medium_sequence_, rng_init_long_sequence_.  PRAND_SEQ_DEFAULT is
+   PRAND_SEQ where the generator has it, else PRAND_SEQ_SHORT. */
+enum prand_variant {
+  PRAND_SEQ_DEFAULT = 0,
+  PRAND_SEQ = 1,
+  PRAND_SEQ_SHORT = 2,
+  PRAND_SEQ_MEDIUM = 3,
+  PRAND_SEQ_LONG = 4
+};
+
+#define PRAND_OK 0
+#define PRAND_EINVAL (-1)        /* null pointer, bad enum value, limb count out of range */
+#define PRAND_EUNSUPPORTED (-2)  /* variant not listed in Table 4 for this generator */
+#define PRAND_ERANGE (-3)        /* size beyond what the entry point accepts */
+#define PRAND_EHIP (-4)          /* HIP runtime error, see prand_last_hip_error() */
+#define PRAND_ENOMEM (-5)        /* allocation failed */
+#define PRAND_ENODEV (-6)        /* no usable gfx950 device */
+
+typedef struct prand_ctx prand_ctx;
+
+/* Text for an error code.  Never NULL; the string is static. */
+const char* prand_strerror(int code);
+
+/* hipError_t of the most recent PRAND_EHIP returned through this context. */
+int prand_last_hip_error(const prand_ctx* ctx);
+
+/* Create a context on HIP device `hip_device`: uploads the jump-ahead tables
+   (the counterpart of the paper's rng_init_device_consts_, section "Function
+   call interface for MRG32K3A / MT19937"): matrix powers A^(2^j), B^(2^j) for
+   MRG32K3A, 32x32 F2 matrix powers for LFSR113, 2x2 matrix powers for GM/GQ,
+   and x^(2^j) mod phi for MT19937 (equation g_v; phi is computed once by
+   Berlekamp-Massey).  *ctx is set to NULL on failure. */
+int prand_ctx_create(prand_ctx** ctx, int hip_device);
+
+/* Free the context's device tables (rng_free_device_consts_).  NULL is OK. */
+int prand_ctx_destroy(prand_ctx* ctx);
+
+/* Size in bytes of the state blob of `gen`; 0 for an invalid generator. */
+size_t prand_state_bytes(int gen);
+
+/* Block-splitting block length: stream `id` starts id * L outputs into the
+   base sequence, L = 2^e ensemble steps (= 2^e outputs except GQ58.3, where
+   it is 9 * 2^(e-3) outputs).  Returns e >= 0, or PRAND_EUNSUPPORTED /
+   PRAND_EINVAL.  (Paper, section "Parallel streams", Table 4.) */
+int prand_block_log2(int gen, int variant);
+
+/* Table 4 metadata: the number of independent sequences and the maximal
+   length the paper guarantees for this initialising function. */
+int prand_independence_limit(int gen, int variant, double* max_streams, double* max_length);
+
+/* Default state (rng_init_): MT19937 init_genrand(5489), MRG32K3A and
+   LFSR113 all words 12345, GM/GQ the seed-0 expansion.  Blocks. */
+int prand_init_default(prand_ctx* ctx, int gen, void* h_state);
+
+/* Seeded state.  MT19937: init_genrand(seed) for seed < 2^32, else
+   init_by_array over the two 32-bit halves.  MRG32K3A: all six words = seed
+   when 1 <= seed < m2.  LFSR113: all four words = seed when
+   128 <= seed < 2^32.  Otherwise (and for GM/GQ, per element) SplitMix64
+   draws reduced by rejection.  Blocks. */
+int prand_seed(prand_ctx* ctx, int gen, uint64_t seed, void* h_state);
+
+/* count states from count seeds, on the device. */
+int prand_seed_dev(prand_ctx* ctx, int gen, const uint64_t* d_seeds, uint32_t count,
+                   void* d_states, void* stream);
+
+/* Jump a host state ahead by `dist` outputs (rng_skipahead_, section
+   "Jumping ahead").  dist: nlimbs little-endian uint64 limbs, 0 <= nlimbs
+   <= 8.  Runs on the device; blocks. */
+int prand_skipahead(prand_ctx* ctx, int gen, void* h_state, const uint64_t* h_dist, int nlimbs);
+
+/* Jump count device states ahead.  d_dist holds nlimbs limbs per stream
+   (count * nlimbs uint64, stream-major) when per_stream != 0, else one
+   distance of nlimbs limbs shared by all streams. */
+int prand_skipahead_dev(prand_ctx* ctx, int gen, void* d_states, uint32_t count,
+                        const uint64_t* d_dist, int nlimbs, int per_stream, void* stream);
+
+/* Stream `id` by block splitting (rng_init_sequence_ and variants): the
+   default state jumped ahead id * L outputs.  Any uint64 id is accepted;
+   independence is only claimed below prand_independence_limit().  Blocks. */
+int prand_init_stream(prand_ctx* ctx, int gen, int variant, uint64_t id, void* h_state);
+
+/* count streams on the device: d_states[i] = base jumped id[i] * L.
+   d_base_state: a device state blob, or NULL for the default state. */
+int prand_init_streams_dev(prand_ctx* ctx, int gen, int variant, const void* d_base_state,
+                           const uint64_t* d_ids, uint32_t count, void* d_states, void* stream);
+
+/* Fill d_out with the next n outputs of one host state (rng_generate_gpu_
+   array_[float_|double_], section "Multi-threaded generation"): the array is
+   cut into sections that jump to their start and fill in parallel; the
+   result equals sequential generation for every n (no divisibility or
+   power-of-two condition).  h_state is advanced by n.  Blocks. */
+int prand_generate(prand_ctx* ctx, int gen, void* h_state, int dtype, void* d_out, uint64_t n,
+                   void* stream);
+
+/* Many independent streams: d_out[s * n_per_stream + i] = output i of
+   stream s, for s < count; each d_states[s] is advanced by n_per_stream. */
+int prand_generate_streams(prand_ctx* ctx, int gen, void* d_states, uint32_t count,
+                           uint64_t n_per_stream, int dtype, void* d_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRAND_H */

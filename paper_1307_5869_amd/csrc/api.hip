@@ -1,0 +1,440 @@
+// The C ABI declared in include/prand.h: argument checks, context set-up and
+// the choice of launch shapes.  Every generated number and every jump is
+// computed by the HIP kernels; host code here only validates, plans and
+// copies states for the entry points that take host states.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "prand_impl.h"
+
+using namespace prand;
+
+struct prand_ctx {
+  int device = 0;
+  DeviceTables T;
+  bool mt_ready = false;
+  std::mutex mu;          // guards mt_ready and the host-call scratch
+  void* scratch = nullptr;
+  int last_hip = 0;
+};
+
+namespace {
+
+constexpr size_t kScratch = 64 * 1024;
+
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int hipfail(prand_ctx* c, hipError_t e) {
+  if (c) c->last_hip = (int)e;
+  return PRAND_EHIP;
+}
+
+bool valid_gen(int g) { return g >= 0 && g < PRAND_NUM_GENERATORS; }
+bool valid_dtype(int d) { return d >= PRAND_U32 && d <= PRAND_F64; }
+
+size_t state_bytes(int g) {
+  switch (g) {
+    case PRAND_MT19937: return sizeof(MtState);
+    case PRAND_MRG32K3A: return sizeof(MrgState);
+    case PRAND_LFSR113: return sizeof(LfsrState);
+    default: return valid_gen(g) ? sizeof(GmState) : 0;
+  }
+}
+size_t elem_bytes(int dtype) { return dtype == PRAND_F64 ? 8 : 4; }
+
+// Block-splitting block lengths, log2 of ensemble steps, per initialising
+// function of the paper's Table 4: the smallest power of two no shorter than
+// the table's maximal sequence length.  -1: function not provided.
+constexpr int kBlockLog2[PRAND_NUM_GENERATORS][4] = {
+    /*            SEQ SHORT MEDIUM LONG */
+    /* MT19937  */ {432, -1, -1, -1},
+    /* MRG32K3A */ {127, -1, -1, -1},
+    /* LFSR113  */ {34, -1, -1, 80},
+    /* GM19     */ {23, -1, -1, -1},
+    /* GM29     */ {-1, 27, 33, 40},
+    /* GM31     */ {-1, 27, 33, 40},
+    /* GM55     */ {-1, 34, -1, 67},
+    /* GM61     */ {34, -1, -1, 85},
+    /* GQ58.1   */ {-1, 27, 33, 40},
+    /* GQ58.3   */ {-1, 27, 33, 40},
+    /* GQ58.4   */ {-1, 27, 33, 40},
+};
+// Table 4: (number of sequences, maximal length) per initialising function
+constexpr double kLimits[PRAND_NUM_GENERATORS][4][2] = {
+    /* MT19937  */ {{1e19, 1e130}, {0, 0}, {0, 0}, {0, 0}},
+    /* MRG32K3A */ {{1e19, 1e38}, {0, 0}, {0, 0}, {0, 0}},
+    /* LFSR113  */ {{3.8e18, 1e10}, {0, 0}, {0, 0}, {4e9, 1e24}},
+    /* GM19     */ {{1e3, 6e6}, {0, 0}, {0, 0}, {0, 0}},
+    /* GM29     */ {{0, 0}, {1e8, 8e7}, {1e6, 8e9}, {1e4, 8e11}},
+    /* GM31     */ {{0, 0}, {1e9, 8e7}, {1e7, 8e9}, {1e5, 8e11}},
+    /* GM55     */ {{0, 0}, {1e18, 1e10}, {0, 0}, {4e9, 1e20}},
+    /* GM61     */ {{1.8e19, 1e10}, {0, 0}, {0, 0}, {4e9, 3e25}},
+    /* GQ58.1   */ {{0, 0}, {1e8, 8e7}, {1e6, 8e9}, {1e4, 8e11}},
+    /* GQ58.3   */ {{0, 0}, {2e8, 8e7}, {2e6, 8e9}, {2e4, 8e11}},
+    /* GQ58.4   */ {{0, 0}, {3e8, 8e7}, {3e6, 8e9}, {3e4, 8e11}},
+};
+
+int block_log2(int gen, int variant) {
+  if (!valid_gen(gen) || variant < PRAND_SEQ_DEFAULT || variant > PRAND_SEQ_LONG) return PRAND_EINVAL;
+  if (variant == PRAND_SEQ_DEFAULT) {
+    const int e = kBlockLog2[gen][0];
+    return e >= 0 ? e : kBlockLog2[gen][1];
+  }
+  const int e = kBlockLog2[gen][variant - 1];
+  return e >= 0 ? e : PRAND_EUNSUPPORTED;
+}
+
+int resolve_variant(int gen, int variant) {
+  if (variant != PRAND_SEQ_DEFAULT) return variant;
+  return kBlockLog2[gen][0] >= 0 ? PRAND_SEQ : PRAND_SEQ_SHORT;
+}
+
+template <class T>
+hipError_t upload(T** dst, const T* src, size_t n) {
+  hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+hipError_t ensure_mt(prand_ctx* c) {
+  // caller holds c->mu
+  if (c->mt_ready) return hipSuccess;
+  std::vector<uint32_t> mt((size_t)kLadder * 624);
+  if (!build_mt_ladder(mt.data())) return hipErrorUnknown;
+  hipError_t e = upload(&c->T.mt, mt.data(), mt.size());
+  if (e == hipSuccess) c->mt_ready = true;
+  return e;
+}
+
+int ensure_mt_locked(prand_ctx* c, int gen) {
+  if (gen != PRAND_MT19937) return PRAND_OK;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipError_t e = ensure_mt(c);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+hipError_t launch_jump(prand_ctx* c, int gen, void* states, uint32_t count, const JumpSpec& js, const void* base,
+                       hipStream_t st) {
+  switch (gen) {
+    case PRAND_MT19937: return launch_mt_jump(c->T, (MtState*)states, count, js, (const MtState*)base, st);
+    case PRAND_MRG32K3A: return launch_mrg_jump(c->T, (MrgState*)states, count, js, (const MrgState*)base, st);
+    case PRAND_LFSR113: return launch_lfsr_jump(c->T, (LfsrState*)states, count, js, (const LfsrState*)base, st);
+    default: return launch_gm_jump(c->T, gen, (GmState*)states, count, js, (const GmState*)base, st);
+  }
+}
+
+// many-stream generation; sin/sout may alias (sections of a stream never
+// straddle a wavefront)
+hipError_t launch_streams(prand_ctx* c, int gen, const void* sin, void* sout, uint32_t count, uint64_t n,
+                          int dtype, void* out, hipStream_t st) {
+  if (gen == PRAND_MRG32K3A || gen == PRAND_LFSR113) {
+    // enough lanes to fill the chip: up to 64 sections per stream, each at
+    // least 64 outputs long, section starts 16-byte aligned
+    int nsec_log2 = 0;
+    while (nsec_log2 < 6 && ((uint64_t)count << nsec_log2) < (1ull << 19) && (n >> (nsec_log2 + 1)) >= 64)
+      nsec_log2++;
+    uint64_t seclen = (n + (1ull << nsec_log2) - 1) >> nsec_log2;
+    seclen = (seclen + 3) & ~3ull;
+    if (seclen == 0) seclen = 4;
+    if (gen == PRAND_MRG32K3A)
+      return launch_mrg_generate(c->T, (const MrgState*)sin, (MrgState*)sout, count, n, nsec_log2, seclen, dtype,
+                                 out, st);
+    return launch_lfsr_generate(c->T, (const LfsrState*)sin, (LfsrState*)sout, count, n, nsec_log2, seclen, dtype,
+                                out, st);
+  }
+  if (gen == PRAND_MT19937) {
+    if (sin != sout) {
+      hipError_t e = hipMemcpyAsync(sout, sin, (size_t)count * sizeof(MtState), hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return e;
+    }
+    return launch_mt_generate((MtState*)sout, count, n, dtype, out, st);
+  }
+  return launch_gm_generate(c->T, gen, (const GmState*)sin, (GmState*)sout, count, n, dtype, out, st);
+}
+
+__global__ void iota_times_kernel(uint64_t* d, uint32_t count, uint64_t step) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) d[i] = (uint64_t)i * step;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* prand_strerror(int code) {
+  switch (code) {
+    case PRAND_OK: return "success";
+    case PRAND_EINVAL: return "invalid argument";
+    case PRAND_EUNSUPPORTED: return "variant not provided for this generator";
+    case PRAND_ERANGE: return "size out of range";
+    case PRAND_EHIP: return "HIP runtime error";
+    case PRAND_ENOMEM: return "out of memory";
+    case PRAND_ENODEV: return "no usable gfx950 device";
+    default: return "unknown error";
+  }
+}
+
+int prand_last_hip_error(const prand_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+size_t prand_state_bytes(int gen) { return state_bytes(gen); }
+
+int prand_block_log2(int gen, int variant) { return block_log2(gen, variant); }
+
+int prand_independence_limit(int gen, int variant, double* max_streams, double* max_length) {
+  const int e = block_log2(gen, variant);
+  if (e < 0) return e;
+  if (!max_streams || !max_length) return PRAND_EINVAL;
+  const int v = resolve_variant(gen, variant) - 1;
+  *max_streams = kLimits[gen][v][0];
+  *max_length = kLimits[gen][v][1];
+  return PRAND_OK;
+}
+
+int prand_ctx_create(prand_ctx** out, int hip_device) {
+  if (!out) return PRAND_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return PRAND_ENODEV;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return PRAND_ENODEV;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PRAND_ENODEV;
+  DeviceGuard g(hip_device);
+  if (g.err != hipSuccess) return PRAND_ENODEV;
+  prand_ctx* c = new (std::nothrow) prand_ctx;
+  if (!c) return PRAND_ENOMEM;
+  c->device = hip_device;
+  HostTables* H = new (std::nothrow) HostTables;
+  if (!H) { delete c; return PRAND_ENOMEM; }
+  build_mrg_ladder(H->mrg);
+  build_lfsr_ladder(H->lfsr);
+  build_gm_ladders(H->gm);
+  hipError_t e = upload(&c->T.mrg, H->mrg, sizeof(H->mrg) / sizeof(H->mrg[0]));
+  if (e == hipSuccess) e = upload(&c->T.lfsr, H->lfsr, sizeof(H->lfsr) / sizeof(H->lfsr[0]));
+  if (e == hipSuccess) e = upload(&c->T.gm, H->gm, sizeof(H->gm) / sizeof(H->gm[0]));
+  delete H;
+  if (e == hipSuccess) e = hipMalloc(&c->T.defaults, kDefaultStride * PRAND_NUM_GENERATORS);
+  if (e == hipSuccess) e = hipMalloc(&c->scratch, kScratch);
+  if (e == hipSuccess) {
+    // default states: the documented default seed of each generator
+    uint64_t seeds[PRAND_NUM_GENERATORS];
+    for (int gidx = 0; gidx < PRAND_NUM_GENERATORS; gidx++)
+      seeds[gidx] = gidx == PRAND_MT19937 ? 5489 : (gidx <= PRAND_LFSR113 ? 12345 : 0);
+    e = hipMemcpy(c->scratch, seeds, sizeof seeds, hipMemcpyHostToDevice);
+    for (int gidx = 0; gidx < PRAND_NUM_GENERATORS && e == hipSuccess; gidx++)
+      e = launch_seed(gidx, (const uint64_t*)c->scratch + gidx, 1, (char*)c->T.defaults + kDefaultStride * gidx,
+                      nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
+  if (e != hipSuccess) {
+    prand_ctx_destroy(c);
+    return PRAND_EHIP;
+  }
+  *out = c;
+  return PRAND_OK;
+}
+
+int prand_ctx_destroy(prand_ctx* c) {
+  if (!c) return PRAND_OK;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(c->T.mrg);
+  (void)hipFree(c->T.lfsr);
+  (void)hipFree(c->T.gm);
+  (void)hipFree(c->T.mt);
+  (void)hipFree(c->T.defaults);
+  (void)hipFree(c->scratch);
+  delete c;
+  return PRAND_OK;
+}
+
+int prand_seed_dev(prand_ctx* c, int gen, const uint64_t* d_seeds, uint32_t count, void* d_states, void* stream) {
+  if (!c || !valid_gen(gen)) return PRAND_EINVAL;
+  if (count == 0) return PRAND_OK;
+  if (!d_seeds || !d_states) return PRAND_EINVAL;
+  DeviceGuard g(c->device);
+  hipError_t e = launch_seed(gen, d_seeds, count, d_states, (hipStream_t)stream);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+int prand_seed(prand_ctx* c, int gen, uint64_t seed, void* h_state) {
+  if (!c || !valid_gen(gen) || !h_state) return PRAND_EINVAL;
+  DeviceGuard g(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  uint64_t* d_seed = (uint64_t*)c->scratch;
+  void* d_state = (char*)c->scratch + 256;
+  hipError_t e = hipMemcpy(d_seed, &seed, 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_seed(gen, d_seed, 1, d_state, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(h_state, d_state, state_bytes(gen), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+int prand_init_default(prand_ctx* c, int gen, void* h_state) {
+  if (!c || !valid_gen(gen) || !h_state) return PRAND_EINVAL;
+  DeviceGuard g(c->device);
+  hipError_t e = hipMemcpy(h_state, (char*)c->T.defaults + kDefaultStride * gen, state_bytes(gen),
+                           hipMemcpyDeviceToHost);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+int prand_skipahead_dev(prand_ctx* c, int gen, void* d_states, uint32_t count, const uint64_t* d_dist, int nlimbs,
+                        int per_stream, void* stream) {
+  if (!c || !valid_gen(gen) || nlimbs < 0 || nlimbs > kMaxLimbs) return PRAND_EINVAL;
+  if (count == 0 || nlimbs == 0) return PRAND_OK;
+  if (!d_states || !d_dist) return PRAND_EINVAL;
+  DeviceGuard g(c->device);
+  int rc = ensure_mt_locked(c, gen);
+  if (rc) return rc;
+  JumpSpec js;
+  js.dist = d_dist;
+  js.nlimbs = nlimbs;
+  js.per_stream = per_stream ? 1 : 0;
+  hipError_t e = launch_jump(c, gen, d_states, count, js, nullptr, (hipStream_t)stream);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+int prand_skipahead(prand_ctx* c, int gen, void* h_state, const uint64_t* h_dist, int nlimbs) {
+  if (!c || !valid_gen(gen) || !h_state || nlimbs < 0 || nlimbs > kMaxLimbs || (nlimbs > 0 && !h_dist))
+    return PRAND_EINVAL;
+  if (nlimbs == 0) return PRAND_OK;
+  DeviceGuard g(c->device);
+  int rc = ensure_mt_locked(c, gen);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  uint64_t* d_dist = (uint64_t*)c->scratch;
+  void* d_state = (char*)c->scratch + 256;
+  hipError_t e = hipMemcpy(d_dist, h_dist, 8 * (size_t)nlimbs, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_state, h_state, state_bytes(gen), hipMemcpyHostToDevice);
+  JumpSpec js;
+  js.dist = d_dist;
+  js.nlimbs = nlimbs;
+  if (e == hipSuccess) e = launch_jump(c, gen, d_state, 1, js, nullptr, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(h_state, d_state, state_bytes(gen), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+int prand_init_streams_dev(prand_ctx* c, int gen, int variant, const void* d_base_state, const uint64_t* d_ids,
+                           uint32_t count, void* d_states, void* stream) {
+  if (!c || !valid_gen(gen)) return PRAND_EINVAL;
+  const int be = block_log2(gen, variant);
+  if (be < 0) return be;
+  if (count == 0) return PRAND_OK;
+  if (!d_ids || !d_states) return PRAND_EINVAL;
+  DeviceGuard g(c->device);
+  int rc = ensure_mt_locked(c, gen);
+  if (rc) return rc;
+  JumpSpec js;
+  js.ids = d_ids;
+  js.block_e = be;
+  const void* base = d_base_state ? d_base_state : (const char*)c->T.defaults + kDefaultStride * gen;
+  hipError_t e = launch_jump(c, gen, d_states, count, js, base, (hipStream_t)stream);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+int prand_init_stream(prand_ctx* c, int gen, int variant, uint64_t id, void* h_state) {
+  if (!c || !valid_gen(gen) || !h_state) return PRAND_EINVAL;
+  const int be = block_log2(gen, variant);
+  if (be < 0) return be;
+  DeviceGuard g(c->device);
+  int rc = ensure_mt_locked(c, gen);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  uint64_t* d_id = (uint64_t*)c->scratch;
+  void* d_state = (char*)c->scratch + 256;
+  hipError_t e = hipMemcpy(d_id, &id, 8, hipMemcpyHostToDevice);
+  JumpSpec js;
+  js.ids = d_id;
+  js.block_e = be;
+  if (e == hipSuccess)
+    e = launch_jump(c, gen, d_state, 1, js, (const char*)c->T.defaults + kDefaultStride * gen, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(h_state, d_state, state_bytes(gen), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+int prand_generate_streams(prand_ctx* c, int gen, void* d_states, uint32_t count, uint64_t n, int dtype,
+                           void* d_out, void* stream) {
+  if (!c || !valid_gen(gen) || !valid_dtype(dtype)) return PRAND_EINVAL;
+  if (count == 0 || n == 0) return PRAND_OK;
+  if (!d_states || !d_out) return PRAND_EINVAL;
+  if (n > (1ull << 40) || (unsigned __int128)count * n * elem_bytes(dtype) > ((unsigned __int128)1 << 50))
+    return PRAND_ERANGE;
+  DeviceGuard g(c->device);
+  hipError_t e = launch_streams(c, gen, d_states, d_states, count, n, dtype, d_out, (hipStream_t)stream);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+int prand_generate(prand_ctx* c, int gen, void* h_state, int dtype, void* d_out, uint64_t n, void* stream) {
+  if (!c || !valid_gen(gen) || !valid_dtype(dtype) || !h_state) return PRAND_EINVAL;
+  if (n == 0) return PRAND_OK;
+  if (!d_out) return PRAND_EINVAL;
+  if (n > (1ull << 40)) return PRAND_ERANGE;
+  DeviceGuard g(c->device);
+  int rc = ensure_mt_locked(c, gen);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  // sections of 2^k outputs: each starts from the state jumped j * 2^k ahead
+  // (one ladder application per set bit of j), fills its slice, and the last
+  // one leaves the advanced state
+  uint64_t min_sec, max_secs;
+  switch (gen) {
+    case PRAND_MT19937: min_sec = 1ull << 18; max_secs = 4096; break;
+    case PRAND_MRG32K3A:
+    case PRAND_LFSR113: min_sec = 256; max_secs = 1u << 19; break;
+    default: min_sec = 4096; max_secs = 1u << 16; break;
+  }
+  int k = 0;
+  while ((1ull << k) < min_sec) k++;
+  while (((n + (1ull << k) - 1) >> k) > max_secs) k++;
+  if ((1ull << k) >= n) k = 63;  // one section
+  const uint64_t seclen = k == 63 ? n : (1ull << k);
+  const uint64_t nsec = (n + seclen - 1) / seclen;
+  const uint64_t lastlen = n - (nsec - 1) * seclen;
+  const size_t sb = state_bytes(gen);
+  void* d_states = nullptr;
+  uint64_t* d_dist = nullptr;
+  hipError_t e = hipMalloc(&d_states, nsec * sb);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_dist, nsec * 8);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    void* d_base = c->scratch;
+    if (e == hipSuccess) e = hipMemcpyAsync(d_base, h_state, sb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(iota_times_kernel, dim3((uint32_t)((nsec + 255) / 256)), dim3(256), 0, st, d_dist,
+                         (uint32_t)nsec, seclen);
+      e = hipGetLastError();
+    }
+    JumpSpec js;
+    js.dist = d_dist;
+    js.nlimbs = 1;
+    js.per_stream = 1;
+    if (e == hipSuccess) e = launch_jump(c, gen, d_states, (uint32_t)nsec, js, d_base, st);
+    if (e == hipSuccess && nsec > 1)
+      e = launch_streams(c, gen, d_states, d_states, (uint32_t)(nsec - 1), seclen, dtype, d_out, st);
+    void* last = (char*)d_states + (nsec - 1) * sb;
+    if (e == hipSuccess)
+      e = launch_streams(c, gen, last, last, 1, lastlen, dtype, (char*)d_out + (nsec - 1) * seclen * elem_bytes(dtype),
+                         st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_state, last, sb, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  (void)hipFree(d_states);
+  (void)hipFree(d_dist);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+}  // extern "C"

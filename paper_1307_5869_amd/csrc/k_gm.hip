@@ -1,0 +1,561 @@
+// GM19, GM29, GM31, GM55, GM61, GQ58.1, GQ58.3, GQ58.4 on gfx950: ensembles of
+// s torus maps x_i^(n) = k x_i^(n-1) - q x_i^(n-2) mod g (paper, equation
+// rec1; k, q, g, v of Table 2).  Each element contributes a v-bit digit
+// floor(2^v x / g) per step; digits are packed element 0 first, most
+// significant bit first, into 32-bit words (GQ58.3: 36 bits per step, 9 words
+// per 8 steps).
+//
+// One lane per element: v = 1 ensembles (s = 32) take half a wavefront per
+// stream and pack a word with one ballot; v = 4 ensembles (s = 8) take 8
+// lanes and OR their nibbles with three xor-shuffles; GQ58.3 (s = 12) takes 16
+// lanes.  Each lane keeps the word of one step of every 32 (8), so a flush
+// writes consecutive words from consecutive lanes.
+//
+// Arithmetic is exact: special-form reductions (2^19-1, 2^29-3, 2^61-1,
+// 2^51-129) in integers, or FP64 where all values stay below 2^53 (GM31,
+// GQ58).  For g = p 2^t (GM55: t = 4, GQ58: t = 29) the even k and q kill the
+// 2-adic part within n0 steps; from then on x = 2^t y with y following the
+// same recurrence mod p and the digit equal to floor(2^v y / p), so the
+// kernel runs exact mod-g steps only until every element of the wavefront has
+// collapsed and then switches to the mod-p recurrence.
+#include "prand_impl.h"
+
+namespace prand {
+namespace {
+
+typedef unsigned __int128 u128;
+
+// ------------------------------------------------------------ per generator
+template <int G>
+struct Eng;
+
+// GM19: g = 2^19 - 1, k = 15, q = 28
+template <>
+struct Eng<0> {
+  static constexpr bool kComposite = false;
+  using F = uint32_t;
+  static constexpr uint32_t g = 524287u;
+  __device__ static F to_fast(uint64_t x) { return (F)x; }
+  __device__ static uint64_t from_fast(F y) { return y; }
+  __device__ static F step(F xc, F xp) {
+    uint32_t t = 15u * xc + 28u * (g - xp);   // < 43 * 2^19
+    t = (t & g) + (t >> 19);
+    return min(t, t - g);
+  }
+  __device__ static uint32_t digit(F x) { return x >= (g + 1) / 2; }
+};
+
+// GM29: g = 2^29 - 3, k = 4, q = 2
+template <>
+struct Eng<1> {
+  static constexpr bool kComposite = false;
+  using F = uint32_t;
+  static constexpr uint32_t g = 536870909u;
+  __device__ static F to_fast(uint64_t x) { return (F)x; }
+  __device__ static uint64_t from_fast(F y) { return y; }
+  __device__ static F step(F xc, F xp) {
+    uint32_t t = (xc << 2) + ((g - xp) << 1);   // < 6 * 2^29
+    t = (t & 0x1FFFFFFFu) + 3u * (t >> 29);
+    return min(t, t - g);
+  }
+  __device__ static uint32_t digit(F x) { return x >= (g + 1) / 2; }
+};
+
+// GM31: g = 2^31 - 1, k = 11, q = 14; exact in FP64 (|k x - q x'| < 2^36)
+template <>
+struct Eng<2> {
+  static constexpr bool kComposite = false;
+  using F = double;
+  __device__ static F to_fast(uint64_t x) { return (double)x; }
+  __device__ static uint64_t from_fast(F y) { return (uint64_t)y; }
+  __device__ static F step(F xc, F xp) {
+    const double g = 2147483647.0, inv = 1.0 / 2147483647.0;
+    const double t = fma(11.0, xc, -14.0 * xp);
+    const double k = floor(t * inv);
+    double r = fma(-k, g, t);
+    r = (r < 0.0) ? r + g : r;
+    return (r >= g) ? r - g : r;
+  }
+  __device__ static uint32_t digit(F x) { return x >= 1073741824.0; }
+};
+
+// GM61: g = 2^61 - 1, k = 24, q = 74
+template <>
+struct Eng<4> {
+  static constexpr bool kComposite = false;
+  using F = uint64_t;
+  static constexpr uint64_t g = 2305843009213693951ull;
+  __device__ static F to_fast(uint64_t x) { return x; }
+  __device__ static uint64_t from_fast(F y) { return y; }
+  __device__ static F step(F xc, F xp) {
+    const u128 t = (u128)24u * xc + (u128)74u * (g - xp);   // < 2^68
+    const uint64_t lo = (uint64_t)t, hi = (uint64_t)(t >> 64);
+    uint64_t r = (lo & g) + ((lo >> 61) | (hi << 3));
+    return r >= g ? r - g : r;
+  }
+  __device__ static uint32_t digit(F x) { return x >= (1ull << 60); }
+};
+
+// GM55: g = 2^4 p, p = 2^51 - 129, k = 256, q = 176, v = 4
+template <>
+struct Eng<3> {
+  static constexpr bool kComposite = true;
+  static constexpr int t = 4, v = 4;
+  static constexpr uint64_t p = 2251799813685119ull;
+  static constexpr uint64_t g = p << 4;
+  using F = uint64_t;
+  __device__ static uint64_t modp_fold(uint64_t h) {   // h < 2^60
+    h = (h & ((1ull << 51) - 1)) + 129ull * (h >> 51);
+    return h >= p ? h - p : h;
+  }
+  __device__ static bool collapsed(uint64_t x) { return (x & 15u) == 0; }
+  __device__ static uint64_t slow_step(uint64_t xc, uint64_t xp) {
+    const uint64_t s = (xc << 8) + 176ull * (g - xp);   // < 2^64
+    return (modp_fold(s >> 4) << 4) | (s & 15u);
+  }
+  __device__ static uint32_t slow_digit(uint64_t x) {  // floor(16 x / 16 p) = floor(x / p)
+    const uint64_t d0 = x >> 51;
+    return (uint32_t)(d0 + ((d0 + 1) * p <= x));
+  }
+  __device__ static F to_fast(uint64_t x) { return x >> 4; }
+  __device__ static uint64_t from_fast(F y) { return y << 4; }
+  __device__ static F step(F yc, F yp) {
+    const uint64_t s = (yc << 8) + 176ull * (p - yp);   // < 2^60
+    return modp_fold(s);
+  }
+  __device__ static uint32_t digit(F y) {
+    const uint64_t num = y << 4, d0 = num >> 51;
+    return (uint32_t)(d0 + ((d0 + 1) * p <= num));
+  }
+};
+
+// GQ58.x: g = 2^29 p, p = 2^29 - 3, k = 8, q = 48, v = 1, 3, 4
+template <int V>
+struct EngGQ {
+  static constexpr bool kComposite = true;
+  static constexpr int t = 29, v = V;
+  static constexpr uint64_t p = 536870909ull;
+  static constexpr uint64_t g = p << 29;
+  using F = double;
+  __device__ static bool collapsed(uint64_t x) { return (x & 0x1FFFFFFFull) == 0; }
+  __device__ static uint64_t slow_step(uint64_t xc, uint64_t xp) {
+    const uint64_t s = (xc << 3) + 48ull * (g - xp);   // < 2^64
+    uint64_t h = s >> 29;                               // < 2^35
+    h = (h & 0x1FFFFFFFull) + 3ull * (h >> 29);
+    h = h >= p ? h - p : h;
+    return (h << 29) | (s & 0x1FFFFFFFull);
+  }
+  __device__ static uint32_t slow_digit(uint64_t x) {  // floor(((2^v x) >> 29) / p)
+    const uint64_t num = (x << V) >> 29, d0 = num >> 29;
+    return (uint32_t)(d0 + ((d0 + 1) * p <= num));
+  }
+  __device__ static F to_fast(uint64_t x) { return (double)(x >> 29); }
+  __device__ static uint64_t from_fast(F y) { return ((uint64_t)y) << 29; }
+  __device__ static F step(F yc, F yp) {
+    const double pd = 536870909.0, inv = 1.0 / 536870909.0;
+    const double s = fma(8.0, yc, -48.0 * yp);
+    const double k = floor(s * inv);
+    double r = fma(-k, pd, s);
+    r = (r < 0.0) ? r + pd : r;
+    return (r >= pd) ? r - pd : r;
+  }
+  __device__ static uint32_t digit(F y) {
+    const double pd = 536870909.0;
+    if (V == 1) return y >= 268435455.0;   // 2y >= p
+    const double num = y * (double)(1 << V);
+    double d = floor(num * (1.0 / 536870909.0));
+    d = (d * pd > num) ? d - 1.0 : d;
+    d = ((d + 1.0) * pd <= num) ? d + 1.0 : d;
+    return (uint32_t)d;
+  }
+};
+template <> struct Eng<5> : EngGQ<1> {};
+template <> struct Eng<6> : EngGQ<3> {};
+template <> struct Eng<7> : EngGQ<4> {};
+
+// Per-element runner: slow exact-mod-g steps until the whole wavefront has
+// collapsed (composite moduli), then the fast recurrence.  The mode only
+// switches between steps and is wavefront-uniform.
+template <int G>
+struct Elem {
+  using E = Eng<G>;
+  typename E::F fc, fp;   // fast representation
+  uint64_t sc, sp;        // exact mod-g values (slow mode)
+  bool fast;
+  __device__ void load(uint64_t xc, uint64_t xp) {
+    if constexpr (E::kComposite) {
+      sc = xc; sp = xp; fast = false;
+    } else {
+      fc = E::to_fast(xc); fp = E::to_fast(xp); fast = true;
+    }
+  }
+  __device__ void maybe_switch() {
+    if constexpr (E::kComposite) {
+      if (!fast) {
+        const bool mine = E::collapsed(sc) && E::collapsed(sp);
+        if (__all(mine)) {
+          fc = E::to_fast(sc); fp = E::to_fast(sp); fast = true;
+        }
+      }
+    }
+  }
+  __device__ uint32_t step() {
+    if constexpr (E::kComposite) {
+      if (!fast) {
+        const uint64_t nx = E::slow_step(sc, sp);
+        sp = sc; sc = nx;
+        return E::slow_digit(nx);
+      }
+    }
+    const typename E::F nx = E::step(fc, fp);
+    fp = fc; fc = nx;
+    return E::digit(nx);
+  }
+  __device__ void get(uint64_t& xc, uint64_t& xp) const {
+    if (fast) { xc = E::from_fast(fc); xp = E::from_fast(fp); }
+    else { xc = sc; xp = sp; }
+  }
+};
+
+template <int DT>
+__device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
+  if (DT == PRAND_U32) ((uint32_t*)out)[i] = w;
+  else if (DT == PRAND_F32) ((float*)out)[i] = (float)(w >> 8) * 0x1p-24f;
+  else ((double*)out)[i] = (double)w * 0x1p-32;
+}
+
+// ------------------------------------------------ v = 1, s = 32: ballots
+template <int G, int DT>
+__global__ void __launch_bounds__(256) gm_gen32_kernel(const GmState* sin, GmState* sout,
+                                                       uint32_t count, uint64_t n, void* __restrict__ out) {
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t s = gid >> 5;
+  const int li = threadIdx.x & 31;        // bit position of this element's digit
+  const int e = 31 - li;                  // element index
+  const bool live = s < count;
+  Elem<G> el;
+  el.load(live ? sin[s].xc[e] : 0, live ? sin[s].xp[e] : 0);
+  const int hsh = threadIdx.x & 32;
+  uint32_t keep = 0;
+  for (uint64_t t0 = 0; t0 < n; t0 += 32) {
+    const int m = (n - t0) < 32 ? (int)(n - t0) : 32;
+    for (int u = 0; u < m; u++) {
+      el.maybe_switch();
+      const uint32_t d = el.step();
+      const uint64_t mask = __ballot(d);
+      const uint32_t w = (uint32_t)(mask >> hsh);
+      keep = (u == li) ? w : keep;
+    }
+    if (live && li < m) put<DT>(out, s * n + t0 + li, keep);
+  }
+  if (live) {
+    uint64_t xc, xp;
+    el.get(xc, xp);
+    sout[s].xc[e] = xc;
+    sout[s].xp[e] = xp;
+    if (li == 0) { sout[s].off = 0; sout[s].pad = 0; }
+  }
+}
+
+// ------------------------------------------------ v = 4, s = 8: nibbles
+template <int G, int DT>
+__global__ void __launch_bounds__(256) gm_gen8_kernel(const GmState* sin, GmState* sout,
+                                                      uint32_t count, uint64_t n, void* __restrict__ out) {
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t s = gid >> 3;
+  const int e = threadIdx.x & 7;
+  const bool live = s < count;
+  Elem<G> el;
+  el.load(live ? sin[s].xc[e] : 0, live ? sin[s].xp[e] : 0);
+  const int shift = 28 - 4 * e;
+  uint32_t keep = 0;
+  for (uint64_t t0 = 0; t0 < n; t0 += 8) {
+    const int m = (n - t0) < 8 ? (int)(n - t0) : 8;
+    for (int u = 0; u < m; u++) {
+      el.maybe_switch();
+      uint32_t w = el.step() << shift;
+      w |= __shfl_xor(w, 1);
+      w |= __shfl_xor(w, 2);
+      w |= __shfl_xor(w, 4);
+      keep = (u == e) ? w : keep;
+    }
+    if (live && e < m) put<DT>(out, s * n + t0 + e, keep);
+  }
+  if (live) {
+    uint64_t xc, xp;
+    el.get(xc, xp);
+    sout[s].xc[e] = xc;
+    sout[s].xp[e] = xp;
+    if (e == 0) { sout[s].off = 0; sout[s].pad = 0; }
+  }
+}
+
+// --------------------------------- GQ58.3: v = 3, s = 12, 16 lanes / stream
+// 8 steps of 36 bits = 9 words.  The state sits at a block boundary with
+// `off` words of the block consumed; a call emits block words from off on and
+// keeps the state at the start of the last, partially used block.
+template <int DT>
+__global__ void __launch_bounds__(256) gq58x3_gen_kernel(const GmState* sin, GmState* sout,
+                                                         uint32_t count, uint64_t n, void* __restrict__ out) {
+  constexpr int G = 6;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t s = gid >> 4;
+  const int e = threadIdx.x & 15;
+  const int gbase = threadIdx.x & 48;     // first lane of this stream's group (within the wavefront)
+  const bool live = s < count;
+  const bool elem = e < 12;
+  Elem<G> el;
+  el.load((live && elem) ? sin[s].xc[e] : 0, (live && elem) ? sin[s].xp[e] : 0);
+  const uint32_t off0 = live ? sin[s].off : 0;
+  const uint64_t total = off0 + n;
+  const uint64_t full = total / 9;
+  const uint32_t rem = (uint32_t)(total % 9);
+  const uint64_t blocks = full + (rem ? 1 : 0);
+  // wavefront-uniform block count: lanes of dead streams follow along
+  uint64_t nb = blocks;
+  Elem<G> saved = el;
+  const int shift = elem ? 33 - 3 * e : 0;
+  for (uint64_t b = 0; b < nb; b++) {
+    el.maybe_switch();
+    saved = el;
+    uint64_t keep = 0;
+    for (int u = 0; u < 8; u++) {
+      const uint32_t d = el.step();
+      uint64_t c = elem ? ((uint64_t)d << shift) : 0;
+      uint32_t lo = (uint32_t)c, hi = (uint32_t)(c >> 32);
+      lo |= __shfl_xor(lo, 1); hi |= __shfl_xor(hi, 1);
+      lo |= __shfl_xor(lo, 2); hi |= __shfl_xor(hi, 2);
+      lo |= __shfl_xor(lo, 4); hi |= __shfl_xor(hi, 4);
+      lo |= __shfl_xor(lo, 8); hi |= __shfl_xor(hi, 8);
+      c = ((uint64_t)hi << 32) | lo;
+      keep = (u == e) ? c : keep;
+    }
+    // word w (lane w < 9): bits [32w, 32w+32) of the 288-bit block
+    const int w = e < 9 ? e : 8;
+    const int ci = (32 * w) / 36, o = 32 * w - 36 * ci;
+    const uint32_t alo = __shfl((uint32_t)keep, gbase + ci);
+    const uint32_t ahi = __shfl((uint32_t)(keep >> 32), gbase + ci);
+    const int cj = ci + 1 < 8 ? ci + 1 : 7;
+    const uint32_t blo = __shfl((uint32_t)keep, gbase + cj);
+    const uint32_t bhi = __shfl((uint32_t)(keep >> 32), gbase + cj);
+    const uint64_t A = ((uint64_t)ahi << 32) | alo;
+    const uint64_t B = (ci + 1 < 8) ? (((uint64_t)bhi << 32) | blo) : 0;
+    const int k = 40 - o;   // the word is (A:B >> k) & (2^32 - 1) of the 72-bit A:B
+    const uint32_t word = (k > 36) ? (uint32_t)(A >> (k - 36)) : (uint32_t)((A << (36 - k)) | (B >> k));
+    const int64_t q = (int64_t)(b * 9 + w) - (int64_t)off0;
+    if (live && e < 9 && q >= 0 && (uint64_t)q < n) put<DT>(out, s * n + (uint64_t)q, word);
+  }
+  if (live && elem) {
+    uint64_t xc, xp;
+    if (rem && nb > 0) saved.get(xc, xp); else el.get(xc, xp);
+    sout[s].xc[e] = xc;
+    sout[s].xp[e] = xp;
+  }
+  if (live && e == 0) { sout[s].off = rem; sout[s].pad = 0; }
+}
+
+// -------------------------------------------------------------- jumping
+template <int G>
+struct Mod;
+template <int G>
+__device__ __forceinline__ uint64_t fold_special(u128 x, int e, uint64_t c, uint64_t p) {
+  const uint64_t mask = (1ull << e) - 1;
+  for (int i = 0; i < 3; i++) x = (x & mask) + (u128)c * (uint64_t)(x >> e);
+  uint64_t r = (uint64_t)x;
+  r = r >= p ? r - p : r;
+  r = r >= p ? r - p : r;
+  return r;
+}
+// prime part p = 2^e - c of each generator's modulus
+__device__ __forceinline__ void prime_form(int G, int& e, uint64_t& c) {
+  switch (G) {
+    case 0: e = 19; c = 1; break;
+    case 1: e = 29; c = 3; break;
+    case 2: e = 31; c = 1; break;
+    case 3: e = 51; c = 129; break;
+    case 4: e = 61; c = 1; break;
+    default: e = 29; c = 3; break;
+  }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) gm_jump_kernel(GmState* __restrict__ states, uint32_t count,
+                                                      const uint64_t* __restrict__ dist, int nlimbs, int per_stream,
+                                                      const uint64_t* __restrict__ ids, int block_e,
+                                                      const GmState* __restrict__ base,
+                                                      const uint64_t* __restrict__ ladder) {
+  using E = Eng<G>;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t s = gid >> 5;
+  if (s >= count) return;
+  const int e = threadIdx.x & 31;
+  const GmState* src = base ? base : states + s;
+  uint64_t xc = src->xc[e], xp = src->xp[e];
+  const uint32_t off = src->off;
+  uint64_t N[kMaxLimbs + 1];
+  for (int l = 0; l <= kMaxLimbs; l++) N[l] = 0;
+  if (ids) {
+    const uint64_t id = ids[s];
+    const int q = block_e >> 6, r = block_e & 63;   // block in ensemble steps
+    N[q] = id << r;
+    if (r) N[q + 1] = id >> (64 - r);
+  } else {
+    const uint64_t* d = dist + (per_stream ? (size_t)s * nlimbs : 0);
+    for (int l = 0; l < nlimbs; l++) N[l] = d[l];
+  }
+  uint32_t new_off = 0;
+  if (G == 6 && !ids) {
+    // GQ58.3: distance in words -> (off + N) = 9 B + rem; steps = 8 B
+    uint64_t carry = off;
+    for (int l = 0; l <= kMaxLimbs && carry; l++) {
+      const uint64_t old = N[l];
+      N[l] = old + carry;
+      carry = N[l] < old ? 1 : 0;
+    }
+    uint64_t r = 0;   // divide by 9 in 32-bit pieces
+    for (int l = kMaxLimbs; l >= 0; l--) {
+      const uint64_t hi = (r << 32) | (N[l] >> 32);
+      const uint64_t qh = hi / 9;
+      r = hi % 9;
+      const uint64_t lo = (r << 32) | (N[l] & 0xFFFFFFFFull);
+      const uint64_t ql = lo / 9;
+      r = lo % 9;
+      N[l] = (qh << 32) | ql;
+    }
+    new_off = (uint32_t)r;
+    uint64_t c3 = 0;   // times 8
+    for (int l = 0; l <= kMaxLimbs; l++) {
+      const uint64_t v = N[l];
+      N[l] = (v << 3) | c3;
+      c3 = v >> 61;
+    }
+  } else if (G == 6) {
+    new_off = off;   // whole blocks: the offset inside the block is kept
+  }
+  const bool active = e < kGmParams[G].s;
+  if (active) {
+    int pe;
+    uint64_t pc;
+    prime_form(G, pe, pc);
+    const uint64_t p = kGmParams[G].p;
+    const uint64_t* L = ladder + (size_t)G * kLadder * 4;
+    if constexpr (E::kComposite) {
+      // small distances: exact steps; otherwise collapse, then jump mod p
+      bool small = true;
+      for (int l = 1; l <= kMaxLimbs; l++) small = small && N[l] == 0;
+      uint64_t steps_done = 0;
+      const uint64_t n0 = (uint64_t)kGmParams[G].n0;
+      if (small && N[0] < n0) {
+        for (uint64_t i = 0; i < N[0]; i++) { const uint64_t nx = E::slow_step(xc, xp); xp = xc; xc = nx; }
+      } else {
+        if (!(E::collapsed(xc) && E::collapsed(xp))) {
+          for (uint64_t i = 0; i < n0; i++) { const uint64_t nx = E::slow_step(xc, xp); xp = xc; xc = nx; }
+          steps_done = n0;
+        }
+        uint64_t borrow = steps_done;
+        for (int l = 0; l <= kMaxLimbs && borrow; l++) {
+          const uint64_t old = N[l];
+          N[l] = old - borrow;
+          borrow = old < borrow ? 1 : 0;
+        }
+        uint64_t yc = xc >> E::t, yp = xp >> E::t;
+        for (int l = 0; l < kMaxLimbs; l++) {
+          uint64_t wd = N[l];
+          while (wd) {
+            const int b = __builtin_ctzll(wd) + 64 * l;
+            wd &= wd - 1;
+            const uint64_t* M = L + (size_t)b * 4;
+            const uint64_t nc = fold_special<G>((u128)M[0] * yc + (u128)M[1] * yp, pe, pc, p);
+            const uint64_t np = fold_special<G>((u128)M[2] * yc + (u128)M[3] * yp, pe, pc, p);
+            yc = nc; yp = np;
+          }
+        }
+        xc = yc << E::t;
+        xp = yp << E::t;
+      }
+    } else {
+      for (int l = 0; l < kMaxLimbs; l++) {
+        uint64_t wd = N[l];
+        while (wd) {
+          const int b = __builtin_ctzll(wd) + 64 * l;
+          wd &= wd - 1;
+          const uint64_t* M = L + (size_t)b * 4;
+          const uint64_t nc = fold_special<G>((u128)M[0] * xc + (u128)M[1] * xp, pe, pc, p);
+          const uint64_t np = fold_special<G>((u128)M[2] * xc + (u128)M[3] * xp, pe, pc, p);
+          xc = nc; xp = np;
+        }
+      }
+    }
+  }
+  GmState* dst = states + s;
+  dst->xc[e] = xc;
+  dst->xp[e] = xp;
+  if (e == 0) { dst->off = new_off; dst->pad = 0; }
+}
+
+template <int G, int DT>
+hipError_t launch_gen(const GmState* sin, GmState* sout, uint32_t count, uint64_t n, void* out, hipStream_t st) {
+  const int lps = (G == 3 || G == 7) ? 8 : (G == 6 ? 16 : 32);
+  const uint64_t lanes = (uint64_t)count * lps;
+  const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
+  if constexpr (G == 6)
+    hipLaunchKernelGGL(gq58x3_gen_kernel<DT>, dim3(blocks), dim3(256), 0, st, sin, sout, count, n, out);
+  else if constexpr (G == 3 || G == 7)
+    hipLaunchKernelGGL((gm_gen8_kernel<G, DT>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n, out);
+  else
+    hipLaunchKernelGGL((gm_gen32_kernel<G, DT>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n, out);
+  return hipGetLastError();
+}
+
+template <int G>
+hipError_t launch_gen_g(int dtype, const GmState* sin, GmState* sout, uint32_t count, uint64_t n, void* out,
+                        hipStream_t st) {
+  switch (dtype) {
+    case PRAND_U32: return launch_gen<G, PRAND_U32>(sin, sout, count, n, out, st);
+    case PRAND_F32: return launch_gen<G, PRAND_F32>(sin, sout, count, n, out, st);
+    default: return launch_gen<G, PRAND_F64>(sin, sout, count, n, out, st);
+  }
+}
+
+template <int G>
+hipError_t launch_jump_g(const DeviceTables& T, GmState* states, uint32_t count, const JumpSpec& js,
+                         const GmState* base, hipStream_t st) {
+  const uint64_t lanes = (uint64_t)count * 32;
+  const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
+  hipLaunchKernelGGL(gm_jump_kernel<G>, dim3(blocks), dim3(256), 0, st, states, count, js.dist, js.nlimbs,
+                     js.per_stream, js.ids, js.block_e, base, T.gm);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gm_generate(const DeviceTables& T, int gen, const GmState* sin, GmState* sout, uint32_t count,
+                              uint64_t n, int dtype, void* out, hipStream_t st) {
+  (void)T;
+  switch (gen - PRAND_GM19) {
+    case 0: return launch_gen_g<0>(dtype, sin, sout, count, n, out, st);
+    case 1: return launch_gen_g<1>(dtype, sin, sout, count, n, out, st);
+    case 2: return launch_gen_g<2>(dtype, sin, sout, count, n, out, st);
+    case 3: return launch_gen_g<3>(dtype, sin, sout, count, n, out, st);
+    case 4: return launch_gen_g<4>(dtype, sin, sout, count, n, out, st);
+    case 5: return launch_gen_g<5>(dtype, sin, sout, count, n, out, st);
+    case 6: return launch_gen_g<6>(dtype, sin, sout, count, n, out, st);
+    default: return launch_gen_g<7>(dtype, sin, sout, count, n, out, st);
+  }
+}
+
+hipError_t launch_gm_jump(const DeviceTables& T, int gen, GmState* states, uint32_t count, const JumpSpec& js,
+                          const GmState* base, hipStream_t st) {
+  switch (gen - PRAND_GM19) {
+    case 0: return launch_jump_g<0>(T, states, count, js, base, st);
+    case 1: return launch_jump_g<1>(T, states, count, js, base, st);
+    case 2: return launch_jump_g<2>(T, states, count, js, base, st);
+    case 3: return launch_jump_g<3>(T, states, count, js, base, st);
+    case 4: return launch_jump_g<4>(T, states, count, js, base, st);
+    case 5: return launch_jump_g<5>(T, states, count, js, base, st);
+    case 6: return launch_jump_g<6>(T, states, count, js, base, st);
+    default: return launch_jump_g<7>(T, states, count, js, base, st);
+  }
+}
+
+}  // namespace prand

@@ -1,0 +1,213 @@
+// MRG32K3A on gfx950: X_{n+1} = A X_n mod m1, Y_{n+1} = B Y_n mod m2 (paper,
+// section on jumping ahead for MRG32K3A), output z = (x - y) mod m1 in
+// [1, m1].  One lane owns one (stream, section) pair and keeps the six state
+// words in registers.  The recurrence runs in exact double arithmetic: every
+// product is an integer below 2^53, so fma + floor(p / m) with a +-1
+// correction gives the exact residue at full FP64 rate (gfx950 issues FP64
+// FMA at the FP32 rate, integer 32x32 multiplies at a quarter of it).
+// Jumps apply A^(2^b), B^(2^b) from the context ladder for each set bit b of
+// the distance (binary decomposition, O(log n)).
+#include "prand_impl.h"
+
+namespace prand {
+namespace {
+
+constexpr double kM1 = 4294967087.0;
+constexpr double kM2 = 4294944443.0;
+constexpr double kInvM1 = 1.0 / 4294967087.0;
+constexpr double kInvM2 = 1.0 / 4294944443.0;
+constexpr double kNorm = 1.0 / 4294967088.0;   // RN(1/(m1+1))
+
+struct Regs {
+  double x0, x1, x2, y0, y1, y2;   // x_n, x_{n-1}, x_{n-2}, ...
+};
+
+__device__ __forceinline__ double reduce_exact(double p, double m, double inv) {
+  double k = floor(p * inv);
+  double r = fma(-k, m, p);
+  r = (r < 0.0) ? r + m : r;
+  r = (r >= m) ? r - m : r;
+  return r;
+}
+
+__device__ __forceinline__ double step(Regs& r) {
+  double p1 = fma(1403580.0, r.x1, -810728.0 * r.x2);
+  double p2 = fma(527612.0, r.y0, -1370589.0 * r.y2);
+  double x = reduce_exact(p1, kM1, kInvM1);
+  double y = reduce_exact(p2, kM2, kInvM2);
+  r.x2 = r.x1; r.x1 = r.x0; r.x0 = x;
+  r.y2 = r.y1; r.y1 = r.y0; r.y0 = y;
+  double z = x - y;
+  return (z <= 0.0) ? z + kM1 : z;
+}
+
+// 2^32 = C (mod 2^32 - C): fold a 64-bit value to its residue
+template <uint32_t C>
+__device__ __forceinline__ uint32_t fold32(uint64_t v) {
+  v = (v >> 32) * C + (v & 0xFFFFFFFFull);
+  v = (v >> 32) * C + (v & 0xFFFFFFFFull);
+  v = (v >> 32) * C + (v & 0xFFFFFFFFull);
+  const uint64_t m = (1ull << 32) - C;
+  return (uint32_t)(v >= m ? v - m : v);
+}
+
+template <uint32_t C>
+__device__ __forceinline__ void mat3_apply(const uint32_t* M, uint32_t v[3]) {
+  const uint64_t m = (1ull << 32) - C;
+  uint32_t r[3];
+  for (int i = 0; i < 3; i++) {
+    uint64_t acc = 0;
+    for (int k = 0; k < 3; k++) acc += fold32<C>((uint64_t)M[3 * i + k] * v[k]);
+    acc = acc >= m ? acc - m : acc;
+    acc = acc >= m ? acc - m : acc;
+    r[i] = (uint32_t)acc;
+  }
+  v[0] = r[0]; v[1] = r[1]; v[2] = r[2];
+}
+
+__device__ __noinline__ void jump_state(const uint32_t* ladder, uint32_t x[3], uint32_t y[3],
+                                           const uint64_t* limbs, int nlimbs) {
+  for (int l = 0; l < nlimbs; l++) {
+    uint64_t w = limbs[l];
+    while (w) {
+      int b = __builtin_ctzll(w) + 64 * l;
+      w &= w - 1;
+      const uint32_t* M = ladder + (size_t)b * 18;
+      mat3_apply<209u>(M, x);
+      mat3_apply<22853u>(M + 9, y);
+    }
+  }
+}
+
+template <int DT>
+__device__ __forceinline__ void put(void* out, uint64_t i, double z) {
+  if (DT == PRAND_U32) {
+    ((uint32_t*)out)[i] = (uint32_t)z;
+  } else if (DT == PRAND_F32) {
+    ((float*)out)[i] = (float)(((uint32_t)z) >> 8) * 0x1p-24f;
+  } else {
+    ((double*)out)[i] = z * kNorm;
+  }
+}
+
+// Lane gid -> stream gid >> nsec_log2, section gid & (nsec - 1).  The
+// sections of one stream cover [j*seclen, min((j+1)*seclen, n)); the lane
+// whose section ends at n writes the advanced state to sout.
+template <int DT, bool VEC>
+__global__ void __launch_bounds__(256) mrg_generate_kernel(const MrgState* sin,
+                                                           MrgState* sout, uint32_t count,
+                                                           uint64_t n, int nsec_log2, uint64_t seclen,
+                                                           void* __restrict__ out,
+                                                           const uint32_t* __restrict__ ladder) {
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t s = gid >> nsec_log2;
+  if (s >= count) return;
+  const uint64_t j = gid & ((1ull << nsec_log2) - 1);
+  const uint64_t start = j * seclen;
+  const uint64_t jlast = (n == 0) ? 0 : (n - 1) / seclen;
+  if (j > jlast) return;
+  const uint64_t len = (j == jlast) ? n - start : seclen;
+
+  MrgState st = sin[s];
+  if (start) jump_state(ladder, st.x, st.y, &start, 1);
+  Regs r = {(double)st.x[0], (double)st.x[1], (double)st.x[2],
+            (double)st.y[0], (double)st.y[1], (double)st.y[2]};
+  const uint64_t base = s * n + start;
+  uint64_t i = 0;
+  if (VEC) {
+    if (DT == PRAND_F64) {
+      double2* o = (double2*)((double*)out + base);
+      for (; i + 2 <= len; i += 2) {
+        double a = step(r), b = step(r);
+        o[i >> 1] = make_double2(a * kNorm, b * kNorm);
+      }
+    } else if (DT == PRAND_F32) {
+      float4* o = (float4*)((float*)out + base);
+      for (; i + 4 <= len; i += 4) {
+        uint32_t a = (uint32_t)step(r), b = (uint32_t)step(r), c = (uint32_t)step(r), d = (uint32_t)step(r);
+        o[i >> 2] = make_float4((float)(a >> 8) * 0x1p-24f, (float)(b >> 8) * 0x1p-24f,
+                                (float)(c >> 8) * 0x1p-24f, (float)(d >> 8) * 0x1p-24f);
+      }
+    } else {
+      uint4* o = (uint4*)((uint32_t*)out + base);
+      for (; i + 4 <= len; i += 4) {
+        uint32_t a = (uint32_t)step(r), b = (uint32_t)step(r), c = (uint32_t)step(r), d = (uint32_t)step(r);
+        o[i >> 2] = make_uint4(a, b, c, d);
+      }
+    }
+  }
+  for (; i < len; i++) put<DT>(out, base + i, step(r));
+  if (j == jlast) {
+    MrgState o;
+    o.x[0] = (uint32_t)r.x0; o.x[1] = (uint32_t)r.x1; o.x[2] = (uint32_t)r.x2;
+    o.y[0] = (uint32_t)r.y0; o.y[1] = (uint32_t)r.y1; o.y[2] = (uint32_t)r.y2;
+    sout[s] = o;
+  }
+}
+
+// One lane per stream: states[i] = (base ? *base : states[i]) jumped by the
+// stream's distance (explicit limbs, or id * 2^block_e).
+__global__ void __launch_bounds__(256) mrg_jump_kernel(MrgState* __restrict__ states, uint32_t count,
+                                                       const uint64_t* __restrict__ dist, int nlimbs,
+                                                       int per_stream, const uint64_t* __restrict__ ids,
+                                                       int block_e, const MrgState* __restrict__ base,
+                                                       const uint32_t* __restrict__ ladder) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  MrgState st = base ? *base : states[i];
+  uint64_t limbs[kMaxLimbs];
+  int nl;
+  if (ids) {
+    // id * 2^block_e as limbs
+    for (int l = 0; l < kMaxLimbs; l++) limbs[l] = 0;
+    const uint64_t id = ids[i];
+    const int q = block_e >> 6, r = block_e & 63;
+    limbs[q] = id << r;
+    if (r && q + 1 < kMaxLimbs) limbs[q + 1] = id >> (64 - r);
+    nl = kMaxLimbs;
+  } else {
+    const uint64_t* d = dist + (per_stream ? (size_t)i * nlimbs : 0);
+    for (int l = 0; l < nlimbs; l++) limbs[l] = d[l];
+    nl = nlimbs;
+  }
+  jump_state(ladder, st.x, st.y, limbs, nl);
+  states[i] = st;
+}
+
+template <int DT>
+hipError_t launch_gen_dt(const DeviceTables& T, const MrgState* sin, MrgState* sout, uint32_t count, uint64_t n,
+                         int nsec_log2, uint64_t seclen, void* out, hipStream_t st, bool vec) {
+  const uint64_t lanes = (uint64_t)count << nsec_log2;
+  const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
+  if (vec)
+    hipLaunchKernelGGL((mrg_generate_kernel<DT, true>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
+                       nsec_log2, seclen, out, T.mrg);
+  else
+    hipLaunchKernelGGL((mrg_generate_kernel<DT, false>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
+                       nsec_log2, seclen, out, T.mrg);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_mrg_generate(const DeviceTables& T, const MrgState* sin, MrgState* sout, uint32_t count,
+                               uint64_t n, int nsec_log2, uint64_t seclen, int dtype, void* out,
+                               hipStream_t st) {
+  const uint64_t es = dtype == PRAND_F64 ? 8 : 4;
+  const bool vec = ((uintptr_t)out % 16 == 0) && ((n * es) % 16 == 0) && ((seclen * es) % 16 == 0);
+  switch (dtype) {
+    case PRAND_U32: return launch_gen_dt<PRAND_U32>(T, sin, sout, count, n, nsec_log2, seclen, out, st, vec);
+    case PRAND_F32: return launch_gen_dt<PRAND_F32>(T, sin, sout, count, n, nsec_log2, seclen, out, st, vec);
+    default: return launch_gen_dt<PRAND_F64>(T, sin, sout, count, n, nsec_log2, seclen, out, st, vec);
+  }
+}
+
+hipError_t launch_mrg_jump(const DeviceTables& T, MrgState* states, uint32_t count, const JumpSpec& js,
+                           const MrgState* base, hipStream_t st) {
+  const uint32_t blocks = (count + 255) / 256;
+  hipLaunchKernelGGL(mrg_jump_kernel, dim3(blocks), dim3(256), 0, st, states, count, js.dist, js.nlimbs,
+                     js.per_stream, js.ids, js.block_e, base, T.mrg);
+  return hipGetLastError();
+}
+
+}  // namespace prand

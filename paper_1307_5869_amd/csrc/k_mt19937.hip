@@ -1,0 +1,225 @@
+// MT19937 on gfx950.
+//
+// Generation: one wavefront per stream, the 624-word state in LDS.  A twist
+// renews the block in three dependency phases (words 0..226 read old words
+// 397..623; 227..453 read words renewed in phase one; 454..623 read phase two
+// and word 0), each phase parallel across the 64 lanes; every renewed word is
+// tempered and stored straight from registers, so consecutive lanes write
+// consecutive addresses.
+//
+// Jump-ahead (paper, section on MT19937 jump-ahead, equation g_v):
+// A^v Y = g_v(A) Y = sum_i a_i A^(i-1) Y with g_v = x^v mod phi.  A^(i-1) Y is
+// the window of 624 consecutive raw words starting i-1 words later, so word t
+// of the result is the XOR of seq[i + t] over the set coefficients i, seq
+// being the raw-word sequence continued from the state.  A distance is applied
+// as one polynomial x^(2^b) mod phi (from the context ladder) per set bit b.
+// One wavefront does one stream: the sequence is produced 227 words at a time
+// into an LDS ring, and lane l accumulates outputs t = 10l .. 10l+9 while a
+// register window of 10 sequence words slides over the coefficients, so each
+// coefficient costs one LDS read per lane and, when set, 10 XORs.
+#include "prand_impl.h"
+
+namespace prand {
+namespace {
+
+constexpr uint32_t kUpper = 0x80000000u;
+constexpr uint32_t kLower = 0x7FFFFFFFu;
+constexpr uint32_t kMatA = 0x9908B0DFu;
+
+__device__ __forceinline__ uint32_t temper(uint32_t y) {
+  y ^= y >> 11;
+  y ^= (y << 7) & 0x9D2C5680u;
+  y ^= (y << 15) & 0xEFC60000u;
+  return y ^ (y >> 18);
+}
+// x_{j+624} from x_j (upper bit), x_{j+1} (lower bits), x_{j+397}
+__device__ __forceinline__ uint32_t recur(uint32_t xj, uint32_t xj1, uint32_t xjm) {
+  const uint32_t y = (xj & kUpper) | (xj1 & kLower);
+  return xjm ^ (y >> 1) ^ ((xj1 & 1u) ? kMatA : 0u);
+}
+
+template <int DT>
+__device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
+  if (DT == PRAND_U32) ((uint32_t*)out)[i] = w;
+  else if (DT == PRAND_F32) ((float*)out)[i] = (float)(w >> 8) * 0x1p-24f;
+  else ((double*)out)[i] = (double)w * 0x1p-32;
+}
+
+template <int DT>
+__global__ void __launch_bounds__(64) mt_generate_kernel(MtState* __restrict__ states, uint32_t count, uint64_t n,
+                                                         void* __restrict__ out) {
+  __shared__ uint32_t mt[624];
+  const uint32_t s = blockIdx.x;
+  if (s >= count) return;
+  const int lane = threadIdx.x;
+  MtState* S = states + s;
+  for (int i = lane; i < 624; i += 64) mt[i] = S->mt[i];
+  uint32_t idx = S->idx < 624u ? S->idx : 624u;   // an index past the block means "block used up"
+  __syncthreads();
+  const uint64_t base = (uint64_t)s * n;
+  // rest of the current block
+  const uint64_t first = (uint64_t)(624 - idx) < n ? (uint64_t)(624 - idx) : n;
+  for (uint32_t i = lane; i < first; i += 64) put<DT>(out, base + i, temper(mt[idx + i]));
+  uint64_t pos = first;
+  idx += (uint32_t)first;
+  while (pos < n) {
+    const uint64_t left = n - pos;
+    const int want = left < 624 ? (int)left : 624;
+    const uint64_t ob = base + pos;
+    for (int j = lane; j < 227; j += 64) {
+      const uint32_t v = recur(mt[j], mt[j + 1], mt[j + 397]);
+      mt[j] = v;
+      if (j < want) put<DT>(out, ob + j, temper(v));
+    }
+    __syncthreads();
+    for (int j = 227 + lane; j < 454; j += 64) {
+      const uint32_t v = recur(mt[j], mt[j + 1], mt[j - 227]);
+      mt[j] = v;
+      if (j < want) put<DT>(out, ob + j, temper(v));
+    }
+    __syncthreads();
+    for (int j = 454 + lane; j < 624; j += 64) {
+      const uint32_t v = recur(mt[j], mt[j == 623 ? 0 : j + 1], mt[j - 227]);
+      mt[j] = v;
+      if (j < want) put<DT>(out, ob + j, temper(v));
+    }
+    __syncthreads();
+    pos += want;
+    idx = want;
+  }
+  for (int i = lane; i < 624; i += 64) S->mt[i] = mt[i];
+  if (lane == 0) S->idx = idx;
+}
+
+// ------------------------------------------------------------------ jump
+constexpr int kRing = 2048;                 // LDS ring of sequence words
+constexpr int kMask = kRing - 1;
+constexpr int kDeg = 19937;
+constexpr int kSeqLen = kDeg - 1 + 624;     // words seq[0..20559] take part
+constexpr int kPer = 10;                    // outputs per lane: 64 * 10 >= 624
+
+// Extend the ring to hold seq[0..upto) (227 words per phase).
+__device__ __forceinline__ void extend(uint32_t* ring, int& gen_hi, int upto, int lane) {
+  if (upto > kSeqLen) upto = kSeqLen;
+  while (gen_hi < upto) {
+    const int g0 = gen_hi;
+    const int g1 = (g0 + 227 < kSeqLen) ? g0 + 227 : kSeqLen;
+    for (int j = g0 + lane; j < g1; j += 64)
+      ring[j & kMask] = recur(ring[(j - 624) & kMask], ring[(j - 623) & kMask], ring[(j - 227) & kMask]);
+    __syncthreads();
+    gen_hi = g1;
+  }
+}
+
+// ring[0..623] holds a window (next output = tempered successor); replace it
+// by g(A) applied to it, g = poly (624 words of coefficient bits).
+__device__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, int lane) {
+  int gen_hi = 624;
+  extend(ring, gen_hi, 660, lane);
+  uint32_t acc[kPer], c[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; r++) {
+    acc[r] = 0;
+    c[r] = ring[(kPer * lane + r) & kMask];
+  }
+  for (int i0 = 0; i0 < kDeg; i0 += kPer) {
+    extend(ring, gen_hi, i0 + 660, lane);
+    const int w = i0 >> 5, sh = i0 & 31;
+    const uint64_t pair = (uint64_t)poly[w] | ((w + 1 < 624) ? ((uint64_t)poly[w + 1] << 32) : 0ull);
+    uint32_t bits = (uint32_t)(pair >> sh) & ((1u << kPer) - 1);
+    if (i0 + kPer > kDeg) bits &= (1u << (kDeg - i0)) - 1;
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+      if ((bits >> u) & 1u) {
+#pragma unroll
+        for (int r = 0; r < kPer; r++) acc[r] ^= c[(r + u) % kPer];
+      }
+      // element leaving the window is seq[i + 10 lane]; the one entering for
+      // the next coefficient is seq[i + 10 lane + 10]
+      c[u] = ring[(i0 + u + kPer * lane + kPer) & kMask];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kPer; r++) {
+    const int t = kPer * lane + r;
+    if (t < 624) ring[t] = (t == 0) ? (acc[r] & kUpper) : acc[r];
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ states, uint32_t count,
+                                                     const uint64_t* __restrict__ dist, int nlimbs, int per_stream,
+                                                     const uint64_t* __restrict__ ids, int block_e,
+                                                     const MtState* __restrict__ base,
+                                                     const uint32_t* __restrict__ ladder) {
+  __shared__ uint32_t ring[kRing];
+  const uint32_t s = blockIdx.x;
+  if (s >= count) return;
+  const int lane = threadIdx.x;
+  const MtState* src = base ? base : states + s;
+  uint64_t N[kMaxLimbs];
+  for (int l = 0; l < kMaxLimbs; l++) N[l] = 0;
+  if (ids) {
+    const uint64_t id = ids[s];
+    const int q = block_e >> 6, r = block_e & 63;
+    N[q] = id << r;
+    if (r && q + 1 < kMaxLimbs) N[q + 1] = id >> (64 - r);
+  } else {
+    const uint64_t* d = dist + (per_stream ? (size_t)s * nlimbs : 0);
+    for (int l = 0; l < nlimbs; l++) N[l] = d[l];
+  }
+  for (int i = lane; i < 624; i += 64) ring[i] = src->mt[i];
+  uint32_t idx = src->idx < 624u ? src->idx : 624u;
+  __syncthreads();
+  // consume the rest of the current block first
+  const uint64_t rest = 624 - idx;
+  bool small = true;
+  for (int l = 1; l < kMaxLimbs; l++) small = small && (N[l] == 0);
+  small = small && (N[0] <= rest);
+  if (small) {
+    idx += (uint32_t)N[0];
+  } else {
+    uint64_t borrow = rest;
+    for (int l = 0; l < kMaxLimbs && borrow; l++) {
+      const uint64_t old = N[l];
+      N[l] = old - borrow;
+      borrow = old < borrow ? 1 : 0;
+    }
+    idx = 624;
+    for (int l = 0; l < kMaxLimbs; l++) {
+      uint64_t wd = N[l];
+      while (wd) {
+        const int b = __builtin_ctzll(wd) + 64 * l;
+        wd &= wd - 1;
+        apply_poly(ring, ladder + (size_t)b * 624, lane);
+      }
+    }
+  }
+  MtState* dst = states + s;
+  for (int i = lane; i < 624; i += 64) dst->mt[i] = ring[i];
+  if (lane == 0) {
+    dst->idx = idx;
+    dst->pad[0] = dst->pad[1] = dst->pad[2] = 0;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_mt_generate(MtState* states, uint32_t count, uint64_t n, int dtype, void* out, hipStream_t st) {
+  switch (dtype) {
+    case PRAND_U32: hipLaunchKernelGGL(mt_generate_kernel<PRAND_U32>, dim3(count), dim3(64), 0, st, states, count, n, out); break;
+    case PRAND_F32: hipLaunchKernelGGL(mt_generate_kernel<PRAND_F32>, dim3(count), dim3(64), 0, st, states, count, n, out); break;
+    default: hipLaunchKernelGGL(mt_generate_kernel<PRAND_F64>, dim3(count), dim3(64), 0, st, states, count, n, out); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mt_jump(const DeviceTables& T, MtState* states, uint32_t count, const JumpSpec& js,
+                          const MtState* base, hipStream_t st) {
+  hipLaunchKernelGGL(mt_jump_kernel, dim3(count), dim3(64), 0, st, states, count, js.dist, js.nlimbs, js.per_stream,
+                     js.ids, js.block_e, base, T.mt);
+  return hipGetLastError();
+}
+
+}  // namespace prand

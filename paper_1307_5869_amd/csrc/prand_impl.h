@@ -1,0 +1,127 @@
+// Internal declarations shared by the host side and the HIP kernels of the
+// PRAND library for gfx950.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "prand.h"
+
+namespace prand {
+
+constexpr int kMaxLimbs = 8;        // distances up to 2^512
+constexpr int kLadder = 512;        // jump tables hold M^(2^b) for b < 512
+
+// ---- state blobs (layout documented in prand.h) ----
+struct MtState {
+  uint32_t mt[624];
+  uint32_t idx;
+  uint32_t pad[3];
+};
+struct MrgState {
+  uint32_t x[3];   // x_n, x_{n-1}, x_{n-2}
+  uint32_t y[3];   // y_n, y_{n-1}, y_{n-2}
+};
+struct LfsrState {
+  uint32_t z[4];
+};
+struct GmState {
+  uint64_t xp[32];  // x^(n-1)
+  uint64_t xc[32];  // x^(n)
+  uint32_t off;     // GQ58.3: words of the current 8-step block already consumed
+  uint32_t pad;
+};
+static_assert(sizeof(MtState) == 2512, "MT19937 state layout");
+static_assert(sizeof(MrgState) == 24, "MRG32K3A state layout");
+static_assert(sizeof(LfsrState) == 16, "LFSR113 state layout");
+static_assert(sizeof(GmState) == 520, "GM state layout");
+
+// ---- MRG32K3A constants: matrices A, B of the paper's MRG32K3A section ----
+constexpr uint32_t kMrgM1 = 4294967087u;   // 2^32 - 209
+constexpr uint32_t kMrgM2 = 4294944443u;   // 2^32 - 22853
+constexpr uint32_t kMrgA12 = 1403580u;     // a
+constexpr uint32_t kMrgA13n = 810728u;     // -b
+constexpr uint32_t kMrgA21 = 527612u;      // c
+constexpr uint32_t kMrgA23n = 1370589u;    // -d
+
+// ---- GM/GQ parameters of the paper's Table 2 ----
+// g = p * 2^t; s = ensemble size, v = digit bits per element.
+struct GmParams {
+  uint64_t k, q, p;
+  int t, v, s;
+  int n0;  // M^N = 0 mod 2^t for N >= n0 (composite moduli only)
+};
+constexpr GmParams kGmParams[8] = {
+    /* GM19   */ {15, 28, 524287ull, 0, 1, 32, 0},
+    /* GM29   */ {4, 2, 536870909ull, 0, 1, 32, 0},
+    /* GM31   */ {11, 14, 2147483647ull, 0, 1, 32, 0},
+    /* GM55   */ {256, 176, 2251799813685119ull, 4, 4, 8, 2},
+    /* GM61   */ {24, 74, 2305843009213693951ull, 0, 1, 32, 0},
+    /* GQ58.1 */ {8, 48, 536870909ull, 29, 1, 32, 16},
+    /* GQ58.3 */ {8, 48, 536870909ull, 29, 3, 12, 16},
+    /* GQ58.4 */ {8, 48, 536870909ull, 29, 4, 8, 16},
+};
+inline bool is_gm(int gen) { return gen >= PRAND_GM19 && gen <= PRAND_GQ58X4; }
+
+// ---- device-resident jump tables (built once per context) ----
+struct DeviceTables {
+  uint32_t* mrg = nullptr;    // [kLadder][18]: A^(2^b) mod m1 (row major), B^(2^b) mod m2
+  uint32_t* lfsr = nullptr;   // [kLadder][4][32]: columns of T_c^(2^b)
+  uint64_t* gm = nullptr;     // [8][kLadder][4]: (a b; c d) = M^(2^b) mod p
+  uint32_t* mt = nullptr;     // [kLadder][624]: bits of x^(2^b) mod phi (19937 used)
+  void* defaults = nullptr;   // default state of each generator, 11 x 2560 bytes
+};
+constexpr size_t kDefaultStride = 2560;
+
+// ---- launchers (one per kernel family); all enqueue on `st` ----
+// Distances: `dist` holds nlimbs limbs per stream when per_stream, else one
+// shared distance.  `ids` + `block_e`: distance id * 2^block_e (GQ58.3: in
+// ensemble steps).  Exactly one of (dist, ids) is used.
+struct JumpSpec {
+  const uint64_t* dist = nullptr;
+  int nlimbs = 0;
+  int per_stream = 0;
+  const uint64_t* ids = nullptr;
+  int block_e = 0;
+};
+
+hipError_t launch_mrg_generate(const DeviceTables& T, const MrgState* sin, MrgState* sout, uint32_t count,
+                               uint64_t n, int nsec_log2, uint64_t seclen, int dtype, void* out,
+                               hipStream_t st);
+hipError_t launch_mrg_jump(const DeviceTables& T, MrgState* states, uint32_t count, const JumpSpec& js,
+                           const MrgState* base, hipStream_t st);
+
+hipError_t launch_lfsr_generate(const DeviceTables& T, const LfsrState* sin, LfsrState* sout, uint32_t count,
+                                uint64_t n, int nsec_log2, uint64_t seclen, int dtype, void* out,
+                                hipStream_t st);
+hipError_t launch_lfsr_jump(const DeviceTables& T, LfsrState* states, uint32_t count, const JumpSpec& js,
+                            const LfsrState* base, hipStream_t st);
+
+hipError_t launch_mt_generate(MtState* states, uint32_t count, uint64_t n, int dtype, void* out,
+                              hipStream_t st);
+hipError_t launch_mt_jump(const DeviceTables& T, MtState* states, uint32_t count, const JumpSpec& js,
+                          const MtState* base, hipStream_t st);
+
+hipError_t launch_gm_generate(const DeviceTables& T, int gen, const GmState* sin, GmState* sout,
+                              uint32_t count, uint64_t n, int dtype, void* out, hipStream_t st);
+hipError_t launch_gm_jump(const DeviceTables& T, int gen, GmState* states, uint32_t count, const JumpSpec& js,
+                          const GmState* base, hipStream_t st);
+
+hipError_t launch_seed(int gen, const uint64_t* seeds, uint32_t count, void* states, hipStream_t st);
+
+// ---- host-side table construction (context set-up) ----
+struct HostTables {
+  uint32_t mrg[kLadder * 18];
+  uint32_t lfsr[kLadder * 4 * 32];
+  uint64_t gm[8 * kLadder * 4];
+};
+void build_mrg_ladder(uint32_t* out);
+void build_lfsr_ladder(uint32_t* out);
+void build_gm_ladders(uint64_t* out);
+// phi of MT19937 by Berlekamp-Massey, then x^(2^b) mod phi for b < kLadder;
+// out: kLadder * 624 words.  Returns false if the polynomial has the wrong degree.
+bool build_mt_ladder(uint32_t* out);
+
+}  // namespace prand

@@ -1,0 +1,199 @@
+"""Thin ctypes binding of libprand.so (argument marshalling only).
+
+Every ``prand_*`` function of ``include/prand.h`` is exposed under the same
+name; :class:`Context` wraps them for torch tensors and numpy host states.
+The library must have been built (``python -m paper_1307_5869_amd.build``);
+there is no fallback of any kind.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libprand.so")
+
+MT19937, MRG32K3A, LFSR113, GM19, GM29, GM31, GM55, GM61, GQ58X1, GQ58X3, GQ58X4 = range(11)
+NUM_GENERATORS = 11
+NAMES = ["MT19937", "MRG32K3A", "LFSR113", "GM19", "GM29", "GM31", "GM55", "GM61", "GQ58.1", "GQ58.3", "GQ58.4"]
+U32, F32, F64 = 0, 1, 2
+SEQ_DEFAULT, SEQ, SEQ_SHORT, SEQ_MEDIUM, SEQ_LONG = range(5)
+OK, EINVAL, EUNSUPPORTED, ERANGE, EHIP, ENOMEM, ENODEV = 0, -1, -2, -3, -4, -5, -6
+MAX_LIMBS = 8
+
+_u64, _u32, _i32, _vp, _sz = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+_SIGNATURES = {
+    "prand_strerror": (ctypes.c_char_p, [_i32]),
+    "prand_last_hip_error": (_i32, [_vp]),
+    "prand_ctx_create": (_i32, [ctypes.POINTER(_vp), _i32]),
+    "prand_ctx_destroy": (_i32, [_vp]),
+    "prand_state_bytes": (_sz, [_i32]),
+    "prand_block_log2": (_i32, [_i32, _i32]),
+    "prand_independence_limit": (_i32, [_i32, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "prand_init_default": (_i32, [_vp, _i32, _vp]),
+    "prand_seed": (_i32, [_vp, _i32, _u64, _vp]),
+    "prand_seed_dev": (_i32, [_vp, _i32, _vp, _u32, _vp, _vp]),
+    "prand_skipahead": (_i32, [_vp, _i32, _vp, _vp, _i32]),
+    "prand_skipahead_dev": (_i32, [_vp, _i32, _vp, _u32, _vp, _i32, _i32, _vp]),
+    "prand_init_stream": (_i32, [_vp, _i32, _i32, _u64, _vp]),
+    "prand_init_streams_dev": (_i32, [_vp, _i32, _i32, _vp, _vp, _u32, _vp, _vp]),
+    "prand_generate": (_i32, [_vp, _i32, _vp, _i32, _vp, _u64, _vp]),
+    "prand_generate_streams": (_i32, [_vp, _i32, _vp, _u32, _u64, _i32, _vp, _vp]),
+}
+
+_lib = None
+
+
+class PrandError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+def load():
+    """Load libprand.so (raises ImportError when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with python -m paper_1307_5869_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype, fn.argtypes = res, args
+        _lib = lib
+    return _lib
+
+
+def strerror(code):
+    return load().prand_strerror(code).decode()
+
+
+def _chk(rc, what):
+    if rc != OK:
+        raise PrandError(rc, what)
+
+
+def limbs(n):
+    """A non-negative int as 8 little-endian uint64 limbs."""
+    if n < 0 or n >= 1 << (64 * MAX_LIMBS):
+        raise ValueError("distance out of range")
+    return np.array([(n >> (64 * i)) & 0xFFFFFFFFFFFFFFFF for i in range(MAX_LIMBS)], dtype=np.uint64)
+
+
+def _ptr(x):
+    """Device or host address of a torch tensor / numpy array / int / None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("host buffers must be contiguous")
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("device buffers must be contiguous")
+        return x.data_ptr()
+    raise TypeError(f"cannot pass {type(x)}")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def state_bytes(gen):
+    return load().prand_state_bytes(gen)
+
+
+def block_log2(gen, variant=SEQ_DEFAULT):
+    return load().prand_block_log2(gen, variant)
+
+
+def independence_limit(gen, variant=SEQ_DEFAULT):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _chk(load().prand_independence_limit(gen, variant, ctypes.byref(a), ctypes.byref(b)), "independence_limit")
+    return a.value, b.value
+
+
+class Context:
+    """A libprand context on one HIP device."""
+
+    def __init__(self, device=0):
+        lib = load()
+        h = _vp()
+        _chk(lib.prand_ctx_create(ctypes.byref(h), device), "prand_ctx_create")
+        self.handle = h
+        self.device = device
+        self.lib = lib
+
+    def close(self):
+        if self.handle:
+            self.lib.prand_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, name, *args):
+        rc = getattr(self.lib, name)(self.handle, *args)
+        if rc == EHIP:
+            raise PrandError(rc, f"{name} (hipError {self.lib.prand_last_hip_error(self.handle)})")
+        _chk(rc, name)
+
+    # ---- host states (numpy uint8 blobs) ----
+    def new_state(self, gen):
+        return np.zeros(state_bytes(gen), dtype=np.uint8)
+
+    def init_default(self, gen):
+        st = self.new_state(gen)
+        self._call("prand_init_default", gen, _ptr(st))
+        return st
+
+    def seed(self, gen, seed):
+        st = self.new_state(gen)
+        self._call("prand_seed", gen, seed, _ptr(st))
+        return st
+
+    def skipahead(self, gen, state, distance):
+        d = limbs(distance)
+        self._call("prand_skipahead", gen, _ptr(state), _ptr(d), MAX_LIMBS)
+        return state
+
+    def init_stream(self, gen, variant, sid):
+        st = self.new_state(gen)
+        self._call("prand_init_stream", gen, variant, sid, _ptr(st))
+        return st
+
+    def generate(self, gen, state, dtype, d_out, n, stream=None):
+        self._call("prand_generate", gen, _ptr(state), dtype, _ptr(d_out), n, _stream(stream))
+        return d_out
+
+    # ---- device states (torch uint8 tensors of count * state_bytes) ----
+    def seed_dev(self, gen, d_seeds, count, d_states, stream=None):
+        self._call("prand_seed_dev", gen, _ptr(d_seeds), count, _ptr(d_states), _stream(stream))
+
+    def skipahead_dev(self, gen, d_states, count, d_dist, nlimbs, per_stream, stream=None):
+        self._call("prand_skipahead_dev", gen, _ptr(d_states), count, _ptr(d_dist), nlimbs, int(per_stream),
+                   _stream(stream))
+
+    def init_streams_dev(self, gen, variant, d_base, d_ids, count, d_states, stream=None):
+        self._call("prand_init_streams_dev", gen, variant, _ptr(d_base), _ptr(d_ids), count, _ptr(d_states),
+                   _stream(stream))
+
+    def generate_streams(self, gen, d_states, count, n, dtype, d_out, stream=None):
+        self._call("prand_generate_streams", gen, _ptr(d_states), count, n, dtype, _ptr(d_out), _stream(stream))
+
+
+def __getattr__(name):
+    # prand_* under their C names, for callers that want the raw ABI
+    if name.startswith("prand_") and name in _SIGNATURES:
+        return getattr(load(), name)
+    raise AttributeError(name)
