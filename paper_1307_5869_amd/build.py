@@ -32,9 +32,18 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+# pure host sources (no HIP): the host compiler, with the x86 carry-less multiply
+HOST_CXX = os.environ.get("CXX", "g++")
+HOST_SOURCES = {"mt_poly.cpp"}
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-mpclmul", "-msse4.1", "-pthread", "-I", CSRC]
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
+    if os.path.basename(src) in HOST_SOURCES:
+        cmd = [HOST_CXX] + HOST_FLAGS + ["-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -47,7 +56,7 @@ def build(verbose=False):
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -10,6 +10,7 @@
 #include <new>
 #include <vector>
 
+#include "mt_poly.h"
 #include "prand_impl.h"
 
 using namespace prand;
@@ -115,9 +116,10 @@ hipError_t upload(T** dst, const T* src, size_t n) {
 hipError_t ensure_mt(prand_ctx* c) {
   // caller holds c->mu
   if (c->mt_ready) return hipSuccess;
-  std::vector<uint32_t> mt((size_t)kLadder * 624);
-  if (!build_mt_ladder(mt.data())) return hipErrorUnknown;
+  std::vector<uint32_t> mt((size_t)kLadder * 624), dig((size_t)8 * 256 * 624);
+  if (!mt_build_polys(mt.data(), kLadder, dig.data(), kMtDigitE)) return hipErrorUnknown;
   hipError_t e = upload(&c->T.mt, mt.data(), mt.size());
+  if (e == hipSuccess) e = upload(&c->T.mtdig, dig.data(), dig.size());
   if (e == hipSuccess) c->mt_ready = true;
   return e;
 }
@@ -168,9 +170,12 @@ hipError_t launch_streams(prand_ctx* c, int gen, const void* sin, void* sout, ui
   return launch_gm_generate(c->T, gen, (const GmState*)sin, (GmState*)sout, count, n, dtype, out, st);
 }
 
-__global__ void iota_times_kernel(uint64_t* d, uint32_t count, uint64_t step) {
+// distances of the section starts: j * seclen for the bulk sections j < nb,
+// then T for the final section
+__global__ void section_dist_kernel(uint64_t* d, uint32_t nb, uint64_t seclen, uint64_t T) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) d[i] = (uint64_t)i * step;
+  if (i < nb) d[i] = (uint64_t)i * seclen;
+  else if (i == nb) d[i] = T;
 }
 
 }  // namespace
@@ -257,6 +262,7 @@ int prand_ctx_destroy(prand_ctx* c) {
   (void)hipFree(c->T.lfsr);
   (void)hipFree(c->T.gm);
   (void)hipFree(c->T.mt);
+  (void)hipFree(c->T.mtdig);
   (void)hipFree(c->T.defaults);
   (void)hipFree(c->scratch);
   delete c;
@@ -387,9 +393,13 @@ int prand_generate(prand_ctx* c, int gen, void* h_state, int dtype, void* d_out,
   int rc = ensure_mt_locked(c, gen);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  // sections of 2^k outputs: each starts from the state jumped j * 2^k ahead
-  // (one ladder application per set bit of j), fills its slice, and the last
-  // one leaves the advanced state
+  // Bulk sections of 2^k outputs cover [0, T); each starts from the state
+  // jumped j * 2^k ahead (one ladder application per set bit of j) and fills
+  // its slice.  A final section covers [T, n) and leaves the advanced state.
+  // For MT19937, T is the last twist-block boundary of the original stream
+  // before n: a jump yields the canonical window, which differs from the
+  // array sequential generation holds only in bits the next twist
+  // overwrites, so the final section's state is exactly the sequential one.
   uint64_t min_sec, max_secs;
   switch (gen) {
     case PRAND_MT19937: min_sec = 1ull << 18; max_secs = 4096; break;
@@ -400,35 +410,49 @@ int prand_generate(prand_ctx* c, int gen, void* h_state, int dtype, void* d_out,
   int k = 0;
   while ((1ull << k) < min_sec) k++;
   while (((n + (1ull << k) - 1) >> k) > max_secs) k++;
-  if ((1ull << k) >= n) k = 63;  // one section
-  const uint64_t seclen = k == 63 ? n : (1ull << k);
-  const uint64_t nsec = (n + seclen - 1) / seclen;
-  const uint64_t lastlen = n - (nsec - 1) * seclen;
+  const bool one = (1ull << k) >= n;
+  const uint64_t seclen = one ? n : (1ull << k);
+  uint64_t T;
+  if (one) {
+    T = 0;
+  } else if (gen == PRAND_MT19937) {
+    const uint32_t idx0 = std::min<uint32_t>(((const MtState*)h_state)->idx, 624u);
+    const uint64_t r0 = 624 - idx0;
+    T = (n <= r0) ? 0 : r0 + 624 * ((n - r0 + 623) / 624 - 1);
+  } else {
+    T = ((n + seclen - 1) / seclen - 1) * seclen;
+  }
+  const uint64_t full = T / seclen, part = T % seclen;
+  const uint64_t nb = full + (part ? 1 : 0);   // bulk sections
+  const uint64_t nst = nb + 1;                 // plus the final one
   const size_t sb = state_bytes(gen);
+  const size_t es = elem_bytes(dtype);
   void* d_states = nullptr;
   uint64_t* d_dist = nullptr;
-  hipError_t e = hipMalloc(&d_states, nsec * sb);
-  if (e == hipSuccess) e = hipMalloc((void**)&d_dist, nsec * 8);
+  hipError_t e = hipMalloc(&d_states, nst * sb);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_dist, nst * 8);
   {
     std::lock_guard<std::mutex> lk(c->mu);
     void* d_base = c->scratch;
     if (e == hipSuccess) e = hipMemcpyAsync(d_base, h_state, sb, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(iota_times_kernel, dim3((uint32_t)((nsec + 255) / 256)), dim3(256), 0, st, d_dist,
-                         (uint32_t)nsec, seclen);
+      hipLaunchKernelGGL(section_dist_kernel, dim3((uint32_t)((nst + 255) / 256)), dim3(256), 0, st, d_dist,
+                         (uint32_t)nb, seclen, T);
       e = hipGetLastError();
     }
     JumpSpec js;
     js.dist = d_dist;
     js.nlimbs = 1;
     js.per_stream = 1;
-    if (e == hipSuccess) e = launch_jump(c, gen, d_states, (uint32_t)nsec, js, d_base, st);
-    if (e == hipSuccess && nsec > 1)
-      e = launch_streams(c, gen, d_states, d_states, (uint32_t)(nsec - 1), seclen, dtype, d_out, st);
-    void* last = (char*)d_states + (nsec - 1) * sb;
-    if (e == hipSuccess)
-      e = launch_streams(c, gen, last, last, 1, lastlen, dtype, (char*)d_out + (nsec - 1) * seclen * elem_bytes(dtype),
-                         st);
+    if (e == hipSuccess) e = launch_jump(c, gen, d_states, (uint32_t)nst, js, d_base, st);
+    if (e == hipSuccess && full)
+      e = launch_streams(c, gen, d_states, d_states, (uint32_t)full, seclen, dtype, d_out, st);
+    if (e == hipSuccess && part) {
+      void* sp = (char*)d_states + full * sb;
+      e = launch_streams(c, gen, sp, sp, 1, part, dtype, (char*)d_out + full * seclen * es, st);
+    }
+    void* last = (char*)d_states + nb * sb;
+    if (e == hipSuccess) e = launch_streams(c, gen, last, last, 1, n - T, dtype, (char*)d_out + T * es, st);
     if (e == hipSuccess) e = hipMemcpyAsync(h_state, last, sb, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   }

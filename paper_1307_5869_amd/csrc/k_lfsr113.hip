@@ -6,6 +6,7 @@
 // (stream, section) pair with the four words in registers; jumps apply the
 // 32x32 F2 matrices T_c^(2^b) of the context ladder for each set bit b.
 #include "prand_impl.h"
+#include "regstream.h"
 
 namespace prand {
 namespace {
@@ -14,11 +15,13 @@ __device__ __forceinline__ uint32_t comp(uint32_t z, uint32_t mask, int q, int s
   return ((z & mask) << s) ^ (((z << q) ^ z) >> sh1);
 }
 
-struct Regs {
+}  // namespace
+struct LfsrRegs {
   uint32_t z0, z1, z2, z3;
 };
+namespace {
 
-__device__ __forceinline__ uint32_t step(Regs& r) {
+__device__ __forceinline__ uint32_t step(LfsrRegs& r) {
   r.z0 = comp(r.z0, 0xFFFFFFFEu, 6, 13, 18);
   r.z1 = comp(r.z1, 0xFFFFFFF8u, 2, 27, 2);
   r.z2 = comp(r.z2, 0xFFFFFFF0u, 13, 21, 7);
@@ -33,8 +36,7 @@ __device__ __forceinline__ uint32_t f2_apply(const uint32_t* __restrict__ cols, 
   return r;
 }
 
-// kept out of line: the generation loop should not pay for its registers
-__device__ __noinline__ void jump_state(const uint32_t* ladder, uint32_t z[4], const uint64_t* limbs,
+__device__ __forceinline__ void jump_state(const uint32_t* ladder, uint32_t z[4], const uint64_t* limbs,
                                            int nlimbs) {
   for (int l = 0; l < nlimbs; l++) {
     uint64_t w = limbs[l];
@@ -47,62 +49,19 @@ __device__ __noinline__ void jump_state(const uint32_t* ladder, uint32_t z[4], c
   }
 }
 
-template <int DT>
-__device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
-  if (DT == PRAND_U32) ((uint32_t*)out)[i] = w;
-  else if (DT == PRAND_F32) ((float*)out)[i] = (float)(w >> 8) * 0x1p-24f;
-  else ((double*)out)[i] = (double)w * 0x1p-32;
-}
-
-template <int DT, bool VEC>
-__global__ void __launch_bounds__(256) lfsr_generate_kernel(const LfsrState* sin,
-                                                            LfsrState* sout, uint32_t count,
-                                                            uint64_t n, int nsec_log2, uint64_t seclen,
-                                                            void* __restrict__ out,
-                                                            const uint32_t* __restrict__ ladder) {
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t s = gid >> nsec_log2;
-  if (s >= count) return;
-  const uint64_t j = gid & ((1ull << nsec_log2) - 1);
-  const uint64_t start = j * seclen;
-  const uint64_t jlast = (n == 0) ? 0 : (n - 1) / seclen;
-  if (j > jlast) return;
-  const uint64_t len = (j == jlast) ? n - start : seclen;
-
-  LfsrState st = sin[s];
-  if (start) jump_state(ladder, st.z, &start, 1);
-  Regs r = {st.z[0], st.z[1], st.z[2], st.z[3]};
-  const uint64_t base = s * n + start;
-  uint64_t i = 0;
-  if (VEC) {
-    if (DT == PRAND_F64) {
-      double2* o = (double2*)((double*)out + base);
-      for (; i + 2 <= len; i += 2) {
-        uint32_t a = step(r), b = step(r);
-        o[i >> 1] = make_double2((double)a * 0x1p-32, (double)b * 0x1p-32);
-      }
-    } else if (DT == PRAND_F32) {
-      float4* o = (float4*)((float*)out + base);
-      for (; i + 4 <= len; i += 4) {
-        uint32_t a = step(r), b = step(r), c = step(r), d = step(r);
-        o[i >> 2] = make_float4((float)(a >> 8) * 0x1p-24f, (float)(b >> 8) * 0x1p-24f,
-                                (float)(c >> 8) * 0x1p-24f, (float)(d >> 8) * 0x1p-24f);
-      }
-    } else {
-      uint4* o = (uint4*)((uint32_t*)out + base);
-      for (; i + 4 <= len; i += 4) {
-        uint32_t a = step(r), b = step(r), c = step(r), d = step(r);
-        o[i >> 2] = make_uint4(a, b, c, d);
-      }
-    }
-  }
-  for (; i < len; i++) put<DT>(out, base + i, step(r));
-  if (j == jlast) {
+struct LfsrGen {
+  using State = LfsrState;
+  using Regs = prand::LfsrRegs;
+  __device__ static Regs load(const LfsrState& st) { return Regs{st.z[0], st.z[1], st.z[2], st.z[3]}; }
+  __device__ static LfsrState save(const Regs& r) {
     LfsrState o;
     o.z[0] = r.z0; o.z[1] = r.z1; o.z[2] = r.z2; o.z[3] = r.z3;
-    sout[s] = o;
+    return o;
   }
-}
+  __device__ static void jump(LfsrState& st, uint64_t d, const uint32_t* ladder) { jump_state(ladder, st.z, &d, 1); }
+  __device__ static uint32_t next(Regs& r) { return step(r); }
+  __device__ static double f64(uint32_t w) { return (double)w * 0x1p-32; }
+};
 
 __global__ void __launch_bounds__(256) lfsr_jump_kernel(LfsrState* __restrict__ states, uint32_t count,
                                                         const uint64_t* __restrict__ dist, int nlimbs,
@@ -130,32 +89,12 @@ __global__ void __launch_bounds__(256) lfsr_jump_kernel(LfsrState* __restrict__ 
   states[i] = st;
 }
 
-template <int DT>
-hipError_t launch_gen_dt(const DeviceTables& T, const LfsrState* sin, LfsrState* sout, uint32_t count,
-                         uint64_t n, int nsec_log2, uint64_t seclen, void* out, hipStream_t st, bool vec) {
-  const uint64_t lanes = (uint64_t)count << nsec_log2;
-  const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
-  if (vec)
-    hipLaunchKernelGGL((lfsr_generate_kernel<DT, true>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
-                       nsec_log2, seclen, out, T.lfsr);
-  else
-    hipLaunchKernelGGL((lfsr_generate_kernel<DT, false>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
-                       nsec_log2, seclen, out, T.lfsr);
-  return hipGetLastError();
-}
-
 }  // namespace
 
 hipError_t launch_lfsr_generate(const DeviceTables& T, const LfsrState* sin, LfsrState* sout, uint32_t count,
                                 uint64_t n, int nsec_log2, uint64_t seclen, int dtype, void* out,
                                 hipStream_t st) {
-  const uint64_t es = dtype == PRAND_F64 ? 8 : 4;
-  const bool vec = ((uintptr_t)out % 16 == 0) && ((n * es) % 16 == 0) && ((seclen * es) % 16 == 0);
-  switch (dtype) {
-    case PRAND_U32: return launch_gen_dt<PRAND_U32>(T, sin, sout, count, n, nsec_log2, seclen, out, st, vec);
-    case PRAND_F32: return launch_gen_dt<PRAND_F32>(T, sin, sout, count, n, nsec_log2, seclen, out, st, vec);
-    default: return launch_gen_dt<PRAND_F64>(T, sin, sout, count, n, nsec_log2, seclen, out, st, vec);
-  }
+  return launch_regstream<LfsrGen>(sin, sout, count, n, nsec_log2, seclen, dtype, out, T.lfsr, st);
 }
 
 hipError_t launch_lfsr_jump(const DeviceTables& T, LfsrState* states, uint32_t count, const JumpSpec& js,

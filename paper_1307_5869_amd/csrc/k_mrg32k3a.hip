@@ -1,13 +1,14 @@
 // MRG32K3A on gfx950: X_{n+1} = A X_n mod m1, Y_{n+1} = B Y_n mod m2 (paper,
 // section on jumping ahead for MRG32K3A), output z = (x - y) mod m1 in
 // [1, m1].  One lane owns one (stream, section) pair and keeps the six state
-// words in registers.  The recurrence runs in exact double arithmetic: every
+// words in registers (the store path is shared, see regstream.h).  The recurrence runs in exact double arithmetic: every
 // product is an integer below 2^53, so fma + floor(p / m) with a +-1
 // correction gives the exact residue at full FP64 rate (gfx950 issues FP64
 // FMA at the FP32 rate, integer 32x32 multiplies at a quarter of it).
 // Jumps apply A^(2^b), B^(2^b) from the context ladder for each set bit b of
 // the distance (binary decomposition, O(log n)).
 #include "prand_impl.h"
+#include "regstream.h"
 
 namespace prand {
 namespace {
@@ -18,9 +19,11 @@ constexpr double kInvM1 = 1.0 / 4294967087.0;
 constexpr double kInvM2 = 1.0 / 4294944443.0;
 constexpr double kNorm = 1.0 / 4294967088.0;   // RN(1/(m1+1))
 
+}  // namespace
 struct Regs {
   double x0, x1, x2, y0, y1, y2;   // x_n, x_{n-1}, x_{n-2}, ...
 };
+namespace {
 
 __device__ __forceinline__ double reduce_exact(double p, double m, double inv) {
   double k = floor(p * inv);
@@ -65,7 +68,7 @@ __device__ __forceinline__ void mat3_apply(const uint32_t* M, uint32_t v[3]) {
   v[0] = r[0]; v[1] = r[1]; v[2] = r[2];
 }
 
-__device__ __noinline__ void jump_state(const uint32_t* ladder, uint32_t x[3], uint32_t y[3],
+__device__ __forceinline__ void jump_state(const uint32_t* ladder, uint32_t x[3], uint32_t y[3],
                                            const uint64_t* limbs, int nlimbs) {
   for (int l = 0; l < nlimbs; l++) {
     uint64_t w = limbs[l];
@@ -79,71 +82,22 @@ __device__ __noinline__ void jump_state(const uint32_t* ladder, uint32_t x[3], u
   }
 }
 
-template <int DT>
-__device__ __forceinline__ void put(void* out, uint64_t i, double z) {
-  if (DT == PRAND_U32) {
-    ((uint32_t*)out)[i] = (uint32_t)z;
-  } else if (DT == PRAND_F32) {
-    ((float*)out)[i] = (float)(((uint32_t)z) >> 8) * 0x1p-24f;
-  } else {
-    ((double*)out)[i] = z * kNorm;
+struct MrgGen {
+  using State = MrgState;
+  using Regs = prand::Regs;
+  __device__ static Regs load(const MrgState& st) {
+    return Regs{(double)st.x[0], (double)st.x[1], (double)st.x[2], (double)st.y[0], (double)st.y[1], (double)st.y[2]};
   }
-}
-
-// Lane gid -> stream gid >> nsec_log2, section gid & (nsec - 1).  The
-// sections of one stream cover [j*seclen, min((j+1)*seclen, n)); the lane
-// whose section ends at n writes the advanced state to sout.
-template <int DT, bool VEC>
-__global__ void __launch_bounds__(256) mrg_generate_kernel(const MrgState* sin,
-                                                           MrgState* sout, uint32_t count,
-                                                           uint64_t n, int nsec_log2, uint64_t seclen,
-                                                           void* __restrict__ out,
-                                                           const uint32_t* __restrict__ ladder) {
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t s = gid >> nsec_log2;
-  if (s >= count) return;
-  const uint64_t j = gid & ((1ull << nsec_log2) - 1);
-  const uint64_t start = j * seclen;
-  const uint64_t jlast = (n == 0) ? 0 : (n - 1) / seclen;
-  if (j > jlast) return;
-  const uint64_t len = (j == jlast) ? n - start : seclen;
-
-  MrgState st = sin[s];
-  if (start) jump_state(ladder, st.x, st.y, &start, 1);
-  Regs r = {(double)st.x[0], (double)st.x[1], (double)st.x[2],
-            (double)st.y[0], (double)st.y[1], (double)st.y[2]};
-  const uint64_t base = s * n + start;
-  uint64_t i = 0;
-  if (VEC) {
-    if (DT == PRAND_F64) {
-      double2* o = (double2*)((double*)out + base);
-      for (; i + 2 <= len; i += 2) {
-        double a = step(r), b = step(r);
-        o[i >> 1] = make_double2(a * kNorm, b * kNorm);
-      }
-    } else if (DT == PRAND_F32) {
-      float4* o = (float4*)((float*)out + base);
-      for (; i + 4 <= len; i += 4) {
-        uint32_t a = (uint32_t)step(r), b = (uint32_t)step(r), c = (uint32_t)step(r), d = (uint32_t)step(r);
-        o[i >> 2] = make_float4((float)(a >> 8) * 0x1p-24f, (float)(b >> 8) * 0x1p-24f,
-                                (float)(c >> 8) * 0x1p-24f, (float)(d >> 8) * 0x1p-24f);
-      }
-    } else {
-      uint4* o = (uint4*)((uint32_t*)out + base);
-      for (; i + 4 <= len; i += 4) {
-        uint32_t a = (uint32_t)step(r), b = (uint32_t)step(r), c = (uint32_t)step(r), d = (uint32_t)step(r);
-        o[i >> 2] = make_uint4(a, b, c, d);
-      }
-    }
-  }
-  for (; i < len; i++) put<DT>(out, base + i, step(r));
-  if (j == jlast) {
+  __device__ static MrgState save(const Regs& r) {
     MrgState o;
     o.x[0] = (uint32_t)r.x0; o.x[1] = (uint32_t)r.x1; o.x[2] = (uint32_t)r.x2;
     o.y[0] = (uint32_t)r.y0; o.y[1] = (uint32_t)r.y1; o.y[2] = (uint32_t)r.y2;
-    sout[s] = o;
+    return o;
   }
-}
+  __device__ static void jump(MrgState& st, uint64_t d, const uint32_t* ladder) { jump_state(ladder, st.x, st.y, &d, 1); }
+  __device__ static uint32_t next(Regs& r) { return (uint32_t)step(r); }
+  __device__ static double f64(uint32_t z) { return (double)z * kNorm; }
+};
 
 // One lane per stream: states[i] = (base ? *base : states[i]) jumped by the
 // stream's distance (explicit limbs, or id * 2^block_e).
@@ -174,32 +128,12 @@ __global__ void __launch_bounds__(256) mrg_jump_kernel(MrgState* __restrict__ st
   states[i] = st;
 }
 
-template <int DT>
-hipError_t launch_gen_dt(const DeviceTables& T, const MrgState* sin, MrgState* sout, uint32_t count, uint64_t n,
-                         int nsec_log2, uint64_t seclen, void* out, hipStream_t st, bool vec) {
-  const uint64_t lanes = (uint64_t)count << nsec_log2;
-  const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
-  if (vec)
-    hipLaunchKernelGGL((mrg_generate_kernel<DT, true>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
-                       nsec_log2, seclen, out, T.mrg);
-  else
-    hipLaunchKernelGGL((mrg_generate_kernel<DT, false>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
-                       nsec_log2, seclen, out, T.mrg);
-  return hipGetLastError();
-}
-
 }  // namespace
 
 hipError_t launch_mrg_generate(const DeviceTables& T, const MrgState* sin, MrgState* sout, uint32_t count,
                                uint64_t n, int nsec_log2, uint64_t seclen, int dtype, void* out,
                                hipStream_t st) {
-  const uint64_t es = dtype == PRAND_F64 ? 8 : 4;
-  const bool vec = ((uintptr_t)out % 16 == 0) && ((n * es) % 16 == 0) && ((seclen * es) % 16 == 0);
-  switch (dtype) {
-    case PRAND_U32: return launch_gen_dt<PRAND_U32>(T, sin, sout, count, n, nsec_log2, seclen, out, st, vec);
-    case PRAND_F32: return launch_gen_dt<PRAND_F32>(T, sin, sout, count, n, nsec_log2, seclen, out, st, vec);
-    default: return launch_gen_dt<PRAND_F64>(T, sin, sout, count, n, nsec_log2, seclen, out, st, vec);
-  }
+  return launch_regstream<MrgGen>(sin, sout, count, n, nsec_log2, seclen, dtype, out, T.mrg, st);
 }
 
 hipError_t launch_mrg_jump(const DeviceTables& T, MrgState* states, uint32_t count, const JumpSpec& js,

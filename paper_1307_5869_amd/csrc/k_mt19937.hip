@@ -12,7 +12,9 @@
 // the window of 624 consecutive raw words starting i-1 words later, so word t
 // of the result is the XOR of seq[i + t] over the set coefficients i, seq
 // being the raw-word sequence continued from the state.  A distance is applied
-// as one polynomial x^(2^b) mod phi (from the context ladder) per set bit b.
+// as one polynomial x^(2^b) mod phi (from the context ladder) per set bit b;
+// block splitting by id * 2^432 from a block-aligned state uses the context's
+// per-byte tables x^(d 2^(432 + 8j)) mod phi instead: at most 8 polynomials.
 // One wavefront does one stream: the sequence is produced 227 words at a time
 // into an LDS ring, and lane l accumulates outputs t = 10l .. 10l+9 while a
 // register window of 10 sequence words slides over the coefficients, so each
@@ -152,7 +154,8 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
                                                      const uint64_t* __restrict__ dist, int nlimbs, int per_stream,
                                                      const uint64_t* __restrict__ ids, int block_e,
                                                      const MtState* __restrict__ base,
-                                                     const uint32_t* __restrict__ ladder) {
+                                                     const uint32_t* __restrict__ ladder,
+                                                     const uint32_t* __restrict__ digits) {
   __shared__ uint32_t ring[kRing];
   const uint32_t s = blockIdx.x;
   if (s >= count) return;
@@ -172,27 +175,37 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
   for (int i = lane; i < 624; i += 64) ring[i] = src->mt[i];
   uint32_t idx = src->idx < 624u ? src->idx : 624u;
   __syncthreads();
-  // consume the rest of the current block first
-  const uint64_t rest = 624 - idx;
-  bool small = true;
-  for (int l = 1; l < kMaxLimbs; l++) small = small && (N[l] == 0);
-  small = small && (N[0] <= rest);
-  if (small) {
-    idx += (uint32_t)N[0];
-  } else {
-    uint64_t borrow = rest;
-    for (int l = 0; l < kMaxLimbs && borrow; l++) {
-      const uint64_t old = N[l];
-      N[l] = old - borrow;
-      borrow = old < borrow ? 1 : 0;
+  if (ids && block_e == kMtDigitE && idx == 624) {
+    // block splitting from a block-aligned state: id * 2^432 as 8 base-256
+    // digits, one table polynomial x^(d 2^(432 + 8j)) per nonzero digit
+    const uint64_t id = ids[s];
+    for (int j = 0; j < 8; j++) {
+      const uint32_t d = (uint32_t)(id >> (8 * j)) & 255u;
+      if (d) apply_poly(ring, digits + ((size_t)j * 256 + d) * 624, lane);
     }
-    idx = 624;
-    for (int l = 0; l < kMaxLimbs; l++) {
-      uint64_t wd = N[l];
-      while (wd) {
-        const int b = __builtin_ctzll(wd) + 64 * l;
-        wd &= wd - 1;
-        apply_poly(ring, ladder + (size_t)b * 624, lane);
+  } else {
+    // consume the rest of the current block first
+    const uint64_t rest = 624 - idx;
+    bool small = true;
+    for (int l = 1; l < kMaxLimbs; l++) small = small && (N[l] == 0);
+    small = small && (N[0] <= rest);
+    if (small) {
+      idx += (uint32_t)N[0];
+    } else {
+      uint64_t borrow = rest;
+      for (int l = 0; l < kMaxLimbs && borrow; l++) {
+        const uint64_t old = N[l];
+        N[l] = old - borrow;
+        borrow = old < borrow ? 1 : 0;
+      }
+      idx = 624;
+      for (int l = 0; l < kMaxLimbs; l++) {
+        uint64_t wd = N[l];
+        while (wd) {
+          const int b = __builtin_ctzll(wd) + 64 * l;
+          wd &= wd - 1;
+          apply_poly(ring, ladder + (size_t)b * 624, lane);
+        }
       }
     }
   }
@@ -218,7 +231,7 @@ hipError_t launch_mt_generate(MtState* states, uint32_t count, uint64_t n, int d
 hipError_t launch_mt_jump(const DeviceTables& T, MtState* states, uint32_t count, const JumpSpec& js,
                           const MtState* base, hipStream_t st) {
   hipLaunchKernelGGL(mt_jump_kernel, dim3(count), dim3(64), 0, st, states, count, js.dist, js.nlimbs, js.per_stream,
-                     js.ids, js.block_e, base, T.mt);
+                     js.ids, js.block_e, base, T.mt, T.mtdig);
   return hipGetLastError();
 }
 

@@ -1,0 +1,200 @@
+// MT19937 jump polynomials on the host (context set-up).
+//
+// The paper's MT19937 jump (section on MT19937 jump-ahead, equation g_v)
+// needs g_v = x^v mod phi, phi the characteristic polynomial of the
+// generator's F2-linear transition; computing g_v is sequential work, so the
+// paper precomputes polynomials for v = 2^n.  Here phi is found by
+// Berlekamp-Massey on 2 * 19937 output bits, and products modulo phi use the
+// x86 carry-less multiply with Barrett reduction (mu = floor(x^(2n) / phi)),
+// about a millisecond per product, so that besides the 2^b ladder the
+// context can hold per-byte digit tables x^(d * 2^(e + 8j)) mod phi: a stream
+// id then costs one polynomial application per nonzero byte instead of one
+// per set bit.
+#include "mt_poly.h"
+
+#include <wmmintrin.h>
+
+#include <cstring>
+#include <thread>
+#include <vector>
+
+namespace prand {
+namespace {
+
+constexpr int kN = kMtDeg;
+constexpr int kW = 312;   // 64-bit words of a reduced polynomial (19968 bits)
+
+typedef std::vector<uint64_t> Poly;
+
+struct HostMt {
+  uint32_t mt[624];
+  int idx;
+  explicit HostMt(uint32_t s) {
+    mt[0] = s;
+    for (int i = 1; i < 624; i++) mt[i] = 1812433253u * (mt[i - 1] ^ (mt[i - 1] >> 30)) + (uint32_t)i;
+    idx = 624;
+  }
+  uint32_t next() {
+    if (idx == 624) {
+      for (int j = 0; j < 624; j++) {
+        uint32_t y = (mt[j] & 0x80000000u) | (mt[j + 1 < 624 ? j + 1 : 0] & 0x7FFFFFFFu);
+        mt[j] = mt[j + 397 < 624 ? j + 397 : j + 397 - 624] ^ (y >> 1) ^ ((y & 1u) * 0x9908B0DFu);
+      }
+      idx = 0;
+    }
+    uint32_t y = mt[idx++];
+    y ^= y >> 11;
+    y ^= (y << 7) & 0x9D2C5680u;
+    y ^= (y << 15) & 0xEFC60000u;
+    return y ^ (y >> 18);
+  }
+};
+
+inline int getbit(const uint64_t* a, size_t i) { return (int)((a[i >> 6] >> (i & 63)) & 1u); }
+inline void flipbit(uint64_t* a, size_t i) { a[i >> 6] ^= 1ull << (i & 63); }
+
+inline uint64_t bits64_at(const std::vector<uint64_t>& a, size_t pos) {
+  size_t w = pos >> 6, r = pos & 63;
+  uint64_t lo = w < a.size() ? a[w] >> r : 0;
+  uint64_t hi = (r && w + 1 < a.size()) ? a[w + 1] << (64 - r) : 0;
+  return lo | hi;
+}
+
+// phi (with its x^19937 term) as kW + 1 words; false unless deg phi = 19937
+bool find_phi(Poly& phi) {
+  const size_t n = 2 * kN + 64;
+  const size_t nw = n / 64 + 2;
+  std::vector<uint64_t> rev(nw, 0), C(nw, 0), B(nw, 0), T(nw, 0);
+  HostMt g(5489u);
+  for (size_t i = 0; i < n; i++)
+    if (g.next() & 1u) rev[(n - 1 - i) >> 6] |= 1ull << ((n - 1 - i) & 63);
+  C[0] = B[0] = 1;
+  size_t L = 0, m = 1;
+  for (size_t i = 0; i < n; i++) {
+    // discrepancy sum_{j<=L} c_j s_{i-j}; s_{i-j} sits at reversed position n-1-i+j
+    const size_t off = n - 1 - i;
+    uint64_t acc = 0;
+    for (size_t w = 0; w <= L / 64; w++) acc ^= C[w] & bits64_at(rev, off + 64 * w);
+    if (!(__builtin_popcountll(acc) & 1)) { m++; continue; }
+    T = C;
+    const size_t q = m >> 6, r = m & 63;
+    for (size_t w = 0; w + q < nw; w++) {
+      C[w + q] ^= B[w] << r;
+      if (r && w + q + 1 < nw) C[w + q + 1] ^= B[w] >> (64 - r);
+    }
+    if (2 * L <= i) {
+      L = i + 1 - L;
+      B = T;
+      m = 1;
+    } else {
+      m++;
+    }
+  }
+  if (L != (size_t)kN) return false;
+  phi.assign(kW + 1, 0);
+  for (int i = 0; i <= kN; i++) {
+    const size_t j = kN - i;   // phi_i = c_{L-i}
+    if (getbit(C.data(), j)) flipbit(phi.data(), i);
+  }
+  return true;
+}
+
+// r[0..na+nb) = a * b in F2[x]
+__attribute__((target("pclmul,sse2"))) void clmul(const uint64_t* a, int na, const uint64_t* b, int nb,
+                                                  uint64_t* r) {
+  std::memset(r, 0, (size_t)(na + nb) * 8);
+  for (int i = 0; i < na; i++) {
+    if (!a[i]) continue;
+    const __m128i A = _mm_set_epi64x(0, (long long)a[i]);
+    for (int j = 0; j < nb; j++) {
+      if (!b[j]) continue;
+      const __m128i P = _mm_clmulepi64_si128(A, _mm_set_epi64x(0, (long long)b[j]), 0x00);
+      r[i + j] ^= (uint64_t)_mm_cvtsi128_si64(P);
+      r[i + j + 1] ^= (uint64_t)_mm_cvtsi128_si64(_mm_unpackhi_epi64(P, P));
+    }
+  }
+}
+
+// a >> s into out (nout words)
+void shr(const uint64_t* a, int na, int s, uint64_t* out, int nout) {
+  const int q = s >> 6, r = s & 63;
+  for (int w = 0; w < nout; w++) {
+    const int i = w + q;
+    uint64_t lo = i < na ? a[i] >> r : 0;
+    uint64_t hi = (r && i + 1 < na) ? a[i + 1] << (64 - r) : 0;
+    out[w] = lo | hi;
+  }
+}
+
+struct Field {
+  Poly phi;   // kW + 1 words
+  Poly mu;    // floor(x^(2n) / phi), degree n: kW + 1 words
+
+  bool init() {
+    if (!find_phi(phi)) return false;
+    // long division of x^(2n) by phi
+    const int tw = 2 * kW + 2;
+    std::vector<uint64_t> rem(tw, 0);
+    flipbit(rem.data(), 2 * kN);
+    mu.assign(kW + 1, 0);
+    for (int d = 2 * kN; d >= kN; d--) {
+      if (!getbit(rem.data(), d)) continue;
+      flipbit(mu.data(), d - kN);
+      const int sh = d - kN, q = sh >> 6, r = sh & 63;
+      for (int w = 0; w <= kW; w++) {
+        rem[w + q] ^= phi[w] << r;
+        if (r && w + q + 1 < tw) rem[w + q + 1] ^= phi[w] >> (64 - r);
+      }
+    }
+    return true;
+  }
+
+  // r = a * b mod phi (a, b, r: kW words, degree < n)
+  void mulmod(const uint64_t* a, const uint64_t* b, uint64_t* r) const {
+    uint64_t c[2 * kW], hi[kW + 1], t[2 * kW + 2], q[kW + 1], s[2 * kW + 2];
+    clmul(a, kW, b, kW, c);                 // degree < 2n - 1
+    shr(c, 2 * kW, kN, hi, kW + 1);         // c div x^n
+    clmul(hi, kW + 1, mu.data(), kW + 1, t);
+    shr(t, 2 * kW + 2, kN, q, kW + 1);      // quotient
+    clmul(q, kW + 1, phi.data(), kW + 1, s);
+    for (int w = 0; w < kW; w++) r[w] = c[w] ^ s[w];
+    r[kW - 1] &= (1ull << (kN - 64 * (kW - 1))) - 1;   // keep bits < n
+  }
+};
+
+void store(const uint64_t* p, uint32_t* out) {
+  for (int w = 0; w < kW; w++) {
+    out[2 * w] = (uint32_t)p[w];
+    out[2 * w + 1] = (uint32_t)(p[w] >> 32);
+  }
+}
+
+}  // namespace
+
+bool mt_build_polys(uint32_t* ladder, int nladder, uint32_t* digits, int digit_e) {
+  Field F;
+  if (!F.init()) return false;
+  std::vector<uint64_t> lad((size_t)nladder * kW, 0);
+  lad[0] = 2;   // x
+  for (int b = 0; b + 1 < nladder; b++) F.mulmod(&lad[(size_t)b * kW], &lad[(size_t)b * kW], &lad[(size_t)(b + 1) * kW]);
+  for (int b = 0; b < nladder; b++) store(&lad[(size_t)b * kW], ladder + (size_t)b * kMtPolyWords);
+  if (digits) {
+    std::memset(digits, 0, sizeof(uint32_t) * 8 * 256 * kMtPolyWords);
+    std::vector<std::thread> th;
+    for (int j = 0; j < 8; j++) {
+      th.emplace_back([&, j]() {
+        const uint64_t* P = &lad[(size_t)(digit_e + 8 * j) * kW];
+        std::vector<uint64_t> g(P, P + kW), nxt(kW);
+        for (int d = 1; d < 256; d++) {
+          store(g.data(), digits + ((size_t)j * 256 + d) * kMtPolyWords);
+          F.mulmod(g.data(), P, nxt.data());
+          g.swap(nxt);
+        }
+      });
+    }
+    for (auto& t : th) t.join();
+  }
+  return true;
+}
+
+}  // namespace prand

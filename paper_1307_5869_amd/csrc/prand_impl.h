@@ -71,9 +71,12 @@ struct DeviceTables {
   uint32_t* lfsr = nullptr;   // [kLadder][4][32]: columns of T_c^(2^b)
   uint64_t* gm = nullptr;     // [8][kLadder][4]: (a b; c d) = M^(2^b) mod p
   uint32_t* mt = nullptr;     // [kLadder][624]: bits of x^(2^b) mod phi (19937 used)
+  uint32_t* mtdig = nullptr;  // [8][256][624]: x^(d 2^(kMtDigitE + 8j)) mod phi
   void* defaults = nullptr;   // default state of each generator, 11 x 2560 bytes
 };
 constexpr size_t kDefaultStride = 2560;
+// exponent of the MT19937 digit tables: the block-splitting block 2^432
+constexpr int kMtDigitE = 432;
 
 // ---- launchers (one per kernel family); all enqueue on `st` ----
 // Distances: `dist` holds nlimbs limbs per stream when per_stream, else one
@@ -120,8 +123,5 @@ struct HostTables {
 void build_mrg_ladder(uint32_t* out);
 void build_lfsr_ladder(uint32_t* out);
 void build_gm_ladders(uint64_t* out);
-// phi of MT19937 by Berlekamp-Massey, then x^(2^b) mod phi for b < kLadder;
-// out: kLadder * 624 words.  Returns false if the polynomial has the wrong degree.
-bool build_mt_ladder(uint32_t* out);
 
 }  // namespace prand

@@ -62,7 +62,7 @@ def test_seed_and_default_match_oracle(ctx, oracle, gen):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("gen", GENS)
-@pytest.mark.parametrize("count,n", [(1, 1), (3, 3), (37, 1000), (5, 4101), (64, 257)])
+@pytest.mark.parametrize("count,n", [(1, 1), (3, 3), (37, 1000), (5, 4101), (64, 257), (33, 4132), (130, 8192)])
 def test_generate_streams(ctx, oracle, gen, dtype, count, n):
     states = [oracle.seed(gen, 1000 + 7 * i) for i in range(count)]
     got, got_states = gpu_generate_streams(ctx, gen, states, n, dtype)
@@ -168,17 +168,20 @@ def test_init_streams_match_oracle(ctx, oracle, gen):
             ctx.init_stream(gen, v, 1)
 
 
+@pytest.mark.parametrize("consumed", [0, 100])
 @pytest.mark.parametrize("gen", GENS)
-def test_init_streams_from_explicit_base(ctx, oracle, gen):
+def test_init_streams_from_explicit_base(ctx, oracle, gen, consumed):
     base = oracle.seed(gen, 31337)
-    ids = [0, 5, 77]
+    if consumed:
+        oracle.generate(gen, base, consumed)    # a base in the middle of its sequence
+    ids = [0, 5, 77, 0x0102030405060708]
     t = torch.tensor(np.array(ids, dtype=np.uint64).view(np.int64), device="cuda")
     db = torch.from_numpy(base.copy()).cuda()
     d = torch.empty(len(ids) * P.state_bytes(gen), dtype=torch.uint8, device="cuda")
     ctx.init_streams_dev(gen, 0, db, t, len(ids), d)
     torch.cuda.synchronize()
     for sid, st in zip(ids, from_dev(d, gen)):
-        assert np.array_equal(st, oracle.init_stream(gen, 0, sid, base=base))
+        assert np.array_equal(st, oracle.init_stream(gen, 0, sid, base=base)), sid
 
 
 SECTIONED_N = {0: 3 * 2**18 + 7, 1: 300001, 2: 300001}
@@ -191,6 +194,23 @@ def test_generate_single_stream_sections(ctx, oracle, gen, dtype):
     st = oracle.seed(gen, 2718)
     if gen in (0, 9):
         oracle.generate(gen, st, 13)
+    mine = st.copy()
+    out = torch.empty(n, dtype=TDT[dtype], device="cuda")
+    ctx.generate(gen, mine, dtype, out, n)
+    ref = oracle.generate(gen, st, n, dtype)
+    np.testing.assert_array_equal(out_np(out, dtype), ref)
+    assert np.array_equal(mine, st)
+
+
+@pytest.mark.parametrize("consumed", [0, 13, 624])
+@pytest.mark.parametrize("n", [1000, 2**19, 611 + 624 * 900, 611 + 624 * 900 + 1, 3 * 2**18 + 7])
+def test_mt19937_sections_leave_the_sequential_state(ctx, oracle, consumed, n):
+    """The final section of a long MT19937 fill starts on a twist-block
+    boundary, so the returned state is the sequential one byte for byte."""
+    gen, dtype = P.MT19937, P.U32
+    st = oracle.seed(gen, 99991)
+    if consumed:
+        oracle.generate(gen, st, consumed)
     mine = st.copy()
     out = torch.empty(n, dtype=TDT[dtype], device="cuda")
     ctx.generate(gen, mine, dtype, out, n)
