@@ -8,8 +8,9 @@
 // One lane per element: v = 1 ensembles (s = 32) take half a wavefront per
 // stream and pack a word with one ballot; v = 4 ensembles (s = 8) take 8
 // lanes and OR their nibbles with three xor-shuffles; GQ58.3 (s = 12) takes 16
-// lanes.  Each lane keeps the word of one step of every 32 (8), so a flush
-// writes consecutive words from consecutive lanes.
+// lanes (the OR-reductions use DPP row permutes).  Each lane keeps the word
+// of one step of every 32 (8), so a flush writes consecutive words from
+// consecutive lanes.
 //
 // Arithmetic is exact: special-form reductions (2^19-1, 2^29-3, 2^61-1,
 // 2^51-129) in integers, or FP64 where all values stay below 2^53 (GM31,
@@ -38,7 +39,8 @@ struct Eng<0> {
   __device__ static F to_fast(uint64_t x) { return (F)x; }
   __device__ static uint64_t from_fast(F y) { return y; }
   __device__ static F step(F xc, F xp) {
-    uint32_t t = 15u * xc + 28u * (g - xp);   // < 43 * 2^19
+    // operands < 2^19: 24-bit multiplies (full rate)
+    uint32_t t = __umul24(15u, xc) + __umul24(28u, g - xp);   // < 43 * 2^19
     t = (t & g) + (t >> 19);
     return min(t, t - g);
   }
@@ -224,6 +226,26 @@ __device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
   else ((double*)out)[i] = (double)w * 0x1p-32;
 }
 
+// v_writelane_b32: lane `lane` of v takes the wavefront-uniform value val
+__device__ __forceinline__ uint32_t writelane(uint32_t v, uint32_t val, uint32_t lane) {
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(val), "s"(lane));
+  return v;
+}
+
+// OR over aligned groups of 8 / 16 lanes with DPP row permutes (no LDS):
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror (lane i of
+// an 8-lane half reads lane 7-i) and row_mirror (lane i of a row reads 15-i)
+__device__ __forceinline__ uint32_t dpp_or8(uint32_t w) {
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0xB1, 0xF, 0xF, false);
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x4E, 0xF, 0xF, false);
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x141, 0xF, 0xF, false);
+  return w;
+}
+__device__ __forceinline__ uint32_t dpp_or16(uint32_t w) {
+  w = dpp_or8(w);
+  return w | (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x140, 0xF, 0xF, false);
+}
+
 // ------------------------------------------------ v = 1, s = 32: ballots
 template <int G, int DT>
 __global__ void __launch_bounds__(256) gm_gen32_kernel(const GmState* sin, GmState* sout,
@@ -235,17 +257,23 @@ __global__ void __launch_bounds__(256) gm_gen32_kernel(const GmState* sin, GmSta
   const bool live = s < count;
   Elem<G> el;
   el.load(live ? sin[s].xc[e] : 0, live ? sin[s].xp[e] : 0);
-  const int hsh = threadIdx.x & 32;
+  // the word of step u goes to lane u of each half: v_writelane from the
+  // ballot's two 32-bit halves
   uint32_t keep = 0;
   for (uint64_t t0 = 0; t0 < n; t0 += 32) {
     const int m = (n - t0) < 32 ? (int)(n - t0) : 32;
-    for (int u = 0; u < m; u++) {
+    auto one = [&](int u) {
       el.maybe_switch();
-      const uint32_t d = el.step();
-      const uint64_t mask = __ballot(d);
-      const uint32_t w = (uint32_t)(mask >> hsh);
-      keep = (u == li) ? w : keep;
+      const uint64_t mask = __ballot(el.step());
+      keep = writelane(keep, (uint32_t)mask, (uint32_t)u);
+      keep = writelane(keep, (uint32_t)(mask >> 32), (uint32_t)u + 32);
+    };
+    int u = 0;
+    for (; u + 2 <= m; u += 2) {   // two steps per trip: no register rotation
+      one(u);
+      one(u + 1);
     }
+    if (u < m) one(u);
     if (live && li < m) put<DT>(out, s * n + t0 + li, keep);
   }
   if (live) {
@@ -271,14 +299,17 @@ __global__ void __launch_bounds__(256) gm_gen8_kernel(const GmState* sin, GmStat
   uint32_t keep = 0;
   for (uint64_t t0 = 0; t0 < n; t0 += 8) {
     const int m = (n - t0) < 8 ? (int)(n - t0) : 8;
-    for (int u = 0; u < m; u++) {
+    auto one = [&](int u) {
       el.maybe_switch();
-      uint32_t w = el.step() << shift;
-      w |= __shfl_xor(w, 1);
-      w |= __shfl_xor(w, 2);
-      w |= __shfl_xor(w, 4);
+      const uint32_t w = dpp_or8(el.step() << shift);
       keep = (u == e) ? w : keep;
+    };
+    int u = 0;
+    for (; u + 2 <= m; u += 2) {
+      one(u);
+      one(u + 1);
     }
+    if (u < m) one(u);
     if (live && e < m) put<DT>(out, s * n + t0 + e, keep);
   }
   if (live) {
@@ -322,11 +353,7 @@ __global__ void __launch_bounds__(256) gq58x3_gen_kernel(const GmState* sin, GmS
     for (int u = 0; u < 8; u++) {
       const uint32_t d = el.step();
       uint64_t c = elem ? ((uint64_t)d << shift) : 0;
-      uint32_t lo = (uint32_t)c, hi = (uint32_t)(c >> 32);
-      lo |= __shfl_xor(lo, 1); hi |= __shfl_xor(hi, 1);
-      lo |= __shfl_xor(lo, 2); hi |= __shfl_xor(hi, 2);
-      lo |= __shfl_xor(lo, 4); hi |= __shfl_xor(hi, 4);
-      lo |= __shfl_xor(lo, 8); hi |= __shfl_xor(hi, 8);
+      const uint32_t lo = dpp_or16((uint32_t)c), hi = dpp_or16((uint32_t)(c >> 32));
       c = ((uint64_t)hi << 32) | lo;
       keep = (u == e) ? c : keep;
     }
