@@ -19,6 +19,8 @@
 // same recurrence mod p and the digit equal to floor(2^v y / p), so the
 // kernel runs exact mod-g steps only until every element of the wavefront has
 // collapsed and then switches to the mod-p recurrence.
+#include <type_traits>
+
 #include "prand_impl.h"
 
 namespace prand {
@@ -226,10 +228,20 @@ __device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
   else ((double*)out)[i] = (double)w * 0x1p-32;
 }
 
-// v_writelane_b32: lane `lane` of v takes the wavefront-uniform value val
-__device__ __forceinline__ uint32_t writelane(uint32_t v, uint32_t val, uint32_t lane) {
-  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(val), "s"(lane));
+// v_writelane_b32 with a constant lane: lane L of v takes the
+// wavefront-uniform value val (an inline-constant lane index keeps the
+// instruction within gfx9's single scalar operand)
+template <int L>
+__device__ __forceinline__ uint32_t writelane(uint32_t v, uint32_t val) {
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(val), "i"(L));
   return v;
+}
+template <int U, int END, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (U < END) {
+    f(std::integral_constant<int, U>{});
+    static_for<U + 1, END>(f);
+  }
 }
 
 // OR over aligned groups of 8 / 16 lanes with DPP row permutes (no LDS):
@@ -257,23 +269,29 @@ __global__ void __launch_bounds__(256) gm_gen32_kernel(const GmState* sin, GmSta
   const bool live = s < count;
   Elem<G> el;
   el.load(live ? sin[s].xc[e] : 0, live ? sin[s].xp[e] : 0);
-  // the word of step u goes to lane u of each half: v_writelane from the
-  // ballot's two 32-bit halves
+  // the word of step u goes to lane u of each half of the wavefront: a
+  // full block of 32 steps writes the ballot halves with v_writelane, a
+  // ragged last block selects per lane
+  const bool upper = (threadIdx.x & 32) != 0;
   uint32_t keep = 0;
   for (uint64_t t0 = 0; t0 < n; t0 += 32) {
     const int m = (n - t0) < 32 ? (int)(n - t0) : 32;
-    auto one = [&](int u) {
-      el.maybe_switch();
-      const uint64_t mask = __ballot(el.step());
-      keep = writelane(keep, (uint32_t)mask, (uint32_t)u);
-      keep = writelane(keep, (uint32_t)(mask >> 32), (uint32_t)u + 32);
-    };
-    int u = 0;
-    for (; u + 2 <= m; u += 2) {   // two steps per trip: no register rotation
-      one(u);
-      one(u + 1);
+    if (m == 32) {
+      static_for<0, 32>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        el.maybe_switch();
+        const uint64_t mask = __ballot(el.step());
+        keep = writelane<u>(keep, (uint32_t)mask);
+        keep = writelane<u + 32>(keep, (uint32_t)(mask >> 32));
+      });
+    } else {
+      for (int u = 0; u < m; u++) {
+        el.maybe_switch();
+        const uint64_t mask = __ballot(el.step());
+        const uint32_t w = upper ? (uint32_t)(mask >> 32) : (uint32_t)mask;
+        keep = (u == li) ? w : keep;
+      }
     }
-    if (u < m) one(u);
     if (live && li < m) put<DT>(out, s * n + t0 + li, keep);
   }
   if (live) {
