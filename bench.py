@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--gens", type=str, default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dtype-sweep", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-tasks", type=int, default=20000)
     return ap.parse_args()
 
 
@@ -153,6 +155,10 @@ def main():
             extra[P.NAMES[g]] = r
         del big
 
+    del out, states
+    torch.cuda.empty_cache()
+    batched = None if args.no_batched else batched_vs_plain(ctx, args.batched_tasks, stream)
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(gens, S, N)
 
     line = {
@@ -175,10 +181,91 @@ def main():
         "roofline": roof,
         "per_generator": per_gen,
         "dtype_sweep": extra,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def batched_vs_plain(ctx, ntasks, stream):
+    """Many streams of mixed generators and uneven lengths (log-uniform in
+    [1e3, 1e7]) in f32: one autotuned persistent launch replayed from a HIP
+    graph, against plain per-stream launches timed on a sample of the tasks."""
+    import torch
+
+    from paper_1307_5869_amd import prand as P
+    from paper_1307_5869_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    gens, ids, lens = W.batched_tasks(count=ntasks)
+    total = int(lens.sum())
+    out = torch.empty(total, dtype=torch.float32, device=dev)
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    sb = [P.state_bytes(g) for g in range(P.NUM_GENERATORS)]
+    sin = {}
+    for g in range(P.NUM_GENERATORS):
+        sel = np.nonzero(gens == g)[0]
+        if sel.size == 0:
+            continue
+        st = torch.empty(sel.size * sb[g], dtype=torch.uint8, device=dev)
+        t_ids = torch.from_numpy(ids[sel].view(np.int64)).to(dev)
+        ctx.init_streams_dev(g, P.SEQ_DEFAULT, None, t_ids, sel.size, st, stream)
+        sin[g] = (sel, st)
+    sout = {g: torch.empty_like(v[1]) for g, v in sin.items()}
+    tasks = [None] * ntasks
+    for g, (sel, st) in sin.items():
+        base_in, base_out = st.data_ptr(), sout[g].data_ptr()
+        for j, k in enumerate(sel):
+            tasks[k] = (g, P.F32, int(lens[k]), base_in + j * sb[g], base_out + j * sb[g],
+                        out.data_ptr() + 4 * int(offs[k]))
+    torch.cuda.synchronize()
+    # tune on a sample of the mix, then run the whole batch
+    t0 = time.perf_counter()
+    best = P.autotune(ctx, tasks[:1500])
+    tune_s = time.perf_counter() - t0
+    b = P.Batch(ctx, tasks, best)
+    b.launch(stream)
+    torch.cuda.synchronize()
+    reps = 2
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        b.launch(stream)
+    z.record(stream)
+    z.synchronize()
+    ms = a.elapsed_time(z) / reps
+    tiles = b.tiles()
+    b.close()
+    # plain: one generate launch per stream (prand_generate_streams, count 1),
+    # over a random order of the tasks until about 10 s of GPU time have been
+    # spent; the output states are copies of the input states, advanced in place
+    order = np.random.default_rng(7).permutation(ntasks)
+    for g, (sel, st) in sin.items():
+        sout[g].copy_(st)
+    torch.cuda.synchronize()
+    plain_ms, done, plain_numbers = 0.0, 0, 0
+    while done < ntasks and plain_ms < 10e3:
+        chunk = order[done:done + 25]
+        a.record(stream)
+        for k in chunk:
+            g, _, n, _, pst, pout = tasks[k]
+            ctx.generate_streams(g, pst, 1, n, P.F32, pout, stream)
+        z.record(stream)
+        z.synchronize()
+        plain_ms += a.elapsed_time(z)
+        done += len(chunk)
+        plain_numbers += int(lens[chunk].sum())
+    del out
+    torch.cuda.empty_cache()
+    return {"tasks": ntasks, "numbers": total, "dtype": "f32", "tiles": tiles,
+            "config": {"waves_per_cu": best.waves_per_cu, "reg_section": best.reg_section,
+                       "gm_section": best.gm_section, "graph": bool(best.use_graph)},
+            "autotune_s": round(tune_s, 2), "batched_ms": round(ms, 3),
+            "batched_numbers_per_s": total / (ms * 1e-3),
+            "plain_sample_tasks": done, "plain_sample_numbers": plain_numbers,
+            "plain_ms": round(plain_ms, 3), "plain_numbers_per_s": plain_numbers / (plain_ms * 1e-3),
+            "speedup": (total / (ms * 1e-3)) / (plain_numbers / (plain_ms * 1e-3))}
 
 
 def cpu_baseline(gens, S, N):

@@ -164,6 +164,49 @@ int prand_generate(prand_ctx* ctx, int gen, void* h_state, int dtype, void* d_ou
 int prand_generate_streams(prand_ctx* ctx, int gen, void* d_states, uint32_t count,
                            uint64_t n_per_stream, int dtype, void* d_out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched persistent launch: many streams of uneven lengths and mixed
+ * generators and dtypes in one fused launch, replayed from a HIP graph.
+ * Each task is cut into sections that jump to their first output (the
+ * sectioning of "Multi-threaded generation"), grouped into per-wavefront
+ * tiles that a fixed grid of wavefronts pulls from a work queue.
+ * ------------------------------------------------------------------------ */
+typedef struct prand_task {
+  int32_t gen;           /* enum prand_gen */
+  int32_t dtype;         /* enum prand_dtype */
+  uint64_t n;            /* outputs */
+  const void* state_in;  /* device state blob (read only) */
+  void* state_out;       /* device state blob: state_in advanced by n.  No state_out may
+                            overlap any task's state_in; state_out blobs are distinct. */
+  void* out;             /* device array of n values of dtype (may be NULL when n = 0) */
+} prand_task;
+
+typedef struct prand_batch_config {
+  uint32_t waves_per_cu;   /* persistent wavefronts per compute unit (0: 16) */
+  uint32_t reg_section;    /* MRG32K3A/LFSR113 outputs per lane section, multiple of 32 (0: 2048) */
+  uint32_t gm_section;     /* GM/GQ outputs per element-group section (0: 4096) */
+  uint32_t use_graph;      /* 1: capture the launch in a HIP graph and replay it */
+} prand_batch_config;
+
+typedef struct prand_batch prand_batch;
+
+/* Plan a batch (tasks are read on the host; the device pointers they hold
+   must stay valid while the batch is launched).  cfg NULL: defaults. */
+int prand_batch_create(prand_ctx* ctx, const prand_task* h_tasks, uint32_t ntasks, const prand_batch_config* cfg,
+                       prand_batch** batch);
+/* Enqueue the batch on `stream` (a hipStream_t, NULL = default stream).
+   Launches of the same batch must not overlap each other. */
+int prand_batch_launch(prand_batch* batch, void* stream);
+/* Number of tiles (wavefront work items) the plan holds. */
+int prand_batch_tiles(const prand_batch* batch, uint32_t* ntiles);
+int prand_batch_destroy(prand_batch* batch);
+
+/* Time candidate configurations on these tasks (their outputs and output
+   states are overwritten) and return the fastest in *best.  When the
+   environment variable PRAND_TUNE_CACHE names a file, results are kept there
+   keyed by the device and a signature of the task mix, and reused.  Blocks. */
+int prand_batch_autotune(prand_ctx* ctx, const prand_task* h_tasks, uint32_t ntasks, prand_batch_config* best);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,36 +15,9 @@
 
 using namespace prand;
 
-struct prand_ctx {
-  int device = 0;
-  DeviceTables T;
-  bool mt_ready = false;
-  std::mutex mu;          // guards mt_ready and the host-call scratch
-  void* scratch = nullptr;
-  int last_hip = 0;
-};
-
 namespace {
 
 constexpr size_t kScratch = 64 * 1024;
-
-struct DeviceGuard {
-  int prev = -1;
-  hipError_t err = hipSuccess;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) err = hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
-int hipfail(prand_ctx* c, hipError_t e) {
-  if (c) c->last_hip = (int)e;
-  return PRAND_EHIP;
-}
 
 bool valid_gen(int g) { return g >= 0 && g < PRAND_NUM_GENERATORS; }
 bool valid_dtype(int d) { return d >= PRAND_U32 && d <= PRAND_F64; }
@@ -224,6 +197,8 @@ int prand_ctx_create(prand_ctx** out, int hip_device) {
   prand_ctx* c = new (std::nothrow) prand_ctx;
   if (!c) return PRAND_ENOMEM;
   c->device = hip_device;
+  c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  std::strncpy(c->arch, prop.gcnArchName, sizeof(c->arch) - 1);
   HostTables* H = new (std::nothrow) HostTables;
   if (!H) { delete c; return PRAND_ENOMEM; }
   build_mrg_ladder(H->mrg);

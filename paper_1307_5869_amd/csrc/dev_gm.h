@@ -1,0 +1,534 @@
+// GM19, GM29, GM31, GM55, GM61, GQ58.1, GQ58.3, GQ58.4 on gfx950: ensembles of
+// s torus maps x_i^(n) = k x_i^(n-1) - q x_i^(n-2) mod g (paper, equation
+// rec1; k, q, g, v of Table 2).  Each element contributes a v-bit digit
+// floor(2^v x / g) per step; digits are packed element 0 first, most
+// significant bit first, into 32-bit words (GQ58.3: 36 bits per step, 9 words
+// per 8 steps).
+//
+// One lane per element: v = 1 ensembles (s = 32) take half a wavefront per
+// stream and pack a word with one ballot; v = 4 ensembles (s = 8) take 8
+// lanes and OR their nibbles with three xor-shuffles; GQ58.3 (s = 12) takes 16
+// lanes (the OR-reductions use DPP row permutes).  Each lane keeps the word
+// of one step of every 32 (8), so a flush writes consecutive words from
+// consecutive lanes.
+//
+// Arithmetic is exact: special-form reductions (2^19-1, 2^29-3, 2^61-1,
+// 2^51-129) in integers, or FP64 where all values stay below 2^53 (GM31,
+// GQ58).  For g = p 2^t (GM55: t = 4, GQ58: t = 29) the even k and q kill the
+// 2-adic part within n0 steps; from then on x = 2^t y with y following the
+// same recurrence mod p and the digit equal to floor(2^v y / p), so the
+// kernel runs exact mod-g steps only until every element of the wavefront has
+// collapsed and then switches to the mod-p recurrence.
+// GM/GQ device code shared by the GM/GQ kernels and the batched kernel.
+#pragma once
+
+#include <type_traits>
+
+#include "prand_impl.h"
+
+namespace prand {
+namespace gm {
+
+typedef unsigned __int128 u128;
+
+// ------------------------------------------------------------ per generator
+template <int G>
+struct Eng;
+
+// GM19: g = 2^19 - 1, k = 15, q = 28
+template <>
+struct Eng<0> {
+  static constexpr bool kComposite = false;
+  using F = uint32_t;
+  static constexpr uint32_t g = 524287u;
+  __device__ static F to_fast(uint64_t x) { return (F)x; }
+  __device__ static uint64_t from_fast(F y) { return y; }
+  __device__ static F step(F xc, F xp) {
+    // operands < 2^19: 24-bit multiplies (full rate)
+    uint32_t t = __umul24(15u, xc) + __umul24(28u, g - xp);   // < 43 * 2^19
+    t = (t & g) + (t >> 19);
+    return min(t, t - g);
+  }
+  __device__ static uint32_t digit(F x) { return x >= (g + 1) / 2; }
+};
+
+// GM29: g = 2^29 - 3, k = 4, q = 2
+template <>
+struct Eng<1> {
+  static constexpr bool kComposite = false;
+  using F = uint32_t;
+  static constexpr uint32_t g = 536870909u;
+  __device__ static F to_fast(uint64_t x) { return (F)x; }
+  __device__ static uint64_t from_fast(F y) { return y; }
+  __device__ static F step(F xc, F xp) {
+    uint32_t t = (xc << 2) + ((g - xp) << 1);   // < 6 * 2^29
+    t = (t & 0x1FFFFFFFu) + 3u * (t >> 29);
+    return min(t, t - g);
+  }
+  __device__ static uint32_t digit(F x) { return x >= (g + 1) / 2; }
+};
+
+// GM31: g = 2^31 - 1, k = 11, q = 14; exact in FP64 (|k x - q x'| < 2^36)
+template <>
+struct Eng<2> {
+  static constexpr bool kComposite = false;
+  using F = double;
+  __device__ static F to_fast(uint64_t x) { return (double)x; }
+  __device__ static uint64_t from_fast(F y) { return (uint64_t)y; }
+  __device__ static F step(F xc, F xp) {
+    const double g = 2147483647.0, inv = 1.0 / 2147483647.0;
+    const double t = fma(11.0, xc, -14.0 * xp);
+    const double k = floor(t * inv);
+    double r = fma(-k, g, t);
+    r = (r < 0.0) ? r + g : r;
+    return (r >= g) ? r - g : r;
+  }
+  __device__ static uint32_t digit(F x) { return x >= 1073741824.0; }
+};
+
+// GM61: g = 2^61 - 1, k = 24, q = 74
+template <>
+struct Eng<4> {
+  static constexpr bool kComposite = false;
+  using F = uint64_t;
+  static constexpr uint64_t g = 2305843009213693951ull;
+  __device__ static F to_fast(uint64_t x) { return x; }
+  __device__ static uint64_t from_fast(F y) { return y; }
+  __device__ static F step(F xc, F xp) {
+    const u128 t = (u128)24u * xc + (u128)74u * (g - xp);   // < 2^68
+    const uint64_t lo = (uint64_t)t, hi = (uint64_t)(t >> 64);
+    uint64_t r = (lo & g) + ((lo >> 61) | (hi << 3));
+    return r >= g ? r - g : r;
+  }
+  __device__ static uint32_t digit(F x) { return x >= (1ull << 60); }
+};
+
+// GM55: g = 2^4 p, p = 2^51 - 129, k = 256, q = 176, v = 4
+template <>
+struct Eng<3> {
+  static constexpr bool kComposite = true;
+  static constexpr int t = 4, v = 4;
+  static constexpr uint64_t p = 2251799813685119ull;
+  static constexpr uint64_t g = p << 4;
+  using F = uint64_t;
+  __device__ static uint64_t modp_fold(uint64_t h) {   // h < 2^60
+    h = (h & ((1ull << 51) - 1)) + 129ull * (h >> 51);
+    return h >= p ? h - p : h;
+  }
+  __device__ static bool collapsed(uint64_t x) { return (x & 15u) == 0; }
+  __device__ static uint64_t slow_step(uint64_t xc, uint64_t xp) {
+    const uint64_t s = (xc << 8) + 176ull * (g - xp);   // < 2^64
+    return (modp_fold(s >> 4) << 4) | (s & 15u);
+  }
+  __device__ static uint32_t slow_digit(uint64_t x) {  // floor(16 x / 16 p) = floor(x / p)
+    const uint64_t d0 = x >> 51;
+    return (uint32_t)(d0 + ((d0 + 1) * p <= x));
+  }
+  __device__ static F to_fast(uint64_t x) { return x >> 4; }
+  __device__ static uint64_t from_fast(F y) { return y << 4; }
+  __device__ static F step(F yc, F yp) {
+    const uint64_t s = (yc << 8) + 176ull * (p - yp);   // < 2^60
+    return modp_fold(s);
+  }
+  __device__ static uint32_t digit(F y) {
+    const uint64_t num = y << 4, d0 = num >> 51;
+    return (uint32_t)(d0 + ((d0 + 1) * p <= num));
+  }
+};
+
+// GQ58.x: g = 2^29 p, p = 2^29 - 3, k = 8, q = 48, v = 1, 3, 4
+template <int V>
+struct EngGQ {
+  static constexpr bool kComposite = true;
+  static constexpr int t = 29, v = V;
+  static constexpr uint64_t p = 536870909ull;
+  static constexpr uint64_t g = p << 29;
+  using F = double;
+  __device__ static bool collapsed(uint64_t x) { return (x & 0x1FFFFFFFull) == 0; }
+  __device__ static uint64_t slow_step(uint64_t xc, uint64_t xp) {
+    const uint64_t s = (xc << 3) + 48ull * (g - xp);   // < 2^64
+    uint64_t h = s >> 29;                               // < 2^35
+    h = (h & 0x1FFFFFFFull) + 3ull * (h >> 29);
+    h = h >= p ? h - p : h;
+    return (h << 29) | (s & 0x1FFFFFFFull);
+  }
+  __device__ static uint32_t slow_digit(uint64_t x) {  // floor(((2^v x) >> 29) / p)
+    const uint64_t num = (x << V) >> 29, d0 = num >> 29;
+    return (uint32_t)(d0 + ((d0 + 1) * p <= num));
+  }
+  __device__ static F to_fast(uint64_t x) { return (double)(x >> 29); }
+  __device__ static uint64_t from_fast(F y) { return ((uint64_t)y) << 29; }
+  __device__ static F step(F yc, F yp) {
+    const double pd = 536870909.0, inv = 1.0 / 536870909.0;
+    const double s = fma(8.0, yc, -48.0 * yp);
+    const double k = floor(s * inv);
+    double r = fma(-k, pd, s);
+    r = (r < 0.0) ? r + pd : r;
+    return (r >= pd) ? r - pd : r;
+  }
+  __device__ static uint32_t digit(F y) {
+    const double pd = 536870909.0;
+    if (V == 1) return y >= 268435455.0;   // 2y >= p
+    const double num = y * (double)(1 << V);
+    double d = floor(num * (1.0 / 536870909.0));
+    d = (d * pd > num) ? d - 1.0 : d;
+    d = ((d + 1.0) * pd <= num) ? d + 1.0 : d;
+    return (uint32_t)d;
+  }
+};
+template <> struct Eng<5> : EngGQ<1> {};
+template <> struct Eng<6> : EngGQ<3> {};
+template <> struct Eng<7> : EngGQ<4> {};
+
+// Per-element runner: slow exact-mod-g steps until the whole wavefront has
+// collapsed (composite moduli), then the fast recurrence.  The mode only
+// switches between steps and is wavefront-uniform.
+template <int G>
+struct Elem {
+  using E = Eng<G>;
+  typename E::F fc, fp;   // fast representation
+  uint64_t sc, sp;        // exact mod-g values (slow mode)
+  bool fast;
+  __device__ void load(uint64_t xc, uint64_t xp) {
+    if constexpr (E::kComposite) {
+      sc = xc; sp = xp; fast = false;
+    } else {
+      fc = E::to_fast(xc); fp = E::to_fast(xp); fast = true;
+    }
+  }
+  __device__ void maybe_switch() {
+    if constexpr (E::kComposite) {
+      if (!fast) {
+        const bool mine = E::collapsed(sc) && E::collapsed(sp);
+        if (__all(mine)) {
+          fc = E::to_fast(sc); fp = E::to_fast(sp); fast = true;
+        }
+      }
+    }
+  }
+  __device__ uint32_t step() {
+    if constexpr (E::kComposite) {
+      if (!fast) {
+        const uint64_t nx = E::slow_step(sc, sp);
+        sp = sc; sc = nx;
+        return E::slow_digit(nx);
+      }
+    }
+    const typename E::F nx = E::step(fc, fp);
+    fp = fc; fc = nx;
+    return E::digit(nx);
+  }
+  __device__ void get(uint64_t& xc, uint64_t& xp) const {
+    if (fast) { xc = E::from_fast(fc); xp = E::from_fast(fp); }
+    else { xc = sc; xp = sp; }
+  }
+};
+
+template <int DT>
+__device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
+  if (DT == PRAND_U32) ((uint32_t*)out)[i] = w;
+  else if (DT == PRAND_F32) ((float*)out)[i] = (float)(w >> 8) * 0x1p-24f;
+  else ((double*)out)[i] = (double)w * 0x1p-32;
+}
+
+// v_writelane_b32 with a constant lane: lane L of v takes the
+// wavefront-uniform value val (an inline-constant lane index keeps the
+// instruction within gfx9's single scalar operand)
+template <int L>
+__device__ __forceinline__ uint32_t writelane(uint32_t v, uint32_t val) {
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(val), "i"(L));
+  return v;
+}
+template <int U, int END, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (U < END) {
+    f(std::integral_constant<int, U>{});
+    static_for<U + 1, END>(f);
+  }
+}
+
+// OR over aligned groups of 8 / 16 lanes with DPP row permutes (no LDS):
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror (lane i of
+// an 8-lane half reads lane 7-i) and row_mirror (lane i of a row reads 15-i)
+__device__ __forceinline__ uint32_t dpp_or8(uint32_t w) {
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0xB1, 0xF, 0xF, false);
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x4E, 0xF, 0xF, false);
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x141, 0xF, 0xF, false);
+  return w;
+}
+__device__ __forceinline__ uint32_t dpp_or16(uint32_t w) {
+  w = dpp_or8(w);
+  return w | (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x140, 0xF, 0xF, false);
+}
+
+// -------------------------------------------------------------- jumping
+template <int G>
+__device__ __forceinline__ uint64_t fold_special(u128 x, int e, uint64_t c, uint64_t p) {
+  const uint64_t mask = (1ull << e) - 1;
+  for (int i = 0; i < 3; i++) x = (x & mask) + (u128)c * (uint64_t)(x >> e);
+  uint64_t r = (uint64_t)x;
+  r = r >= p ? r - p : r;
+  r = r >= p ? r - p : r;
+  return r;
+}
+// prime part p = 2^e - c of each generator's modulus
+__device__ __forceinline__ void prime_form(int G, int& e, uint64_t& c) {
+  switch (G) {
+    case 0: e = 19; c = 1; break;
+    case 1: e = 29; c = 3; break;
+    case 2: e = 31; c = 1; break;
+    case 3: e = 51; c = 129; break;
+    case 4: e = 61; c = 1; break;
+    default: e = 29; c = 3; break;
+  }
+}
+
+// Jump one element (xc, xp) = (x^(n), x^(n-1)) ahead by N ensemble steps
+// (little-endian limbs, N[kMaxLimbs] must be 0 on entry to the ladder part):
+// one ladder matrix M^(2^b) mod p per set bit b.  Composite moduli first
+// collapse (n0 exact steps) unless the element already has, then jump x/2^t
+// mod p; distances below n0 are taken as exact steps.
+template <int G>
+__device__ __forceinline__ void jump_steps_elem(uint64_t& xc, uint64_t& xp, uint64_t* N,
+                                                const uint64_t* __restrict__ ladder) {
+  using E = Eng<G>;
+  int pe;
+  uint64_t pc;
+  prime_form(G, pe, pc);
+  const uint64_t p = kGmParams[G].p;
+  const uint64_t* L = ladder + (size_t)G * kLadder * 4;
+  if constexpr (E::kComposite) {
+    bool small = true;
+    for (int l = 1; l <= kMaxLimbs; l++) small = small && N[l] == 0;
+    const uint64_t n0 = (uint64_t)kGmParams[G].n0;
+    if (small && N[0] < n0) {
+      for (uint64_t i = 0; i < N[0]; i++) { const uint64_t nx = E::slow_step(xc, xp); xp = xc; xc = nx; }
+      return;
+    }
+    if (!(E::collapsed(xc) && E::collapsed(xp))) {
+      for (uint64_t i = 0; i < n0; i++) { const uint64_t nx = E::slow_step(xc, xp); xp = xc; xc = nx; }
+      uint64_t borrow = n0;
+      for (int l = 0; l <= kMaxLimbs && borrow; l++) {
+        const uint64_t old = N[l];
+        N[l] = old - borrow;
+        borrow = old < borrow ? 1 : 0;
+      }
+    }
+    uint64_t yc = xc >> E::t, yp = xp >> E::t;
+    for (int l = 0; l < kMaxLimbs; l++) {
+      uint64_t wd = N[l];
+      while (wd) {
+        const int b = __builtin_ctzll(wd) + 64 * l;
+        wd &= wd - 1;
+        const uint64_t* M = L + (size_t)b * 4;
+        const uint64_t nc = fold_special<G>((u128)M[0] * yc + (u128)M[1] * yp, pe, pc, p);
+        const uint64_t np = fold_special<G>((u128)M[2] * yc + (u128)M[3] * yp, pe, pc, p);
+        yc = nc; yp = np;
+      }
+    }
+    xc = yc << E::t;
+    xp = yp << E::t;
+  } else {
+    for (int l = 0; l < kMaxLimbs; l++) {
+      uint64_t wd = N[l];
+      while (wd) {
+        const int b = __builtin_ctzll(wd) + 64 * l;
+        wd &= wd - 1;
+        const uint64_t* M = L + (size_t)b * 4;
+        const uint64_t nc = fold_special<G>((u128)M[0] * xc + (u128)M[1] * xp, pe, pc, p);
+        const uint64_t np = fold_special<G>((u128)M[2] * xc + (u128)M[3] * xp, pe, pc, p);
+        xc = nc; xp = np;
+      }
+    }
+  }
+}
+
+// GQ58.3: a distance of N words from word offset `off` inside an 8-step
+// block: (off + N) = 9 B + rem; N becomes 8 B ensemble steps, *new_off = rem.
+__device__ __forceinline__ void gq3_words_to_steps(uint64_t* N, uint32_t off, uint32_t* new_off) {
+  uint64_t carry = off;
+  for (int l = 0; l <= kMaxLimbs && carry; l++) {
+    const uint64_t old = N[l];
+    N[l] = old + carry;
+    carry = N[l] < old ? 1 : 0;
+  }
+  uint64_t r = 0;   // divide by 9 in 32-bit pieces
+  for (int l = kMaxLimbs; l >= 0; l--) {
+    const uint64_t hi = (r << 32) | (N[l] >> 32);
+    const uint64_t qh = hi / 9;
+    r = hi % 9;
+    const uint64_t lo = (r << 32) | (N[l] & 0xFFFFFFFFull);
+    const uint64_t ql = lo / 9;
+    r = lo % 9;
+    N[l] = (qh << 32) | ql;
+  }
+  *new_off = (uint32_t)r;
+  uint64_t c3 = 0;   // times 8
+  for (int l = 0; l <= kMaxLimbs; l++) {
+    const uint64_t v = N[l];
+    N[l] = (v << 3) | c3;
+    c3 = v >> 61;
+  }
+}
+
+// Load element e of *in and move it `start` outputs ahead (start < 2^64).
+// Returns the word offset inside the GQ58.3 block (0 for the others).
+template <int G>
+__device__ __forceinline__ uint32_t load_at(const GmState* in, int e, uint64_t start, uint64_t& xc, uint64_t& xp,
+                                            const uint64_t* __restrict__ ladder) {
+  xc = in->xc[e];
+  xp = in->xp[e];
+  uint32_t off = (G == 6) ? in->off : 0;
+  if (start) {
+    uint64_t N[kMaxLimbs + 1];
+    for (int l = 0; l <= kMaxLimbs; l++) N[l] = 0;
+    N[0] = start;
+    if (G == 6) gq3_words_to_steps(N, off, &off);
+    jump_steps_elem<G>(xc, xp, N, ladder);
+  }
+  return off;
+}
+
+// ---------------------------------------------- v = 1, s = 32: ballots
+// Each half-wavefront is one section: element e = 31 - (lane & 31) of state
+// *in moved `start` outputs ahead, n outputs to out, advanced state to *sout
+// (none when sout is null).
+// n must be the same for both halves (the ballot spans the wavefront); a dead
+// half (live = false) follows along without loads or stores.
+template <int G, int DT>
+__device__ __forceinline__ void gen32_wave(bool live, const GmState* in, uint64_t start, uint64_t n, void* out,
+                                           GmState* sout, const uint64_t* __restrict__ ladder) {
+  const int li = threadIdx.x & 31;        // bit position of this element's digit
+  const int e = 31 - li;                  // element index
+  uint64_t xc = 0, xp = 0;
+  if (live) load_at<G>(in, e, start, xc, xp, ladder);
+  Elem<G> el;
+  el.load(xc, xp);
+  // the word of step u goes to lane u of each half of the wavefront: a
+  // full block of 32 steps writes the ballot halves with v_writelane, a
+  // ragged last block selects per lane
+  const bool upper = (threadIdx.x & 32) != 0;
+  uint32_t keep = 0;
+  for (uint64_t t0 = 0; t0 < n; t0 += 32) {
+    const int m = (n - t0) < 32 ? (int)(n - t0) : 32;
+    if (m == 32) {
+      static_for<0, 32>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        el.maybe_switch();
+        const uint64_t mask = __ballot(el.step());
+        keep = writelane<u>(keep, (uint32_t)mask);
+        keep = writelane<u + 32>(keep, (uint32_t)(mask >> 32));
+      });
+    } else {
+      for (int u = 0; u < m; u++) {
+        el.maybe_switch();
+        const uint64_t mask = __ballot(el.step());
+        const uint32_t w = upper ? (uint32_t)(mask >> 32) : (uint32_t)mask;
+        keep = (u == li) ? w : keep;
+      }
+    }
+    if (live && li < m) put<DT>(out, t0 + li, keep);
+  }
+  if (live && sout) {
+    el.get(xc, xp);
+    sout->xc[e] = xc;
+    sout->xp[e] = xp;
+    if (li == 0) { sout->off = 0; sout->pad = 0; }
+  }
+}
+
+// ---------------------------------------------- v = 4, s = 8: nibbles
+// Each aligned group of 8 lanes is one section (element e = lane & 7).
+template <int G, int DT>
+__device__ __forceinline__ void gen8_wave(bool live, const GmState* in, uint64_t start, uint64_t n, void* out,
+                                          GmState* sout, const uint64_t* __restrict__ ladder) {
+  const int e = threadIdx.x & 7;
+  uint64_t xc = 0, xp = 0;
+  if (live) load_at<G>(in, e, start, xc, xp, ladder);
+  Elem<G> el;
+  el.load(xc, xp);
+  const int shift = 28 - 4 * e;
+  uint32_t keep = 0;
+  for (uint64_t t0 = 0; t0 < n; t0 += 8) {
+    const int m = (n - t0) < 8 ? (int)(n - t0) : 8;
+    auto one = [&](int u) {
+      el.maybe_switch();
+      const uint32_t w = dpp_or8(el.step() << shift);
+      keep = (u == e) ? w : keep;
+    };
+    int u = 0;
+    for (; u + 2 <= m; u += 2) {
+      one(u);
+      one(u + 1);
+    }
+    if (u < m) one(u);
+    if (live && e < m) put<DT>(out, t0 + e, keep);
+  }
+  if (live && sout) {
+    el.get(xc, xp);
+    sout->xc[e] = xc;
+    sout->xp[e] = xp;
+    if (e == 0) { sout->off = 0; sout->pad = 0; }
+  }
+}
+
+// ---------------------------- GQ58.3: v = 3, s = 12, 16 lanes per section
+// 8 steps of 36 bits = 9 words.  The state sits at a block boundary with
+// `off` words of the block consumed; a section emits block words from off on
+// and keeps the state at the start of the last, partially used block.
+// Groups of one wavefront may run different numbers of blocks.
+template <int DT>
+__device__ __forceinline__ void gq3_wave(bool live, const GmState* in, uint64_t start, uint64_t n, void* out,
+                                         GmState* sout, const uint64_t* __restrict__ ladder) {
+  constexpr int G = 6;
+  const int e = threadIdx.x & 15;
+  const int gbase = threadIdx.x & 48;     // first lane of this group within the wavefront
+  const bool elem = e < 12;
+  uint64_t xc = 0, xp = 0;
+  uint32_t off0 = 0;
+  if (live) off0 = load_at<G>(in, elem ? e : 0, start, xc, xp, ladder);
+  if (!elem) xc = xp = 0;
+  Elem<G> el;
+  el.load(xc, xp);
+  const uint64_t total = live ? off0 + n : 0;
+  const uint64_t full = total / 9;
+  const uint32_t rem = (uint32_t)(total % 9);
+  const uint64_t nb = full + (rem ? 1 : 0);
+  Elem<G> saved = el;
+  const int shift = elem ? 33 - 3 * e : 0;
+  for (uint64_t b = 0; b < nb; b++) {
+    el.maybe_switch();
+    saved = el;
+    uint64_t keep = 0;
+    for (int u = 0; u < 8; u++) {
+      const uint32_t d = el.step();
+      uint64_t c = elem ? ((uint64_t)d << shift) : 0;
+      const uint32_t lo = dpp_or16((uint32_t)c), hi = dpp_or16((uint32_t)(c >> 32));
+      c = ((uint64_t)hi << 32) | lo;
+      keep = (u == e) ? c : keep;
+    }
+    // word w (lane w < 9): bits [32w, 32w+32) of the 288-bit block
+    const int w = e < 9 ? e : 8;
+    const int ci = (32 * w) / 36, o = 32 * w - 36 * ci;
+    const uint32_t alo = __shfl((uint32_t)keep, gbase + ci);
+    const uint32_t ahi = __shfl((uint32_t)(keep >> 32), gbase + ci);
+    const int cj = ci + 1 < 8 ? ci + 1 : 7;
+    const uint32_t blo = __shfl((uint32_t)keep, gbase + cj);
+    const uint32_t bhi = __shfl((uint32_t)(keep >> 32), gbase + cj);
+    const uint64_t A = ((uint64_t)ahi << 32) | alo;
+    const uint64_t B = (ci + 1 < 8) ? (((uint64_t)bhi << 32) | blo) : 0;
+    const int k = 40 - o;   // the word is (A:B >> k) & (2^32 - 1) of the 72-bit A:B
+    const uint32_t word = (k > 36) ? (uint32_t)(A >> (k - 36)) : (uint32_t)((A << (36 - k)) | (B >> k));
+    const int64_t q = (int64_t)(b * 9 + w) - (int64_t)off0;
+    if (live && e < 9 && q >= 0 && (uint64_t)q < n) put<DT>(out, (uint64_t)q, word);
+  }
+  if (live && sout && elem) {
+    if (rem && nb > 0) saved.get(xc, xp); else el.get(xc, xp);
+    sout->xc[e] = xc;
+    sout->xp[e] = xp;
+  }
+  if (live && sout && e == 0) { sout->off = rem; sout->pad = 0; }
+}
+
+}  // namespace gm
+}  // namespace prand

@@ -1,0 +1,82 @@
+// MT19937 device code shared by the MT19937 kernels and the batched kernel.
+#pragma once
+
+#include "prand_impl.h"
+
+namespace prand {
+namespace mt {
+
+constexpr uint32_t kUpper = 0x80000000u;
+constexpr uint32_t kLower = 0x7FFFFFFFu;
+constexpr uint32_t kMatA = 0x9908B0DFu;
+
+__device__ __forceinline__ uint32_t temper(uint32_t y) {
+  y ^= y >> 11;
+  y ^= (y << 7) & 0x9D2C5680u;
+  y ^= (y << 15) & 0xEFC60000u;
+  return y ^ (y >> 18);
+}
+// x_{j+624} from x_j (upper bit), x_{j+1} (lower bits), x_{j+397}
+__device__ __forceinline__ uint32_t recur(uint32_t xj, uint32_t xj1, uint32_t xjm) {
+  const uint32_t y = (xj & kUpper) | (xj1 & kLower);
+  return xjm ^ (y >> 1) ^ ((xj1 & 1u) ? kMatA : 0u);
+}
+
+template <int DT>
+__device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
+  if (DT == PRAND_U32) ((uint32_t*)out)[i] = w;
+  else if (DT == PRAND_F32) ((float*)out)[i] = (float)(w >> 8) * 0x1p-24f;
+  else ((double*)out)[i] = (double)w * 0x1p-32;
+}
+
+// One wavefront generates n outputs of one stream: state *in (copied into
+// the LDS block mt[624]), outputs at out, advanced state to *sout (may be
+// the same object as *in).  A twist renews the block in three dependency
+// phases (words 0..226 read old words 397..623; 227..453 read words renewed
+// in phase one; 454..623 read phase two and word 0), each parallel across the
+// lanes; renewed words are tempered and stored straight from registers.  The
+// LDS block is private to the wavefront (wavefront-level ordering only).
+template <int DT>
+__device__ __forceinline__ void gen_wave(uint32_t* mt, const MtState* in, MtState* sout, uint64_t n, void* out) {
+  const int lane = threadIdx.x & 63;
+  for (int i = lane; i < 624; i += 64) mt[i] = in->mt[i];
+  uint32_t idx = in->idx < 624u ? in->idx : 624u;   // an index past the block means "block used up"
+  wave_lds_sync();
+  // rest of the current block
+  const uint64_t first = (uint64_t)(624 - idx) < n ? (uint64_t)(624 - idx) : n;
+  for (uint32_t i = lane; i < first; i += 64) put<DT>(out, i, temper(mt[idx + i]));
+  uint64_t pos = first;
+  idx += (uint32_t)first;
+  while (pos < n) {
+    const uint64_t left = n - pos;
+    const int want = left < 624 ? (int)left : 624;
+    for (int j = lane; j < 227; j += 64) {
+      const uint32_t v = recur(mt[j], mt[j + 1], mt[j + 397]);
+      mt[j] = v;
+      if (j < want) put<DT>(out, pos + j, temper(v));
+    }
+    wave_lds_sync();
+    for (int j = 227 + lane; j < 454; j += 64) {
+      const uint32_t v = recur(mt[j], mt[j + 1], mt[j - 227]);
+      mt[j] = v;
+      if (j < want) put<DT>(out, pos + j, temper(v));
+    }
+    wave_lds_sync();
+    for (int j = 454 + lane; j < 624; j += 64) {
+      const uint32_t v = recur(mt[j], mt[j == 623 ? 0 : j + 1], mt[j - 227]);
+      mt[j] = v;
+      if (j < want) put<DT>(out, pos + j, temper(v));
+    }
+    wave_lds_sync();
+    pos += want;
+    idx = want;
+  }
+  for (int i = lane; i < 624; i += 64) sout->mt[i] = mt[i];
+  if (lane == 0) {
+    sout->idx = idx;
+    sout->pad[0] = sout->pad[1] = sout->pad[2] = 0;
+  }
+}
+
+}  // namespace mt
+}  // namespace prand

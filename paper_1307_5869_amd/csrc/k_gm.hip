@@ -19,417 +19,48 @@
 // same recurrence mod p and the digit equal to floor(2^v y / p), so the
 // kernel runs exact mod-g steps only until every element of the wavefront has
 // collapsed and then switches to the mod-p recurrence.
-#include <type_traits>
-
-#include "prand_impl.h"
+#include "dev_gm.h"
 
 namespace prand {
 namespace {
 
-typedef unsigned __int128 u128;
+using namespace gm;
 
-// ------------------------------------------------------------ per generator
-template <int G>
-struct Eng;
+template <int G, int DT>
+__global__ void __launch_bounds__(256) gm_gen32_kernel(const GmState* sin, GmState* sout, uint32_t count, uint64_t n,
+                                                       void* __restrict__ out) {
+  const uint64_t s = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+  const bool live = s < count;
+  constexpr int es = (DT == PRAND_F64) ? 8 : 4;
+  gen32_wave<G, DT>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
+}
 
-// GM19: g = 2^19 - 1, k = 15, q = 28
-template <>
-struct Eng<0> {
-  static constexpr bool kComposite = false;
-  using F = uint32_t;
-  static constexpr uint32_t g = 524287u;
-  __device__ static F to_fast(uint64_t x) { return (F)x; }
-  __device__ static uint64_t from_fast(F y) { return y; }
-  __device__ static F step(F xc, F xp) {
-    // operands < 2^19: 24-bit multiplies (full rate)
-    uint32_t t = __umul24(15u, xc) + __umul24(28u, g - xp);   // < 43 * 2^19
-    t = (t & g) + (t >> 19);
-    return min(t, t - g);
-  }
-  __device__ static uint32_t digit(F x) { return x >= (g + 1) / 2; }
-};
-
-// GM29: g = 2^29 - 3, k = 4, q = 2
-template <>
-struct Eng<1> {
-  static constexpr bool kComposite = false;
-  using F = uint32_t;
-  static constexpr uint32_t g = 536870909u;
-  __device__ static F to_fast(uint64_t x) { return (F)x; }
-  __device__ static uint64_t from_fast(F y) { return y; }
-  __device__ static F step(F xc, F xp) {
-    uint32_t t = (xc << 2) + ((g - xp) << 1);   // < 6 * 2^29
-    t = (t & 0x1FFFFFFFu) + 3u * (t >> 29);
-    return min(t, t - g);
-  }
-  __device__ static uint32_t digit(F x) { return x >= (g + 1) / 2; }
-};
-
-// GM31: g = 2^31 - 1, k = 11, q = 14; exact in FP64 (|k x - q x'| < 2^36)
-template <>
-struct Eng<2> {
-  static constexpr bool kComposite = false;
-  using F = double;
-  __device__ static F to_fast(uint64_t x) { return (double)x; }
-  __device__ static uint64_t from_fast(F y) { return (uint64_t)y; }
-  __device__ static F step(F xc, F xp) {
-    const double g = 2147483647.0, inv = 1.0 / 2147483647.0;
-    const double t = fma(11.0, xc, -14.0 * xp);
-    const double k = floor(t * inv);
-    double r = fma(-k, g, t);
-    r = (r < 0.0) ? r + g : r;
-    return (r >= g) ? r - g : r;
-  }
-  __device__ static uint32_t digit(F x) { return x >= 1073741824.0; }
-};
-
-// GM61: g = 2^61 - 1, k = 24, q = 74
-template <>
-struct Eng<4> {
-  static constexpr bool kComposite = false;
-  using F = uint64_t;
-  static constexpr uint64_t g = 2305843009213693951ull;
-  __device__ static F to_fast(uint64_t x) { return x; }
-  __device__ static uint64_t from_fast(F y) { return y; }
-  __device__ static F step(F xc, F xp) {
-    const u128 t = (u128)24u * xc + (u128)74u * (g - xp);   // < 2^68
-    const uint64_t lo = (uint64_t)t, hi = (uint64_t)(t >> 64);
-    uint64_t r = (lo & g) + ((lo >> 61) | (hi << 3));
-    return r >= g ? r - g : r;
-  }
-  __device__ static uint32_t digit(F x) { return x >= (1ull << 60); }
-};
-
-// GM55: g = 2^4 p, p = 2^51 - 129, k = 256, q = 176, v = 4
-template <>
-struct Eng<3> {
-  static constexpr bool kComposite = true;
-  static constexpr int t = 4, v = 4;
-  static constexpr uint64_t p = 2251799813685119ull;
-  static constexpr uint64_t g = p << 4;
-  using F = uint64_t;
-  __device__ static uint64_t modp_fold(uint64_t h) {   // h < 2^60
-    h = (h & ((1ull << 51) - 1)) + 129ull * (h >> 51);
-    return h >= p ? h - p : h;
-  }
-  __device__ static bool collapsed(uint64_t x) { return (x & 15u) == 0; }
-  __device__ static uint64_t slow_step(uint64_t xc, uint64_t xp) {
-    const uint64_t s = (xc << 8) + 176ull * (g - xp);   // < 2^64
-    return (modp_fold(s >> 4) << 4) | (s & 15u);
-  }
-  __device__ static uint32_t slow_digit(uint64_t x) {  // floor(16 x / 16 p) = floor(x / p)
-    const uint64_t d0 = x >> 51;
-    return (uint32_t)(d0 + ((d0 + 1) * p <= x));
-  }
-  __device__ static F to_fast(uint64_t x) { return x >> 4; }
-  __device__ static uint64_t from_fast(F y) { return y << 4; }
-  __device__ static F step(F yc, F yp) {
-    const uint64_t s = (yc << 8) + 176ull * (p - yp);   // < 2^60
-    return modp_fold(s);
-  }
-  __device__ static uint32_t digit(F y) {
-    const uint64_t num = y << 4, d0 = num >> 51;
-    return (uint32_t)(d0 + ((d0 + 1) * p <= num));
-  }
-};
-
-// GQ58.x: g = 2^29 p, p = 2^29 - 3, k = 8, q = 48, v = 1, 3, 4
-template <int V>
-struct EngGQ {
-  static constexpr bool kComposite = true;
-  static constexpr int t = 29, v = V;
-  static constexpr uint64_t p = 536870909ull;
-  static constexpr uint64_t g = p << 29;
-  using F = double;
-  __device__ static bool collapsed(uint64_t x) { return (x & 0x1FFFFFFFull) == 0; }
-  __device__ static uint64_t slow_step(uint64_t xc, uint64_t xp) {
-    const uint64_t s = (xc << 3) + 48ull * (g - xp);   // < 2^64
-    uint64_t h = s >> 29;                               // < 2^35
-    h = (h & 0x1FFFFFFFull) + 3ull * (h >> 29);
-    h = h >= p ? h - p : h;
-    return (h << 29) | (s & 0x1FFFFFFFull);
-  }
-  __device__ static uint32_t slow_digit(uint64_t x) {  // floor(((2^v x) >> 29) / p)
-    const uint64_t num = (x << V) >> 29, d0 = num >> 29;
-    return (uint32_t)(d0 + ((d0 + 1) * p <= num));
-  }
-  __device__ static F to_fast(uint64_t x) { return (double)(x >> 29); }
-  __device__ static uint64_t from_fast(F y) { return ((uint64_t)y) << 29; }
-  __device__ static F step(F yc, F yp) {
-    const double pd = 536870909.0, inv = 1.0 / 536870909.0;
-    const double s = fma(8.0, yc, -48.0 * yp);
-    const double k = floor(s * inv);
-    double r = fma(-k, pd, s);
-    r = (r < 0.0) ? r + pd : r;
-    return (r >= pd) ? r - pd : r;
-  }
-  __device__ static uint32_t digit(F y) {
-    const double pd = 536870909.0;
-    if (V == 1) return y >= 268435455.0;   // 2y >= p
-    const double num = y * (double)(1 << V);
-    double d = floor(num * (1.0 / 536870909.0));
-    d = (d * pd > num) ? d - 1.0 : d;
-    d = ((d + 1.0) * pd <= num) ? d + 1.0 : d;
-    return (uint32_t)d;
-  }
-};
-template <> struct Eng<5> : EngGQ<1> {};
-template <> struct Eng<6> : EngGQ<3> {};
-template <> struct Eng<7> : EngGQ<4> {};
-
-// Per-element runner: slow exact-mod-g steps until the whole wavefront has
-// collapsed (composite moduli), then the fast recurrence.  The mode only
-// switches between steps and is wavefront-uniform.
-template <int G>
-struct Elem {
-  using E = Eng<G>;
-  typename E::F fc, fp;   // fast representation
-  uint64_t sc, sp;        // exact mod-g values (slow mode)
-  bool fast;
-  __device__ void load(uint64_t xc, uint64_t xp) {
-    if constexpr (E::kComposite) {
-      sc = xc; sp = xp; fast = false;
-    } else {
-      fc = E::to_fast(xc); fp = E::to_fast(xp); fast = true;
-    }
-  }
-  __device__ void maybe_switch() {
-    if constexpr (E::kComposite) {
-      if (!fast) {
-        const bool mine = E::collapsed(sc) && E::collapsed(sp);
-        if (__all(mine)) {
-          fc = E::to_fast(sc); fp = E::to_fast(sp); fast = true;
-        }
-      }
-    }
-  }
-  __device__ uint32_t step() {
-    if constexpr (E::kComposite) {
-      if (!fast) {
-        const uint64_t nx = E::slow_step(sc, sp);
-        sp = sc; sc = nx;
-        return E::slow_digit(nx);
-      }
-    }
-    const typename E::F nx = E::step(fc, fp);
-    fp = fc; fc = nx;
-    return E::digit(nx);
-  }
-  __device__ void get(uint64_t& xc, uint64_t& xp) const {
-    if (fast) { xc = E::from_fast(fc); xp = E::from_fast(fp); }
-    else { xc = sc; xp = sp; }
-  }
-};
+template <int G, int DT>
+__global__ void __launch_bounds__(256) gm_gen8_kernel(const GmState* sin, GmState* sout, uint32_t count, uint64_t n,
+                                                      void* __restrict__ out) {
+  const uint64_t s = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const bool live = s < count;
+  constexpr int es = (DT == PRAND_F64) ? 8 : 4;
+  gen8_wave<G, DT>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
+}
 
 template <int DT>
-__device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
-  if (DT == PRAND_U32) ((uint32_t*)out)[i] = w;
-  else if (DT == PRAND_F32) ((float*)out)[i] = (float)(w >> 8) * 0x1p-24f;
-  else ((double*)out)[i] = (double)w * 0x1p-32;
-}
-
-// v_writelane_b32 with a constant lane: lane L of v takes the
-// wavefront-uniform value val (an inline-constant lane index keeps the
-// instruction within gfx9's single scalar operand)
-template <int L>
-__device__ __forceinline__ uint32_t writelane(uint32_t v, uint32_t val) {
-  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(val), "i"(L));
-  return v;
-}
-template <int U, int END, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (U < END) {
-    f(std::integral_constant<int, U>{});
-    static_for<U + 1, END>(f);
-  }
-}
-
-// OR over aligned groups of 8 / 16 lanes with DPP row permutes (no LDS):
-// quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror (lane i of
-// an 8-lane half reads lane 7-i) and row_mirror (lane i of a row reads 15-i)
-__device__ __forceinline__ uint32_t dpp_or8(uint32_t w) {
-  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0xB1, 0xF, 0xF, false);
-  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x4E, 0xF, 0xF, false);
-  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x141, 0xF, 0xF, false);
-  return w;
-}
-__device__ __forceinline__ uint32_t dpp_or16(uint32_t w) {
-  w = dpp_or8(w);
-  return w | (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x140, 0xF, 0xF, false);
-}
-
-// ------------------------------------------------ v = 1, s = 32: ballots
-template <int G, int DT>
-__global__ void __launch_bounds__(256) gm_gen32_kernel(const GmState* sin, GmState* sout,
-                                                       uint32_t count, uint64_t n, void* __restrict__ out) {
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t s = gid >> 5;
-  const int li = threadIdx.x & 31;        // bit position of this element's digit
-  const int e = 31 - li;                  // element index
+__global__ void __launch_bounds__(256) gq58x3_gen_kernel(const GmState* sin, GmState* sout, uint32_t count,
+                                                         uint64_t n, void* __restrict__ out) {
+  const uint64_t s = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const bool live = s < count;
-  Elem<G> el;
-  el.load(live ? sin[s].xc[e] : 0, live ? sin[s].xp[e] : 0);
-  // the word of step u goes to lane u of each half of the wavefront: a
-  // full block of 32 steps writes the ballot halves with v_writelane, a
-  // ragged last block selects per lane
-  const bool upper = (threadIdx.x & 32) != 0;
-  uint32_t keep = 0;
-  for (uint64_t t0 = 0; t0 < n; t0 += 32) {
-    const int m = (n - t0) < 32 ? (int)(n - t0) : 32;
-    if (m == 32) {
-      static_for<0, 32>([&](auto uc) {
-        constexpr int u = decltype(uc)::value;
-        el.maybe_switch();
-        const uint64_t mask = __ballot(el.step());
-        keep = writelane<u>(keep, (uint32_t)mask);
-        keep = writelane<u + 32>(keep, (uint32_t)(mask >> 32));
-      });
-    } else {
-      for (int u = 0; u < m; u++) {
-        el.maybe_switch();
-        const uint64_t mask = __ballot(el.step());
-        const uint32_t w = upper ? (uint32_t)(mask >> 32) : (uint32_t)mask;
-        keep = (u == li) ? w : keep;
-      }
-    }
-    if (live && li < m) put<DT>(out, s * n + t0 + li, keep);
-  }
-  if (live) {
-    uint64_t xc, xp;
-    el.get(xc, xp);
-    sout[s].xc[e] = xc;
-    sout[s].xp[e] = xp;
-    if (li == 0) { sout[s].off = 0; sout[s].pad = 0; }
-  }
+  constexpr int es = (DT == PRAND_F64) ? 8 : 4;
+  gq3_wave<DT>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
 }
 
-// ------------------------------------------------ v = 4, s = 8: nibbles
-template <int G, int DT>
-__global__ void __launch_bounds__(256) gm_gen8_kernel(const GmState* sin, GmState* sout,
-                                                      uint32_t count, uint64_t n, void* __restrict__ out) {
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t s = gid >> 3;
-  const int e = threadIdx.x & 7;
-  const bool live = s < count;
-  Elem<G> el;
-  el.load(live ? sin[s].xc[e] : 0, live ? sin[s].xp[e] : 0);
-  const int shift = 28 - 4 * e;
-  uint32_t keep = 0;
-  for (uint64_t t0 = 0; t0 < n; t0 += 8) {
-    const int m = (n - t0) < 8 ? (int)(n - t0) : 8;
-    auto one = [&](int u) {
-      el.maybe_switch();
-      const uint32_t w = dpp_or8(el.step() << shift);
-      keep = (u == e) ? w : keep;
-    };
-    int u = 0;
-    for (; u + 2 <= m; u += 2) {
-      one(u);
-      one(u + 1);
-    }
-    if (u < m) one(u);
-    if (live && e < m) put<DT>(out, s * n + t0 + e, keep);
-  }
-  if (live) {
-    uint64_t xc, xp;
-    el.get(xc, xp);
-    sout[s].xc[e] = xc;
-    sout[s].xp[e] = xp;
-    if (e == 0) { sout[s].off = 0; sout[s].pad = 0; }
-  }
-}
-
-// --------------------------------- GQ58.3: v = 3, s = 12, 16 lanes / stream
-// 8 steps of 36 bits = 9 words.  The state sits at a block boundary with
-// `off` words of the block consumed; a call emits block words from off on and
-// keeps the state at the start of the last, partially used block.
-template <int DT>
-__global__ void __launch_bounds__(256) gq58x3_gen_kernel(const GmState* sin, GmState* sout,
-                                                         uint32_t count, uint64_t n, void* __restrict__ out) {
-  constexpr int G = 6;
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t s = gid >> 4;
-  const int e = threadIdx.x & 15;
-  const int gbase = threadIdx.x & 48;     // first lane of this stream's group (within the wavefront)
-  const bool live = s < count;
-  const bool elem = e < 12;
-  Elem<G> el;
-  el.load((live && elem) ? sin[s].xc[e] : 0, (live && elem) ? sin[s].xp[e] : 0);
-  const uint32_t off0 = live ? sin[s].off : 0;
-  const uint64_t total = off0 + n;
-  const uint64_t full = total / 9;
-  const uint32_t rem = (uint32_t)(total % 9);
-  const uint64_t blocks = full + (rem ? 1 : 0);
-  // wavefront-uniform block count: lanes of dead streams follow along
-  uint64_t nb = blocks;
-  Elem<G> saved = el;
-  const int shift = elem ? 33 - 3 * e : 0;
-  for (uint64_t b = 0; b < nb; b++) {
-    el.maybe_switch();
-    saved = el;
-    uint64_t keep = 0;
-    for (int u = 0; u < 8; u++) {
-      const uint32_t d = el.step();
-      uint64_t c = elem ? ((uint64_t)d << shift) : 0;
-      const uint32_t lo = dpp_or16((uint32_t)c), hi = dpp_or16((uint32_t)(c >> 32));
-      c = ((uint64_t)hi << 32) | lo;
-      keep = (u == e) ? c : keep;
-    }
-    // word w (lane w < 9): bits [32w, 32w+32) of the 288-bit block
-    const int w = e < 9 ? e : 8;
-    const int ci = (32 * w) / 36, o = 32 * w - 36 * ci;
-    const uint32_t alo = __shfl((uint32_t)keep, gbase + ci);
-    const uint32_t ahi = __shfl((uint32_t)(keep >> 32), gbase + ci);
-    const int cj = ci + 1 < 8 ? ci + 1 : 7;
-    const uint32_t blo = __shfl((uint32_t)keep, gbase + cj);
-    const uint32_t bhi = __shfl((uint32_t)(keep >> 32), gbase + cj);
-    const uint64_t A = ((uint64_t)ahi << 32) | alo;
-    const uint64_t B = (ci + 1 < 8) ? (((uint64_t)bhi << 32) | blo) : 0;
-    const int k = 40 - o;   // the word is (A:B >> k) & (2^32 - 1) of the 72-bit A:B
-    const uint32_t word = (k > 36) ? (uint32_t)(A >> (k - 36)) : (uint32_t)((A << (36 - k)) | (B >> k));
-    const int64_t q = (int64_t)(b * 9 + w) - (int64_t)off0;
-    if (live && e < 9 && q >= 0 && (uint64_t)q < n) put<DT>(out, s * n + (uint64_t)q, word);
-  }
-  if (live && elem) {
-    uint64_t xc, xp;
-    if (rem && nb > 0) saved.get(xc, xp); else el.get(xc, xp);
-    sout[s].xc[e] = xc;
-    sout[s].xp[e] = xp;
-  }
-  if (live && e == 0) { sout[s].off = rem; sout[s].pad = 0; }
-}
-
-// -------------------------------------------------------------- jumping
-template <int G>
-struct Mod;
-template <int G>
-__device__ __forceinline__ uint64_t fold_special(u128 x, int e, uint64_t c, uint64_t p) {
-  const uint64_t mask = (1ull << e) - 1;
-  for (int i = 0; i < 3; i++) x = (x & mask) + (u128)c * (uint64_t)(x >> e);
-  uint64_t r = (uint64_t)x;
-  r = r >= p ? r - p : r;
-  r = r >= p ? r - p : r;
-  return r;
-}
-// prime part p = 2^e - c of each generator's modulus
-__device__ __forceinline__ void prime_form(int G, int& e, uint64_t& c) {
-  switch (G) {
-    case 0: e = 19; c = 1; break;
-    case 1: e = 29; c = 3; break;
-    case 2: e = 31; c = 1; break;
-    case 3: e = 51; c = 129; break;
-    case 4: e = 61; c = 1; break;
-    default: e = 29; c = 3; break;
-  }
-}
-
+// One lane per element slot (32 per stream): states[s] = base (or states[s])
+// jumped by the stream's distance; GQ58.3 distances count words.
 template <int G>
 __global__ void __launch_bounds__(256) gm_jump_kernel(GmState* __restrict__ states, uint32_t count,
                                                       const uint64_t* __restrict__ dist, int nlimbs, int per_stream,
                                                       const uint64_t* __restrict__ ids, int block_e,
                                                       const GmState* __restrict__ base,
                                                       const uint64_t* __restrict__ ladder) {
-  using E = Eng<G>;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t s = gid >> 5;
   if (s >= count) return;
@@ -449,89 +80,11 @@ __global__ void __launch_bounds__(256) gm_jump_kernel(GmState* __restrict__ stat
     for (int l = 0; l < nlimbs; l++) N[l] = d[l];
   }
   uint32_t new_off = 0;
-  if (G == 6 && !ids) {
-    // GQ58.3: distance in words -> (off + N) = 9 B + rem; steps = 8 B
-    uint64_t carry = off;
-    for (int l = 0; l <= kMaxLimbs && carry; l++) {
-      const uint64_t old = N[l];
-      N[l] = old + carry;
-      carry = N[l] < old ? 1 : 0;
-    }
-    uint64_t r = 0;   // divide by 9 in 32-bit pieces
-    for (int l = kMaxLimbs; l >= 0; l--) {
-      const uint64_t hi = (r << 32) | (N[l] >> 32);
-      const uint64_t qh = hi / 9;
-      r = hi % 9;
-      const uint64_t lo = (r << 32) | (N[l] & 0xFFFFFFFFull);
-      const uint64_t ql = lo / 9;
-      r = lo % 9;
-      N[l] = (qh << 32) | ql;
-    }
-    new_off = (uint32_t)r;
-    uint64_t c3 = 0;   // times 8
-    for (int l = 0; l <= kMaxLimbs; l++) {
-      const uint64_t v = N[l];
-      N[l] = (v << 3) | c3;
-      c3 = v >> 61;
-    }
-  } else if (G == 6) {
-    new_off = off;   // whole blocks: the offset inside the block is kept
+  if (G == 6) {
+    if (ids) new_off = off;   // whole blocks: the offset inside the block is kept
+    else gq3_words_to_steps(N, off, &new_off);
   }
-  const bool active = e < kGmParams[G].s;
-  if (active) {
-    int pe;
-    uint64_t pc;
-    prime_form(G, pe, pc);
-    const uint64_t p = kGmParams[G].p;
-    const uint64_t* L = ladder + (size_t)G * kLadder * 4;
-    if constexpr (E::kComposite) {
-      // small distances: exact steps; otherwise collapse, then jump mod p
-      bool small = true;
-      for (int l = 1; l <= kMaxLimbs; l++) small = small && N[l] == 0;
-      uint64_t steps_done = 0;
-      const uint64_t n0 = (uint64_t)kGmParams[G].n0;
-      if (small && N[0] < n0) {
-        for (uint64_t i = 0; i < N[0]; i++) { const uint64_t nx = E::slow_step(xc, xp); xp = xc; xc = nx; }
-      } else {
-        if (!(E::collapsed(xc) && E::collapsed(xp))) {
-          for (uint64_t i = 0; i < n0; i++) { const uint64_t nx = E::slow_step(xc, xp); xp = xc; xc = nx; }
-          steps_done = n0;
-        }
-        uint64_t borrow = steps_done;
-        for (int l = 0; l <= kMaxLimbs && borrow; l++) {
-          const uint64_t old = N[l];
-          N[l] = old - borrow;
-          borrow = old < borrow ? 1 : 0;
-        }
-        uint64_t yc = xc >> E::t, yp = xp >> E::t;
-        for (int l = 0; l < kMaxLimbs; l++) {
-          uint64_t wd = N[l];
-          while (wd) {
-            const int b = __builtin_ctzll(wd) + 64 * l;
-            wd &= wd - 1;
-            const uint64_t* M = L + (size_t)b * 4;
-            const uint64_t nc = fold_special<G>((u128)M[0] * yc + (u128)M[1] * yp, pe, pc, p);
-            const uint64_t np = fold_special<G>((u128)M[2] * yc + (u128)M[3] * yp, pe, pc, p);
-            yc = nc; yp = np;
-          }
-        }
-        xc = yc << E::t;
-        xp = yp << E::t;
-      }
-    } else {
-      for (int l = 0; l < kMaxLimbs; l++) {
-        uint64_t wd = N[l];
-        while (wd) {
-          const int b = __builtin_ctzll(wd) + 64 * l;
-          wd &= wd - 1;
-          const uint64_t* M = L + (size_t)b * 4;
-          const uint64_t nc = fold_special<G>((u128)M[0] * xc + (u128)M[1] * xp, pe, pc, p);
-          const uint64_t np = fold_special<G>((u128)M[2] * xc + (u128)M[3] * xp, pe, pc, p);
-          xc = nc; xp = np;
-        }
-      }
-    }
-  }
+  if (e < kGmParams[G].s) jump_steps_elem<G>(xc, xp, N, ladder);
   GmState* dst = states + s;
   dst->xc[e] = xc;
   dst->xp[e] = xp;

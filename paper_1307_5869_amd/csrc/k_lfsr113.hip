@@ -5,63 +5,13 @@
 // and the output word is the XOR of the four components.  One lane owns a
 // (stream, section) pair with the four words in registers; jumps apply the
 // 32x32 F2 matrices T_c^(2^b) of the context ladder for each set bit b.
-#include "prand_impl.h"
+#include "dev_lfsr.h"
 #include "regstream.h"
 
 namespace prand {
 namespace {
 
-__device__ __forceinline__ uint32_t comp(uint32_t z, uint32_t mask, int q, int sh1, int s) {
-  return ((z & mask) << s) ^ (((z << q) ^ z) >> sh1);
-}
-
-}  // namespace
-struct LfsrRegs {
-  uint32_t z0, z1, z2, z3;
-};
-namespace {
-
-__device__ __forceinline__ uint32_t step(LfsrRegs& r) {
-  r.z0 = comp(r.z0, 0xFFFFFFFEu, 6, 13, 18);
-  r.z1 = comp(r.z1, 0xFFFFFFF8u, 2, 27, 2);
-  r.z2 = comp(r.z2, 0xFFFFFFF0u, 13, 21, 7);
-  r.z3 = comp(r.z3, 0xFFFFFF80u, 3, 12, 13);
-  return r.z0 ^ r.z1 ^ r.z2 ^ r.z3;
-}
-
-__device__ __forceinline__ uint32_t f2_apply(const uint32_t* __restrict__ cols, uint32_t v) {
-  uint32_t r = 0;
-#pragma unroll 4
-  for (int j = 0; j < 32; j++) r ^= ((v >> j) & 1u) ? cols[j] : 0u;
-  return r;
-}
-
-__device__ __forceinline__ void jump_state(const uint32_t* ladder, uint32_t z[4], const uint64_t* limbs,
-                                           int nlimbs) {
-  for (int l = 0; l < nlimbs; l++) {
-    uint64_t w = limbs[l];
-    while (w) {
-      const int b = __builtin_ctzll(w) + 64 * l;
-      w &= w - 1;
-      const uint32_t* M = ladder + (size_t)b * 128;
-      for (int c = 0; c < 4; c++) z[c] = f2_apply(M + 32 * c, z[c]);
-    }
-  }
-}
-
-struct LfsrGen {
-  using State = LfsrState;
-  using Regs = prand::LfsrRegs;
-  __device__ static Regs load(const LfsrState& st) { return Regs{st.z[0], st.z[1], st.z[2], st.z[3]}; }
-  __device__ static LfsrState save(const Regs& r) {
-    LfsrState o;
-    o.z[0] = r.z0; o.z[1] = r.z1; o.z[2] = r.z2; o.z[3] = r.z3;
-    return o;
-  }
-  __device__ static void jump(LfsrState& st, uint64_t d, const uint32_t* ladder) { jump_state(ladder, st.z, &d, 1); }
-  __device__ static uint32_t next(Regs& r) { return step(r); }
-  __device__ static double f64(uint32_t w) { return (double)w * 0x1p-32; }
-};
+using namespace lfsr;
 
 __global__ void __launch_bounds__(256) lfsr_jump_kernel(LfsrState* __restrict__ states, uint32_t count,
                                                         const uint64_t* __restrict__ dist, int nlimbs,

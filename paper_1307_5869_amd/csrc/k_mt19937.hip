@@ -19,78 +19,22 @@
 // into an LDS ring, and lane l accumulates outputs t = 10l .. 10l+9 while a
 // register window of 10 sequence words slides over the coefficients, so each
 // coefficient costs one LDS read per lane and, when set, 10 XORs.
-#include "prand_impl.h"
+#include "dev_mt.h"
 
 namespace prand {
 namespace {
 
-constexpr uint32_t kUpper = 0x80000000u;
-constexpr uint32_t kLower = 0x7FFFFFFFu;
-constexpr uint32_t kMatA = 0x9908B0DFu;
+using namespace mt;
 
-__device__ __forceinline__ uint32_t temper(uint32_t y) {
-  y ^= y >> 11;
-  y ^= (y << 7) & 0x9D2C5680u;
-  y ^= (y << 15) & 0xEFC60000u;
-  return y ^ (y >> 18);
-}
-// x_{j+624} from x_j (upper bit), x_{j+1} (lower bits), x_{j+397}
-__device__ __forceinline__ uint32_t recur(uint32_t xj, uint32_t xj1, uint32_t xjm) {
-  const uint32_t y = (xj & kUpper) | (xj1 & kLower);
-  return xjm ^ (y >> 1) ^ ((xj1 & 1u) ? kMatA : 0u);
-}
 
 template <int DT>
-__device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
-  if (DT == PRAND_U32) ((uint32_t*)out)[i] = w;
-  else if (DT == PRAND_F32) ((float*)out)[i] = (float)(w >> 8) * 0x1p-24f;
-  else ((double*)out)[i] = (double)w * 0x1p-32;
-}
-
-template <int DT>
-__global__ void __launch_bounds__(64) mt_generate_kernel(MtState* __restrict__ states, uint32_t count, uint64_t n,
+__global__ void __launch_bounds__(64) mt_generate_kernel(MtState* states, uint32_t count, uint64_t n,
                                                          void* __restrict__ out) {
   __shared__ uint32_t mt[624];
   const uint32_t s = blockIdx.x;
   if (s >= count) return;
-  const int lane = threadIdx.x;
-  MtState* S = states + s;
-  for (int i = lane; i < 624; i += 64) mt[i] = S->mt[i];
-  uint32_t idx = S->idx < 624u ? S->idx : 624u;   // an index past the block means "block used up"
-  __syncthreads();
-  const uint64_t base = (uint64_t)s * n;
-  // rest of the current block
-  const uint64_t first = (uint64_t)(624 - idx) < n ? (uint64_t)(624 - idx) : n;
-  for (uint32_t i = lane; i < first; i += 64) put<DT>(out, base + i, temper(mt[idx + i]));
-  uint64_t pos = first;
-  idx += (uint32_t)first;
-  while (pos < n) {
-    const uint64_t left = n - pos;
-    const int want = left < 624 ? (int)left : 624;
-    const uint64_t ob = base + pos;
-    for (int j = lane; j < 227; j += 64) {
-      const uint32_t v = recur(mt[j], mt[j + 1], mt[j + 397]);
-      mt[j] = v;
-      if (j < want) put<DT>(out, ob + j, temper(v));
-    }
-    __syncthreads();
-    for (int j = 227 + lane; j < 454; j += 64) {
-      const uint32_t v = recur(mt[j], mt[j + 1], mt[j - 227]);
-      mt[j] = v;
-      if (j < want) put<DT>(out, ob + j, temper(v));
-    }
-    __syncthreads();
-    for (int j = 454 + lane; j < 624; j += 64) {
-      const uint32_t v = recur(mt[j], mt[j == 623 ? 0 : j + 1], mt[j - 227]);
-      mt[j] = v;
-      if (j < want) put<DT>(out, ob + j, temper(v));
-    }
-    __syncthreads();
-    pos += want;
-    idx = want;
-  }
-  for (int i = lane; i < 624; i += 64) S->mt[i] = mt[i];
-  if (lane == 0) S->idx = idx;
+  constexpr int es = (DT == PRAND_F64) ? 8 : 4;
+  gen_wave<DT>(mt, states + s, states + s, n, (char*)out + (uint64_t)s * n * es);
 }
 
 // ------------------------------------------------------------------ jump

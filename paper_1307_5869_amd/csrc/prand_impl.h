@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 
 #include "prand.h"
 
@@ -78,6 +79,17 @@ constexpr size_t kDefaultStride = 2560;
 // exponent of the MT19937 digit tables: the block-splitting block 2^432
 constexpr int kMtDigitE = 432;
 
+// Order a wavefront's LDS writes before its later LDS reads (and reads before
+// later writes) when the LDS block is private to the wavefront: LDS
+// instructions of one wavefront execute in order, so only the compiler must
+// be kept from reordering.  No workgroup barrier: wavefronts of a persistent
+// workgroup run different amounts of work.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---- launchers (one per kernel family); all enqueue on `st` ----
 // Distances: `dist` holds nlimbs limbs per stream when per_stream, else one
 // shared distance.  `ids` + `block_e`: distance id * 2^block_e (GQ58.3: in
@@ -124,4 +136,37 @@ void build_mrg_ladder(uint32_t* out);
 void build_lfsr_ladder(uint32_t* out);
 void build_gm_ladders(uint64_t* out);
 
+// the calling thread's current device is set to `dev` for the guard's life
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace prand
+
+// the opaque context of the public ABI
+struct prand_ctx {
+  int device = 0;
+  int num_cus = 256;
+  char arch[64] = {0};
+  prand::DeviceTables T;
+  bool mt_ready = false;
+  std::mutex mu;          // guards mt_ready and the host-call scratch
+  void* scratch = nullptr;
+  int last_hip = 0;
+};
+
+namespace prand {
+inline int hipfail(prand_ctx* c, hipError_t e) {
+  if (c) c->last_hip = (int)e;
+  return PRAND_EHIP;
+}
 }  // namespace prand

@@ -1,18 +1,18 @@
-// Many-stream generation for generators whose whole state fits in a lane's
-// registers (MRG32K3A, LFSR113).
+// Generation for generators whose whole state fits in a lane's registers
+// (MRG32K3A, LFSR113): one lane per section of a stream.
 //
-// Lane gid owns section gid & (nsec - 1) of stream gid >> nsec_log2; the
-// sections of a stream cover [j * seclen, min((j + 1) * seclen, n)) and start
-// by jumping j * seclen ahead.  Each lane's outputs are contiguous in memory
-// but 64 lanes write 64 different places, so a lane produces its outputs in
-// chunks of CW words (CW = 32: 128 bytes, 32 u32/f32 or 16 f64 values), parks
-// them in LDS, and the wavefront stores them transposed: in each store
-// instruction the CW/4 consecutive lanes of a group write the 16-byte pieces
-// of one chunk (CW = 32: eight whole 128-byte lines per instruction; CW = 16
-// halves the LDS footprint and doubles occupancy with 64-byte segments).
-// Rounds run while every live lane of the wavefront still has a full chunk
-// to write; the rest of a section is stored lane by lane.  The lane whose
-// section ends at n writes the advanced state to sout.
+// A section starts from a state jumped to its first output and fills a
+// contiguous run of the output.  The 64 runs of a wavefront lie in 64
+// different places, so each lane produces its outputs in chunks of CW words
+// (CW = 32: 128 bytes, 32 u32/f32 or 16 f64 values), parks them in LDS, and
+// the wavefront stores them transposed: in each store instruction the CW/4
+// consecutive lanes of a group write the 16-byte pieces of one chunk (CW = 32:
+// eight whole 128-byte lines per instruction).  Rounds run while every live
+// lane still has a full chunk to write; the rest of each run is stored lane
+// by lane.
+//
+// regstream_wave() is the wavefront routine shared by the many-stream kernel
+// below and by the batched persistent kernel.
 #pragma once
 
 #include <cstdlib>
@@ -21,16 +21,11 @@
 
 namespace prand {
 
-
-// Order this wavefront's LDS writes before its later LDS reads (and reads
-// before later writes).  The staging rows are private to the wavefront, so
-// no workgroup barrier is needed -- and none may be used, since wavefronts of
-// one workgroup can run different numbers of rounds.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+template <int CW>
+struct RegStage {
+  static constexpr int kRowWords = CW + 4;            // padded row, 16-byte aligned
+  static constexpr int kWaveWords = 64 * kRowWords;   // LDS words per wavefront
+};
 
 template <int DT>
 __device__ __forceinline__ void put_word(void* out, uint64_t i, uint32_t w, double f64v) {
@@ -39,88 +34,106 @@ __device__ __forceinline__ void put_word(void* out, uint64_t i, uint32_t w, doub
   else ((double*)out)[i] = f64v;
 }
 
+// One lane's section: live lanes start from *in (jumped `start` outputs
+// ahead), write `len` values at `out` (element pointer of the run) and, when
+// `sout` is set, store the advanced state there.  `coalesce`: every run start
+// is 16-byte aligned (transposed stores allowed).  All 64 lanes must call.
+//
 // G: State, Regs, static load(State) -> Regs, static save(Regs) -> State,
 // static jump(State&, uint64_t distance, const uint32_t* ladder),
 // static next(Regs&) -> uint32_t word, static f64(uint32_t) -> double.
 template <class G, int DT, int CW>
-__global__ void __launch_bounds__(256) regstream_kernel(const typename G::State* sin, typename G::State* sout,
-                                                        uint32_t count, uint64_t n, int nsec_log2, uint64_t seclen,
-                                                        void* __restrict__ out, const uint32_t* __restrict__ ladder,
-                                                        int coalesce) {
-  constexpr int kRowWords = CW + 4;   // padded LDS row, 16-byte aligned
-  constexpr int kPieces = CW / 4;     // 16-byte pieces per chunk
-  __shared__ __align__(16) uint32_t stage[256 / 64][64 * kRowWords];
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void regstream_wave(uint32_t* rows, bool live, const typename G::State* in, uint64_t start,
+                                               uint64_t len, void* out, typename G::State* sout, bool coalesce,
+                                               const uint32_t* __restrict__ ladder) {
+  constexpr int kPieces = CW / 4;                            // 16-byte pieces per chunk
+  constexpr int per = (DT == PRAND_F64) ? CW / 2 : CW;        // values per chunk
+  constexpr int es = (DT == PRAND_F64) ? 8 : 4;
   const int lane = threadIdx.x & 63;
-  uint32_t* rows = stage[threadIdx.x >> 6];
-  const uint64_t nsec = 1ull << nsec_log2;
-  const uint64_t jlast = (n == 0) ? 0 : (n - 1) / seclen;
-  auto section = [&](uint64_t g, uint64_t& s, uint64_t& j, uint64_t& start, uint64_t& len) -> bool {
-    s = g >> nsec_log2;
-    j = g & (nsec - 1);
-    start = j * seclen;
-    len = (j == jlast) ? n - start : seclen;
-    return s < count && j <= jlast;
-  };
-  uint64_t s, j, start, len;
-  const bool live = section(gid, s, j, start, len);
   typename G::State st = {};
   if (live) {
-    st = sin[s];
+    st = *in;
     if (start) G::jump(st, start, ladder);
   }
   typename G::Regs r = G::load(st);
-  constexpr int per = (DT == PRAND_F64) ? CW / 2 : CW;   // values per chunk
-  constexpr int es = (DT == PRAND_F64) ? 8 : 4;
-  // full chunks every live lane of this wavefront can still write
+  // full chunks every live lane can still write (wavefront minimum)
   uint64_t my_rounds = live ? len / per : ~0ull;
   for (int o = 1; o < 64; o <<= 1) {
     const uint64_t other = __shfl_xor(my_rounds, o);
     my_rounds = other < my_rounds ? other : my_rounds;
   }
   const uint64_t rounds = (my_rounds == ~0ull || !coalesce) ? 0 : my_rounds;
-  const uint64_t gid0 = gid - lane;
-  char* const obytes = (char*)out;
-  for (uint64_t rd = 0; rd < rounds; rd++) {
-    uint32_t* row = rows + lane * kRowWords;
-#pragma unroll
-    for (int q = 0; q < kPieces; q++) {
-      uint4 v;
-      if (DT == PRAND_F64) {
-        const double a = G::f64(G::next(r)), b = G::f64(G::next(r));
-        const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
-        v = make_uint4((uint32_t)ua, (uint32_t)(ua >> 32), (uint32_t)ub, (uint32_t)(ub >> 32));
-      } else if (DT == PRAND_F32) {
-        const uint32_t a = G::next(r), b = G::next(r), c = G::next(r), d = G::next(r);
-        v = make_uint4(__float_as_uint((float)(a >> 8) * 0x1p-24f), __float_as_uint((float)(b >> 8) * 0x1p-24f),
-                       __float_as_uint((float)(c >> 8) * 0x1p-24f), __float_as_uint((float)(d >> 8) * 0x1p-24f));
-      } else {
-        const uint32_t a = G::next(r), b = G::next(r), c = G::next(r), d = G::next(r);
-        v = make_uint4(a, b, c, d);
-      }
-      *(uint4*)(row + 4 * q) = v;
-    }
-    wave_lds_sync();
+  if (rounds) {
+    // destination of piece (lane % kPieces) of each source lane's chunk, one
+    // per store instruction; null for dead sources
+    char* const mine = live ? (char*)out : nullptr;
+    char* dst[kPieces];
 #pragma unroll
     for (int i = 0; i < kPieces; i++) {
-      const int src = i * (64 / kPieces) + lane / kPieces, piece = lane % kPieces;
-      uint64_t ss, sj, sstart, slen;
-      const bool slive = section(gid0 + src, ss, sj, sstart, slen);
-      const uint4 v = *(const uint4*)(rows + src * kRowWords + 4 * piece);
-      if (slive) {
-        const uint64_t byte = (ss * n + sstart + rd * per) * es + 16 * piece;
-        *(uint4*)(obytes + byte) = v;
-      }
+      const int src = i * (64 / kPieces) + lane / kPieces;
+      char* b = (char*)__shfl((unsigned long long)mine, src);
+      dst[i] = b ? b + 16 * (lane % kPieces) : nullptr;
     }
-    wave_lds_sync();
+    uint32_t* row = rows + lane * RegStage<CW>::kRowWords;
+    for (uint64_t rd = 0; rd < rounds; rd++) {
+#pragma unroll
+      for (int q = 0; q < kPieces; q++) {
+        uint4 v;
+        if (DT == PRAND_F64) {
+          const double a = G::f64(G::next(r)), b = G::f64(G::next(r));
+          const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+          v = make_uint4((uint32_t)ua, (uint32_t)(ua >> 32), (uint32_t)ub, (uint32_t)(ub >> 32));
+        } else if (DT == PRAND_F32) {
+          const uint32_t a = G::next(r), b = G::next(r), c = G::next(r), d = G::next(r);
+          v = make_uint4(__float_as_uint((float)(a >> 8) * 0x1p-24f), __float_as_uint((float)(b >> 8) * 0x1p-24f),
+                         __float_as_uint((float)(c >> 8) * 0x1p-24f), __float_as_uint((float)(d >> 8) * 0x1p-24f));
+        } else {
+          const uint32_t a = G::next(r), b = G::next(r), c = G::next(r), d = G::next(r);
+          v = make_uint4(a, b, c, d);
+        }
+        *(uint4*)(row + 4 * q) = v;
+      }
+      wave_lds_sync();
+      const uint64_t adv = rd * per * es;
+#pragma unroll
+      for (int i = 0; i < kPieces; i++) {
+        const int src = i * (64 / kPieces) + lane / kPieces;
+        const uint4 v = *(const uint4*)(rows + src * RegStage<CW>::kRowWords + 4 * (lane % kPieces));
+        if (dst[i]) *(uint4*)(dst[i] + adv) = v;
+      }
+      wave_lds_sync();
+    }
   }
   if (live) {
     for (uint64_t i = rounds * per; i < len; i++) {
       const uint32_t w = G::next(r);
-      put_word<DT>(out, s * n + start + i, w, DT == PRAND_F64 ? G::f64(w) : 0.0);
+      put_word<DT>(out, i, w, DT == PRAND_F64 ? G::f64(w) : 0.0);
     }
-    if (j == jlast) sout[s] = G::save(r);
+    if (sout) *sout = G::save(r);
   }
+}
+
+// Many streams: lane gid owns section gid & (nsec - 1) of stream
+// gid >> nsec_log2; the sections of a stream cover
+// [j * seclen, min((j + 1) * seclen, n)) and sit in one wavefront (nsec <= 64),
+// so the state read of every section precedes the write-back of the last.
+template <class G, int DT, int CW>
+__global__ void __launch_bounds__(256) regstream_kernel(const typename G::State* sin, typename G::State* sout,
+                                                        uint32_t count, uint64_t n, int nsec_log2, uint64_t seclen,
+                                                        void* __restrict__ out, const uint32_t* __restrict__ ladder,
+                                                        int coalesce) {
+  __shared__ __align__(16) uint32_t stage[4][RegStage<CW>::kWaveWords];
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t nsec = 1ull << nsec_log2;
+  const uint64_t jlast = (n == 0) ? 0 : (n - 1) / seclen;
+  const uint64_t s = gid >> nsec_log2, j = gid & (nsec - 1);
+  const uint64_t start = j * seclen;
+  const bool live = s < count && j <= jlast;
+  const uint64_t len = live ? ((j == jlast) ? n - start : seclen) : 0;
+  constexpr int es = (DT == PRAND_F64) ? 8 : 4;
+  void* o = (char*)out + (s * n + start) * es;
+  regstream_wave<G, DT, CW>(stage[threadIdx.x >> 6], live, sin + (live ? s : 0), start, len, o,
+                            (live && j == jlast) ? sout + s : nullptr, coalesce != 0, ladder);
 }
 
 // CW of the register-state kernels: 32 unless PRAND_REG_CHUNK_WORDS=16
@@ -135,8 +148,8 @@ inline int regstream_chunk_words() {
 
 template <class G, int CW>
 hipError_t launch_regstream_cw(const typename G::State* sin, typename G::State* sout, uint32_t count, uint64_t n,
-                            int nsec_log2, uint64_t seclen, int dtype, void* out, const uint32_t* ladder,
-                            hipStream_t st) {
+                               int nsec_log2, uint64_t seclen, int dtype, void* out, const uint32_t* ladder,
+                               hipStream_t st) {
   const uint64_t lanes = (uint64_t)count << nsec_log2;
   const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
   // transposed 16-byte stores need every section start 16-byte aligned

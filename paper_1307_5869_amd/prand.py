@@ -39,7 +39,24 @@ _SIGNATURES = {
     "prand_init_streams_dev": (_i32, [_vp, _i32, _i32, _vp, _vp, _u32, _vp, _vp]),
     "prand_generate": (_i32, [_vp, _i32, _vp, _i32, _vp, _u64, _vp]),
     "prand_generate_streams": (_i32, [_vp, _i32, _vp, _u32, _u64, _i32, _vp, _vp]),
+    "prand_batch_create": (_i32, [_vp, _vp, _u32, _vp, ctypes.POINTER(_vp)]),
+    "prand_batch_launch": (_i32, [_vp, _vp]),
+    "prand_batch_tiles": (_i32, [_vp, ctypes.POINTER(_u32)]),
+    "prand_batch_destroy": (_i32, [_vp]),
+    "prand_batch_autotune": (_i32, [_vp, _vp, _u32, _vp]),
 }
+
+
+class Task(ctypes.Structure):
+    """struct prand_task"""
+    _fields_ = [("gen", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_uint64),
+                ("state_in", ctypes.c_void_p), ("state_out", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class BatchConfig(ctypes.Structure):
+    """struct prand_batch_config (zeros select the defaults)"""
+    _fields_ = [("waves_per_cu", ctypes.c_uint32), ("reg_section", ctypes.c_uint32),
+                ("gm_section", ctypes.c_uint32), ("use_graph", ctypes.c_uint32)]
 
 _lib = None
 
@@ -190,6 +207,55 @@ class Context:
 
     def generate_streams(self, gen, d_states, count, n, dtype, d_out, stream=None):
         self._call("prand_generate_streams", gen, _ptr(d_states), count, n, dtype, _ptr(d_out), _stream(stream))
+
+
+class Batch:
+    """A planned batched launch (prand_batch_*).  `tasks`: iterable of
+    (gen, dtype, n, state_in, state_out, out) with device buffers (torch
+    tensors or addresses); the buffers must outlive the batch."""
+
+    def __init__(self, ctx, tasks, config=None):
+        self.ctx = ctx
+        arr = (Task * max(1, len(tasks)))()
+        for i, (gen, dtype, n, sin, sout, out) in enumerate(tasks):
+            arr[i] = Task(gen, dtype, n, _ptr(sin), _ptr(sout), _ptr(out))
+        self.ntasks = len(tasks)
+        self._tasks = arr
+        cfg = ctypes.byref(config) if config is not None else None
+        h = _vp()
+        rc = ctx.lib.prand_batch_create(ctx.handle, ctypes.cast(arr, _vp), len(tasks), cfg, ctypes.byref(h))
+        _chk(rc, "prand_batch_create")
+        self.handle = h
+
+    def tiles(self):
+        n = _u32()
+        _chk(self.ctx.lib.prand_batch_tiles(self.handle, ctypes.byref(n)), "prand_batch_tiles")
+        return n.value
+
+    def launch(self, stream=None):
+        _chk(self.ctx.lib.prand_batch_launch(self.handle, _stream(stream)), "prand_batch_launch")
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.prand_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(ctx, tasks):
+    """prand_batch_autotune on the given tasks; returns a BatchConfig."""
+    arr = (Task * max(1, len(tasks)))()
+    for i, (gen, dtype, n, sin, sout, out) in enumerate(tasks):
+        arr[i] = Task(gen, dtype, n, _ptr(sin), _ptr(sout), _ptr(out))
+    best = BatchConfig()
+    _chk(ctx.lib.prand_batch_autotune(ctx.handle, ctypes.cast(arr, _vp), len(tasks), ctypes.byref(best)),
+         "prand_batch_autotune")
+    return best
 
 
 def __getattr__(name):
