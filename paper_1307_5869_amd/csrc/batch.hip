@@ -298,9 +298,11 @@ int prand_batch_autotune(prand_ctx* c, const prand_task* h_tasks, uint32_t ntask
   const std::string key = signature(c, h_tasks, ntasks);
   if (cache_lookup(key, best)) return PRAND_OK;
   DeviceGuard g(c->device);
+  // the task buffers may still be in flight on other streams
+  hipError_t e = hipDeviceSynchronize();
   hipStream_t st = nullptr;
   hipEvent_t a = nullptr, z = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&z);
   float best_ms = 1e30f;

@@ -231,12 +231,17 @@ __device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
   else ((double*)out)[i] = (double)w * 0x1p-32;
 }
 
-// v_writelane_b32 with a constant lane: lane L of v takes the
-// wavefront-uniform value val (an inline-constant lane index keeps the
-// instruction within gfx9's single scalar operand)
+// Lanes L and L + 32 of v take the two halves of a wavefront ballot, with
+// v_writelane_b32 and constant lane indices (an inline constant keeps each
+// instruction within gfx9's single scalar operand).  The ballot's SGPRs are
+// usually written by the VALU compare just before; gfx950 needs two wait
+// states between a VALU SGPR write and a VALU read of it, and the compiler
+// inserts none for inline assembly, hence the s_nop.
 template <int L>
-__device__ __forceinline__ uint32_t writelane(uint32_t v, uint32_t val) {
-  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(val), "i"(L));
+__device__ __forceinline__ uint32_t writelane_pair(uint32_t v, uint32_t lo, uint32_t hi) {
+  asm("s_nop 1\n\tv_writelane_b32 %0, %1, %3\n\tv_writelane_b32 %0, %2, %4"
+      : "+v"(v)
+      : "s"(lo), "s"(hi), "i"(L), "i"(L + 32));
   return v;
 }
 template <int U, int END, class F>
@@ -416,8 +421,7 @@ __device__ __forceinline__ void gen32_wave(bool live, const GmState* in, uint64_
         constexpr int u = decltype(uc)::value;
         el.maybe_switch();
         const uint64_t mask = __ballot(el.step());
-        keep = writelane<u>(keep, (uint32_t)mask);
-        keep = writelane<u + 32>(keep, (uint32_t)(mask >> 32));
+        keep = writelane_pair<u>(keep, (uint32_t)mask, (uint32_t)(mask >> 32));
       });
     } else {
       for (int u = 0; u < m; u++) {
