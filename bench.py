@@ -27,6 +27,10 @@ HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit lane ops/s: 256 CUs x 64 lanes x 2.4 GHz
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -38,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dtype-sweep", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--batched-tasks", type=int, default=20000)
     return ap.parse_args()
 
@@ -157,7 +164,11 @@ def main():
 
     del out, states
     torch.cuda.empty_cache()
+    log("C2 step done; batched workload")
     batched = None if args.no_batched else batched_vs_plain(ctx, args.batched_tasks, stream)
+    log("batched done; serving loop")
+    serving = None if args.no_serve else serve_trace(ctx, args.serve_rate, args.serve_seconds)
+    log("serving done; CPU baseline")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(gens, S, N)
 
@@ -182,6 +193,7 @@ def main():
         "per_generator": per_gen,
         "dtype_sweep": extra,
         "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -266,6 +278,65 @@ def batched_vs_plain(ctx, ntasks, stream):
             "plain_sample_tasks": done, "plain_sample_numbers": plain_numbers,
             "plain_ms": round(plain_ms, 3), "plain_numbers_per_s": plain_numbers / (plain_ms * 1e-3),
             "speedup": (total / (ms * 1e-3)) / (plain_numbers / (plain_ms * 1e-3))}
+
+
+def serve_trace(ctx, rate, seconds):
+    """Poisson arrivals (rate/s for `seconds`), generator and dtype uniform,
+    stream ids uniform in [0, 1e19), lengths log-uniform in [1e3, 1e8],
+    submitted to the native serving loop at their arrival times; the client
+    releases each output as soon as it is reported complete (outputs stay in
+    HBM, no copy to the host)."""
+    from paper_1307_5869_amd import prand as P
+    from paper_1307_5869_amd import workloads as W
+
+    t_arr, gens, ids, ns, dts = W.serving_requests(rate=rate, seconds=seconds)
+    cfg = P.ServerConfig(hbm_budget=64 << 30)
+    srv = P.Server(ctx, cfg)
+    lat, numbers, rejected = [], 0, 0
+    first_t, last_t = None, 0.0
+    t0 = srv.clock()
+    next_log = 10.0
+
+    def collect(wait_ms=0):
+        nonlocal numbers, first_t, last_t
+        for c in srv.poll(wait_ms=wait_ms):
+            lat.append(c.t_done - (t0 + t_arr[c.tag]))   # from the scheduled arrival
+            numbers += c.n
+            first_t = c.t_submit if first_t is None else min(first_t, c.t_submit)
+            last_t = max(last_t, c.t_done)
+            srv.release(c.ticket)
+
+    for k in range(len(t_arr)):
+        while True:
+            dt = t0 + t_arr[k] - srv.clock()
+            if dt <= 0:
+                break
+            collect()
+            if dt > 2e-4:
+                time.sleep(min(dt, 1e-3))
+        rc, _ = srv.try_submit(int(gens[k]), int(ids[k]), int(ns[k]), int(dts[k]), tag=k)
+        if rc != P.OK:
+            rejected += 1
+        if t_arr[k] >= next_log:
+            log(f"serving: {k + 1} submitted, {len(lat)} complete at t={t_arr[k]:.0f}s")
+            next_log += 10.0
+    deadline = time.time() + 120
+    while len(lat) + rejected < len(t_arr) and time.time() < deadline:
+        collect(wait_ms=50)
+    st = srv.stats()
+    srv.close()
+    lat_ms = np.array(lat) * 1e3
+    span = last_t - (first_t or 0.0)
+    offered = float(ns.sum()) / seconds
+    return {"requests": int(len(t_arr)), "completed": len(lat), "rejected": rejected, "rate_per_s": rate,
+            "seconds": seconds, "offered_numbers_per_s": offered,
+            "sustained_numbers_per_s": numbers / span if span > 0 else None,
+            "p50_ms": float(np.percentile(lat_ms, 50)) if lat else None,
+            "p99_ms": float(np.percentile(lat_ms, 99)) if lat else None,
+            "max_ms": float(lat_ms.max()) if lat else None,
+            "hbm_budget": st["hbm_budget"], "hbm_peak": st["hbm_peak"], "iterations": st["iterations"],
+            "gpu_busy_frac": st["gpu_busy_s"] / span if span > 0 else None,
+            "workload": "Poisson arrivals, gen and dtype uniform, ids uniform in [0,1e19), n log-uniform [1e3,1e8]"}
 
 
 def cpu_baseline(gens, S, N):

@@ -82,6 +82,7 @@ enum prand_variant {
 #define PRAND_EHIP (-4)          /* HIP runtime error, see prand_last_hip_error() */
 #define PRAND_ENOMEM (-5)        /* allocation failed */
 #define PRAND_ENODEV (-6)        /* no usable gfx950 device */
+#define PRAND_EBUSY (-7)         /* serving queue full: request rejected */
 
 typedef struct prand_ctx prand_ctx;
 
@@ -206,6 +207,87 @@ int prand_batch_destroy(prand_batch* batch);
    environment variable PRAND_TUNE_CACHE names a file, results are kept there
    keyed by the device and a signature of the task mix, and reused.  Blocks. */
 int prand_batch_autotune(prand_ctx* ctx, const prand_task* h_tasks, uint32_t ntasks, prand_batch_config* best);
+
+
+/* ------------------------------------------------------------------------
+ * Serving loop: a native request loop over one device.  Requests (generator,
+ * stream id, length, dtype) arrive at any time from any thread; a worker
+ * thread admits them while their output and state fit in a fixed HBM budget,
+ * initialises each request's stream by block splitting on a second HIP
+ * stream, and runs continuous batching: every loop iteration is one batched
+ * persistent launch holding the next chunk of every admitted request, so
+ * short requests finish while long ones are still running.  States stay on
+ * the device between iterations; outputs stay on the device until released.
+ * A request's output equals prand_init_stream(id) followed by generation of n
+ * outputs, whatever else is being served.
+ * ------------------------------------------------------------------------ */
+typedef struct prand_server prand_server;
+
+typedef struct prand_server_config {
+  uint64_t hbm_budget;      /* bytes of device memory for outputs and states (0: 16 GiB);
+                               reserved by prand_server_create */
+  uint64_t iter_numbers;    /* outputs per loop iteration over all requests (0: 2^28) */
+  uint64_t min_chunk;       /* smallest per-request share of an iteration (0: 2^16) */
+  uint64_t mt_chunk;        /* largest MT19937 chunk per iteration (one wavefront each; 0: 2^20) */
+  uint32_t max_active;      /* requests generating at once (0: 8192) */
+  uint32_t max_queue;       /* waiting requests beyond which submissions are rejected (0: 2^20) */
+  uint32_t waves_per_cu;    /* batched-kernel shape, as prand_batch_config (0: defaults) */
+  uint32_t reg_section;
+  uint32_t gm_section;
+  uint32_t pad;
+} prand_server_config;
+
+typedef struct prand_request {
+  int32_t gen;              /* enum prand_gen */
+  int32_t variant;          /* enum prand_variant (stream initialisation) */
+  int32_t dtype;            /* enum prand_dtype */
+  int32_t pad;
+  uint64_t stream_id;       /* block-splitting stream number */
+  uint64_t n;               /* outputs, 1 <= n <= 2^40 */
+  uint64_t tag;             /* caller's value, returned in the completion */
+} prand_request;
+
+typedef struct prand_completion {
+  uint64_t ticket;
+  uint64_t tag;
+  uint64_t n;
+  int32_t gen;
+  int32_t dtype;
+  void* out;                /* device array of n values; valid until prand_server_release(ticket) */
+  void* state;              /* device state blob: the stream advanced by n; same lifetime */
+  double t_submit;          /* seconds on the server clock (prand_server_clock) */
+  double t_admit;           /* memory reserved, initialisation enqueued */
+  double t_done;            /* the worker saw the last chunk's launch complete */
+} prand_completion;
+
+typedef struct prand_server_stats {
+  uint64_t submitted, admitted, rejected, completed, released;
+  uint64_t numbers;         /* outputs of completed requests */
+  uint64_t iterations;      /* batched launches */
+  uint64_t hbm_budget, hbm_used, hbm_peak;
+  uint32_t waiting, active; /* requests waiting for memory / admitted and not complete */
+  double gpu_busy_s;        /* summed duration of the batched launches */
+} prand_server_stats;
+
+/* Start a server on the context's device (cfg NULL: defaults).  Blocks until
+   the budget is reserved and the worker runs. */
+int prand_server_create(prand_ctx* ctx, const prand_server_config* cfg, prand_server** server);
+/* Queue a request.  PRAND_EINVAL for a bad field, PRAND_EUNSUPPORTED for a
+   variant the generator lacks, PRAND_ERANGE when its output and state could
+   never fit the budget, PRAND_EBUSY when the queue is full; otherwise
+   *ticket identifies it.  Thread-safe, does not block on the device. */
+int prand_server_submit(prand_server* server, const prand_request* req, uint64_t* ticket);
+/* Move up to max completions into out[], oldest first; waits up to wait_ms
+   milliseconds for the first one (0: no wait). */
+int prand_server_poll(prand_server* server, prand_completion* out, uint32_t max, uint32_t* count, int wait_ms);
+/* Give back a completed request's output and state memory. */
+int prand_server_release(prand_server* server, uint64_t ticket);
+int prand_server_get_stats(prand_server* server, prand_server_stats* stats);
+/* Seconds since the server started (the clock of the completion times). */
+double prand_server_clock(const prand_server* server);
+/* Stop the worker after the admitted requests have finished and free
+   everything, including unreleased outputs. */
+int prand_server_destroy(prand_server* server);
 
 #ifdef __cplusplus
 }

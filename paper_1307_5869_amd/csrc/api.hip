@@ -153,6 +153,11 @@ __global__ void section_dist_kernel(uint64_t* d, uint32_t nb, uint64_t seclen, u
 
 }  // namespace
 
+int prand::ensure_mt_tables(prand_ctx* c) {
+  DeviceGuard g(c->device);
+  return ensure_mt_locked(c, PRAND_MT19937);
+}
+
 extern "C" {
 
 const char* prand_strerror(int code) {
@@ -164,6 +169,7 @@ const char* prand_strerror(int code) {
     case PRAND_EHIP: return "HIP runtime error";
     case PRAND_ENOMEM: return "out of memory";
     case PRAND_ENODEV: return "no usable gfx950 device";
+    case PRAND_EBUSY: return "request queue full";
     default: return "unknown error";
   }
 }

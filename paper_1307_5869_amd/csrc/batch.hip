@@ -73,7 +73,79 @@ void fill_defaults(prand_batch_config& c) {
   c.gm_section = std::max<uint32_t>(32, c.gm_section);
 }
 
-int plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, std::vector<BatchTile>& tiles) {
+void free_batch(prand_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  (void)hipFree(b->d_tiles);
+  (void)hipFree(b->d_tasks);
+  (void)hipFree(b->d_counter);
+  delete b;
+}
+
+hipError_t enqueue(prand_batch* b, hipStream_t st) {
+  return launch_batch(b->ctx->T, b->d_tiles, b->ntiles, b->d_tasks, b->d_counter, b->blocks, st);
+}
+
+std::string signature(prand_ctx* c, const prand_task* tasks, uint32_t ntasks) {
+  // task count, then per (generator, dtype): tasks and total outputs (2 digits)
+  std::map<int, std::pair<uint64_t, double>> mix;
+  for (uint32_t k = 0; k < ntasks; k++) {
+    auto& m = mix[tasks[k].gen * 4 + tasks[k].dtype];
+    m.first++;
+    m.second += (double)tasks[k].n;
+  }
+  char buf[96];
+  std::string s = std::string(c->arch) + "/" + std::to_string(c->num_cus) + "/" + std::to_string(ntasks);
+  for (auto& kv : mix) {
+    std::snprintf(buf, sizeof buf, "/%d.%d:%llu:%.1e", kv.first / 4, kv.first % 4, (unsigned long long)kv.second.first,
+                  kv.second.second);
+    s += buf;
+  }
+  return s;
+}
+
+bool cache_lookup(const std::string& key, prand_batch_config* cfg) {
+  const char* path = getenv("PRAND_TUNE_CACHE");
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[4096];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    char* tab = std::strchr(line, '\t');
+    if (!tab) continue;
+    *tab = 0;
+    unsigned w, r, g;
+    if (key == line && std::sscanf(tab + 1, "%u %u %u", &w, &r, &g) == 3) {
+      cfg->waves_per_cu = w;
+      cfg->reg_section = r;
+      cfg->gm_section = g;
+      cfg->use_graph = 1;
+      found = true;   // the last entry for a key wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const std::string& key, const prand_batch_config& cfg) {
+  const char* path = getenv("PRAND_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s\t%u %u %u\n", key.c_str(), cfg.waves_per_cu, cfg.reg_section, cfg.gm_section);
+  std::fclose(f);
+}
+
+}  // namespace
+
+namespace prand {
+
+void batch_fill_defaults(prand_batch_config& c) { fill_defaults(c); }
+
+int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, std::vector<BatchTile>& tiles) {
   std::vector<std::pair<double, BatchTile>> work;
   for (uint32_t k = 0; k < ntasks; k++) {
     const prand_task& t = tasks[k];
@@ -150,73 +222,7 @@ int plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg
   return PRAND_OK;
 }
 
-void free_batch(prand_batch* b) {
-  if (!b) return;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->cap) (void)hipStreamDestroy(b->cap);
-  (void)hipFree(b->d_tiles);
-  (void)hipFree(b->d_tasks);
-  (void)hipFree(b->d_counter);
-  delete b;
-}
-
-hipError_t enqueue(prand_batch* b, hipStream_t st) {
-  return launch_batch(b->ctx->T, b->d_tiles, b->ntiles, b->d_tasks, b->d_counter, b->blocks, st);
-}
-
-std::string signature(prand_ctx* c, const prand_task* tasks, uint32_t ntasks) {
-  // task count, then per (generator, dtype): tasks and total outputs (2 digits)
-  std::map<int, std::pair<uint64_t, double>> mix;
-  for (uint32_t k = 0; k < ntasks; k++) {
-    auto& m = mix[tasks[k].gen * 4 + tasks[k].dtype];
-    m.first++;
-    m.second += (double)tasks[k].n;
-  }
-  char buf[96];
-  std::string s = std::string(c->arch) + "/" + std::to_string(c->num_cus) + "/" + std::to_string(ntasks);
-  for (auto& kv : mix) {
-    std::snprintf(buf, sizeof buf, "/%d.%d:%llu:%.1e", kv.first / 4, kv.first % 4, (unsigned long long)kv.second.first,
-                  kv.second.second);
-    s += buf;
-  }
-  return s;
-}
-
-bool cache_lookup(const std::string& key, prand_batch_config* cfg) {
-  const char* path = getenv("PRAND_TUNE_CACHE");
-  if (!path) return false;
-  FILE* f = std::fopen(path, "r");
-  if (!f) return false;
-  char line[4096];
-  bool found = false;
-  while (std::fgets(line, sizeof line, f)) {
-    char* tab = std::strchr(line, '\t');
-    if (!tab) continue;
-    *tab = 0;
-    unsigned w, r, g;
-    if (key == line && std::sscanf(tab + 1, "%u %u %u", &w, &r, &g) == 3) {
-      cfg->waves_per_cu = w;
-      cfg->reg_section = r;
-      cfg->gm_section = g;
-      cfg->use_graph = 1;
-      found = true;   // the last entry for a key wins
-    }
-  }
-  std::fclose(f);
-  return found;
-}
-
-void cache_store(const std::string& key, const prand_batch_config& cfg) {
-  const char* path = getenv("PRAND_TUNE_CACHE");
-  if (!path) return;
-  FILE* f = std::fopen(path, "a");
-  if (!f) return;
-  std::fprintf(f, "%s\t%u %u %u\n", key.c_str(), cfg.waves_per_cu, cfg.reg_section, cfg.gm_section);
-  std::fclose(f);
-}
-
-}  // namespace
+}  // namespace prand
 
 extern "C" {
 
@@ -229,7 +235,7 @@ int prand_batch_create(prand_ctx* c, const prand_task* h_tasks, uint32_t ntasks,
   if (cfg) conf = *cfg;
   fill_defaults(conf);
   std::vector<BatchTile> tiles;
-  int rc = plan(h_tasks, ntasks, conf, tiles);
+  int rc = batch_plan(h_tasks, ntasks, conf, tiles);
   if (rc) return rc;
   DeviceGuard g(c->device);
   prand_batch* b = new (std::nothrow) prand_batch;

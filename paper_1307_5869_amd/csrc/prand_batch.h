@@ -2,6 +2,8 @@
 // planner (batch.hip) and the persistent kernel (k_batch.hip).
 #pragma once
 
+#include <vector>
+
 #include "prand_impl.h"
 
 namespace prand {
@@ -31,6 +33,11 @@ struct BatchTile {
   uint64_t len32;      // v = 1 GM/GQ tiles: the common length of the live
                        // sections; copy tiles: 32-bit words of the state
 };
+
+// zero fields of a configuration replaced by the defaults
+void batch_fill_defaults(prand_batch_config& c);
+// cut tasks into tiles, longest first (PRAND_OK or an error code)
+int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, std::vector<BatchTile>& tiles);
 
 hipError_t launch_batch(const DeviceTables& T, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
                         uint32_t* counter, uint32_t blocks, hipStream_t st);

@@ -165,6 +165,9 @@ struct prand_ctx {
 };
 
 namespace prand {
+// build and upload the MT19937 jump polynomials once per context
+int ensure_mt_tables(prand_ctx* c);
+
 inline int hipfail(prand_ctx* c, hipError_t e) {
   if (c) c->last_hip = (int)e;
   return PRAND_EHIP;

@@ -18,7 +18,7 @@ NUM_GENERATORS = 11
 NAMES = ["MT19937", "MRG32K3A", "LFSR113", "GM19", "GM29", "GM31", "GM55", "GM61", "GQ58.1", "GQ58.3", "GQ58.4"]
 U32, F32, F64 = 0, 1, 2
 SEQ_DEFAULT, SEQ, SEQ_SHORT, SEQ_MEDIUM, SEQ_LONG = range(5)
-OK, EINVAL, EUNSUPPORTED, ERANGE, EHIP, ENOMEM, ENODEV = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EUNSUPPORTED, ERANGE, EHIP, ENOMEM, ENODEV, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 MAX_LIMBS = 8
 
 _u64, _u32, _i32, _vp, _sz = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
@@ -44,6 +44,13 @@ _SIGNATURES = {
     "prand_batch_tiles": (_i32, [_vp, ctypes.POINTER(_u32)]),
     "prand_batch_destroy": (_i32, [_vp]),
     "prand_batch_autotune": (_i32, [_vp, _vp, _u32, _vp]),
+    "prand_server_create": (_i32, [_vp, _vp, ctypes.POINTER(_vp)]),
+    "prand_server_submit": (_i32, [_vp, _vp, ctypes.POINTER(_u64)]),
+    "prand_server_poll": (_i32, [_vp, _vp, _u32, ctypes.POINTER(_u32), _i32]),
+    "prand_server_release": (_i32, [_vp, _u64]),
+    "prand_server_get_stats": (_i32, [_vp, _vp]),
+    "prand_server_clock": (ctypes.c_double, [_vp]),
+    "prand_server_destroy": (_i32, [_vp]),
 }
 
 
@@ -57,6 +64,41 @@ class BatchConfig(ctypes.Structure):
     """struct prand_batch_config (zeros select the defaults)"""
     _fields_ = [("waves_per_cu", ctypes.c_uint32), ("reg_section", ctypes.c_uint32),
                 ("gm_section", ctypes.c_uint32), ("use_graph", ctypes.c_uint32)]
+
+
+
+class ServerConfig(ctypes.Structure):
+    """struct prand_server_config (zeros select the defaults)"""
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("iter_numbers", ctypes.c_uint64), ("min_chunk", ctypes.c_uint64),
+                ("mt_chunk", ctypes.c_uint64), ("max_active", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
+                ("waves_per_cu", ctypes.c_uint32), ("reg_section", ctypes.c_uint32),
+                ("gm_section", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    """struct prand_request"""
+    _fields_ = [("gen", ctypes.c_int32), ("variant", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("stream_id", ctypes.c_uint64), ("n", ctypes.c_uint64),
+                ("tag", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    """struct prand_completion"""
+    _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("n", ctypes.c_uint64),
+                ("gen", ctypes.c_int32), ("dtype", ctypes.c_int32), ("out", ctypes.c_void_p),
+                ("state", ctypes.c_void_p), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    """struct prand_server_stats"""
+    _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "admitted", "rejected", "completed", "released",
+                                                "numbers", "iterations", "hbm_budget", "hbm_used", "hbm_peak")] + \
+               [("waiting", ctypes.c_uint32), ("active", ctypes.c_uint32), ("gpu_busy_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
 
 _lib = None
 
@@ -256,6 +298,67 @@ def autotune(ctx, tasks):
     _chk(ctx.lib.prand_batch_autotune(ctx.handle, ctypes.cast(arr, _vp), len(tasks), ctypes.byref(best)),
          "prand_batch_autotune")
     return best
+
+
+class Server:
+    """A serving loop (prand_server_*) on a context's device."""
+
+    def __init__(self, ctx, config=None):
+        self.ctx = ctx
+        h = _vp()
+        cfg = ctypes.byref(config) if config is not None else None
+        _chk(ctx.lib.prand_server_create(ctx.handle, cfg, ctypes.byref(h)), "prand_server_create")
+        self.handle = h
+        self._buf = (Completion * 1024)()
+
+    def submit(self, gen, stream_id, n, dtype=U32, variant=SEQ_DEFAULT, tag=0):
+        """Queue a request; returns its ticket (raises PrandError when rejected)."""
+        req = Request(gen, variant, dtype, 0, stream_id, n, tag)
+        t = _u64()
+        _chk(self.ctx.lib.prand_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)), "prand_server_submit")
+        return t.value
+
+    def try_submit(self, gen, stream_id, n, dtype=U32, variant=SEQ_DEFAULT, tag=0):
+        """As submit, but returns (rc, ticket) without raising."""
+        req = Request(gen, variant, dtype, 0, stream_id, n, tag)
+        t = _u64()
+        rc = self.ctx.lib.prand_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t))
+        return rc, t.value
+
+    def poll(self, wait_ms=0, max_items=1024):
+        """Completed requests (Completion structs copied out), oldest first."""
+        n = _u32()
+        m = min(max_items, len(self._buf))
+        _chk(self.ctx.lib.prand_server_poll(self.handle, self._buf, m, ctypes.byref(n), int(wait_ms)),
+             "prand_server_poll")
+        out = []
+        for i in range(n.value):
+            c = Completion()
+            ctypes.pointer(c)[0] = self._buf[i]
+            out.append(c)
+        return out
+
+    def release(self, ticket):
+        _chk(self.ctx.lib.prand_server_release(self.handle, ticket), "prand_server_release")
+
+    def stats(self):
+        st = ServerStats()
+        _chk(self.ctx.lib.prand_server_get_stats(self.handle, ctypes.byref(st)), "prand_server_get_stats")
+        return st.as_dict()
+
+    def clock(self):
+        return self.ctx.lib.prand_server_clock(self.handle)
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.prand_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def __getattr__(name):

@@ -23,7 +23,9 @@ def lib():
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(prand_[a-z0-9_]+)\s*\(", text)))
+    # declarations start a line with their return type
+    pat = r"^(?:int|size_t|double|const char\*)\s+(prand_[a-z0-9_]+)\s*\("
+    return sorted(set(re.findall(pat, text, flags=re.M)))
 
 
 def test_header_declares_the_abi():
