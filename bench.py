@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-dtype-sweep", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the steps, one 1 GiB device-to-device copy (a plain copy kernel of known size, "
+                         "the scale for hardware byte counters)")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--batched-tasks", type=int, default=20000)
@@ -140,7 +143,7 @@ def main():
                     "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["avg_ms"] = t * 1e3
-    roof["traffic"] = None
+    roof["traffic"] = recorded_traffic(roof["kernel"])
 
     extra = {}
     if not args.no_dtype_sweep:
@@ -164,6 +167,13 @@ def main():
 
     del out, states
     torch.cuda.empty_cache()
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log("C2 step done; batched workload")
     batched = None if args.no_batched else batched_vs_plain(ctx, args.batched_tasks, stream)
     log("batched done; serving loop")
@@ -198,6 +208,32 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summaries (FETCH_SIZE and WRITE_SIZE runs scaled by a copy kernel of known
+    size), or None when none covers this kernel or its sources have changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+
+    names = {"MT19937 jump": "mt_jump_kernel"}
+    want = names.get(kernel)
+    if want is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_1307_5869_amd", "csrc")
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for m in re.finditer(r"traffic kernel=(\S+) bytes=(\d+) sources=(\S+) sha256_16=([0-9a-f]+)", open(path).read()):
+            if m.group(1) != want:
+                continue
+            h = hashlib.sha256()
+            for f in m.group(3).split("+"):
+                h.update(open(os.path.join(csrc, f), "rb").read())
+            if h.hexdigest()[:16] == m.group(4):
+                return float(m.group(2))
+    return None
 
 
 def batched_vs_plain(ctx, ntasks, stream):
@@ -268,9 +304,33 @@ def batched_vs_plain(ctx, ntasks, stream):
         plain_ms += a.elapsed_time(z)
         done += len(chunk)
         plain_numbers += int(lens[chunk].sum())
+    # plain, sectioned: one prand_generate call per task (the task's sections
+    # jump to their starts and fill in parallel; the call copies the state in
+    # and out and blocks), over the same random order until about 5 s
+    host_states = {}
+    for k in order[:2000]:
+        g, _, n, pin, _, _ = tasks[k]
+        sin_g, st_g = sin[g]
+        j = int(np.nonzero(sin_g == k)[0][0])
+        host_states[k] = st_g[j * sb[g]:(j + 1) * sb[g]].cpu().numpy().copy()
+    torch.cuda.synchronize()
+    sec_s, sec_done, sec_numbers = 0.0, 0, 0
+    for k in order[:2000]:
+        g, _, n, _, _, pout = tasks[k]
+        t0 = time.perf_counter()
+        ctx.generate(g, host_states[k], P.F32, pout, n, stream)
+        sec_s += time.perf_counter() - t0
+        sec_done += 1
+        sec_numbers += n
+        if sec_s > 5.0:
+            break
     del out
     torch.cuda.empty_cache()
     return {"tasks": ntasks, "numbers": total, "dtype": "f32", "tiles": tiles,
+            "plain_sectioned_tasks": sec_done, "plain_sectioned_numbers": sec_numbers,
+            "plain_sectioned_s": round(sec_s, 3),
+            "plain_sectioned_numbers_per_s": sec_numbers / sec_s,
+            "speedup_vs_sectioned": (total / (ms * 1e-3)) / (sec_numbers / sec_s),
             "config": {"waves_per_cu": best.waves_per_cu, "reg_section": best.reg_section,
                        "gm_section": best.gm_section, "graph": bool(best.use_graph)},
             "autotune_s": round(tune_s, 2), "batched_ms": round(ms, 3),

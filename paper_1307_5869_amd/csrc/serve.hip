@@ -1,23 +1,28 @@
 // Serving loop: continuous batching of generate requests over one device.
 //
-// One worker thread owns the device work.  Each turn of its loop it
+// One worker thread owns the device work.  Requests are served in two lanes
+// that run concurrently on their own HIP streams: MT19937 (one wavefront per
+// chunk, so its chunks are long) and every other generator.  Each turn of
+// the worker's loop it
 //  1. takes newly submitted requests into a FIFO of waiting requests and
 //     applies the releases clients have made;
-//  2. admits waiting requests while their output and two state slots fit in
-//     the HBM arena reserved at creation (a later request may pass an earlier
-//     one that does not fit, unless the earlier one has waited too long), and
-//     initialises their streams by block splitting on the init stream: one
-//     jump launch per (generator, variant) group into a staging area, then a
-//     scatter into each request's first state slot;
-//  3. enqueues one loop iteration on the generation stream: a batched
-//     persistent launch holding the next chunk of every request whose stream
-//     is initialised.  Chunks are an equal share of the iteration's output
-//     budget (never below the minimum chunk; MT19937 chunks are capped since
-//     one wavefront generates each); a request's state ping-pongs between its
-//     two slots, so consecutive chunks continue the stream exactly;
-//  4. with two iterations in flight, waits for the older one and reports the
-//     requests whose last chunk it held as complete.
-// Outputs and final states stay in the arena until the client releases them.
+//  2. reports the requests whose last chunk a finished launch held as
+//     complete, and marks the requests of a finished initialisation ready;
+//  3. per lane, when no initialisation is in flight, admits waiting requests
+//     while their output and two state slots fit in the HBM arena reserved at
+//     creation (a later request may pass an earlier one that does not fit,
+//     unless the earlier one has waited too long), and initialises their
+//     streams by block splitting: one jump launch per (generator, variant)
+//     group into a staging area, then a scatter into each request's first
+//     state slot;
+//  4. per lane, with fewer than two launches in flight, enqueues one loop
+//     iteration: a batched persistent launch holding the next chunk of every
+//     ready request of the lane.  Chunks are an equal share of the
+//     iteration's output budget (never below the minimum chunk; MT19937
+//     chunks are capped); a request's state ping-pongs between its two slots,
+//     so consecutive chunks continue the stream exactly.
+// Completion is observed by polling events, so one lane never waits for the
+// other.  Outputs and final states stay in the arena until released.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -151,6 +156,18 @@ struct IterSlot {
   uint64_t seq = 0;
 };
 
+// MT19937 requests, and all the others
+constexpr int kLanes = 2;
+int lane_of(int gen) { return gen == PRAND_MT19937 ? 0 : 1; }
+
+struct Lane {
+  hipStream_t init_st = nullptr, gen_st = nullptr;
+  InitBatch init;
+  IterSlot slot[2];
+  std::vector<Req*> active;      // admitted, not complete
+  uint64_t iter_seq = 0;
+};
+
 }  // namespace
 
 struct prand_server {
@@ -175,12 +192,8 @@ struct prand_server {
 
   // worker only
   char* d_arena = nullptr;
-  hipStream_t gen_st = nullptr, init_st = nullptr;
   std::deque<Req*> waiting;
-  std::vector<Req*> active;
-  InitBatch init;
-  IterSlot slot[2];
-  uint64_t iter_seq = 0;
+  Lane lane[kLanes];
   std::vector<BatchTile> tiles;
   std::vector<prand_task> tasks;
 
@@ -235,19 +248,32 @@ hipError_t grow_slot(prand_server* s, IterSlot& sl, uint32_t ntasks, uint32_t nt
   return e;
 }
 
-// Admit waiting requests (memory, activity and batch limits) and enqueue
-// their stream initialisation.  Worker thread; takes s->mu for the arena.
-int admit_and_init(prand_server* s) {
-  InitBatch& ib = s->init;
+size_t active_total(const prand_server* s) {
+  size_t n = 0;
+  for (const Lane& l : s->lane) n += l.active.size();
+  return n;
+}
+
+// Admit waiting requests of lane li (memory, activity and batch limits) and
+// enqueue their stream initialisation.  Worker thread; takes s->mu for the
+// arena and the active lists.
+int admit_and_init(prand_server* s, int li) {
+  Lane& L = s->lane[li];
+  InitBatch& ib = L.init;
   ib.reqs.clear();
   if (s->waiting.empty()) return PRAND_OK;
   const double t = s->now();
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    size_t limit = s->cfg.max_active > s->active.size() ? s->cfg.max_active - s->active.size() : 0;
+    const size_t act = active_total(s);
+    size_t limit = s->cfg.max_active > act ? s->cfg.max_active - act : 0;
     limit = std::min<size_t>(limit, kInitMax);
     for (auto it = s->waiting.begin(); it != s->waiting.end() && ib.reqs.size() < limit;) {
       Req* r = *it;
+      if (lane_of(r->r.gen) != li) {
+        ++it;
+        continue;
+      }
       uint64_t off;
       if (s->arena.alloc(r->bytes, &off)) {
         r->off = off;
@@ -265,6 +291,7 @@ int admit_and_init(prand_server* s) {
         ++it;
       }
     }
+    for (Req* r : ib.reqs) L.active.push_back(r);
     s->st.hbm_used = s->arena.used();
     s->st.hbm_peak = s->arena.peak();
   }
@@ -288,35 +315,36 @@ int admit_and_init(prand_server* s) {
     ib.h_items[i].words = sb / 4;
   }
   group_start.push_back(n);
-  hipError_t e = hipMemcpyAsync(ib.d_ids, ib.h_ids, n * sizeof(uint64_t), hipMemcpyHostToDevice, s->init_st);
+  hipError_t e = hipMemcpyAsync(ib.d_ids, ib.h_ids, n * sizeof(uint64_t), hipMemcpyHostToDevice, L.init_st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(ib.d_items, ib.h_items, n * sizeof(ScatterItem), hipMemcpyHostToDevice, s->init_st);
+    e = hipMemcpyAsync(ib.d_items, ib.h_items, n * sizeof(ScatterItem), hipMemcpyHostToDevice, L.init_st);
   if (e != hipSuccess) return hipfail(s->ctx, e);
   for (size_t k = 0; k + 1 < group_start.size(); k++) {
     const uint32_t a = group_start[k], b = group_start[k + 1];
     int rc = prand_init_streams_dev(s->ctx, ib.reqs[a]->r.gen, ib.reqs[a]->r.variant, nullptr, ib.d_ids + a, b - a,
-                                    ib.d_staging + (size_t)a * kStateSlot, s->init_st);
+                                    ib.d_staging + (size_t)a * kStateSlot, L.init_st);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(scatter_states_kernel, dim3((n + 3) / 4), dim3(256), 0, s->init_st, ib.d_items, n);
+  hipLaunchKernelGGL(scatter_states_kernel, dim3((n + 3) / 4), dim3(256), 0, L.init_st, ib.d_items, n);
   e = hipGetLastError();
-  if (e == hipSuccess) e = hipEventRecord(ib.ev, s->init_st);
+  if (e == hipSuccess) e = hipEventRecord(ib.ev, L.init_st);
   if (e != hipSuccess) return hipfail(s->ctx, e);
   ib.in_flight = true;
   return PRAND_OK;
 }
 
-// one loop iteration into slot sl; false when no request has work
-int enqueue_iteration(prand_server* s, IterSlot& sl, bool* launched) {
+// one loop iteration of lane L into its slot sl; *launched is false when no
+// request of the lane has work
+int enqueue_iteration(prand_server* s, Lane& L, IterSlot& sl, bool* launched) {
   *launched = false;
   uint64_t m = 0;
-  for (Req* r : s->active)
+  for (Req* r : L.active)
     if (r->ready && r->issued < r->r.n) m++;
   if (m == 0) return PRAND_OK;
   const uint64_t share = std::max<uint64_t>(s->cfg.min_chunk, s->cfg.iter_numbers / m);
   s->tasks.clear();
   sl.finishing.clear();
-  for (Req* r : s->active) {
+  for (Req* r : L.active) {
     if (!r->ready || r->issued >= r->r.n) continue;
     uint64_t chunk = std::min<uint64_t>(r->r.n - r->issued, share);
     if (r->r.gen == PRAND_MT19937) chunk = std::min<uint64_t>(chunk, s->cfg.mt_chunk);
@@ -339,24 +367,22 @@ int enqueue_iteration(prand_server* s, IterSlot& sl, bool* launched) {
   if (e != hipSuccess) return hipfail(s->ctx, e);
   std::memcpy(sl.h_tasks, s->tasks.data(), s->tasks.size() * sizeof(prand_task));
   std::memcpy(sl.h_tiles, s->tiles.data(), s->tiles.size() * sizeof(BatchTile));
-  e = hipMemcpyAsync(sl.d_tasks, sl.h_tasks, s->tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice, s->gen_st);
+  e = hipMemcpyAsync(sl.d_tasks, sl.h_tasks, s->tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice, L.gen_st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(sl.d_tiles, sl.h_tiles, s->tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice, s->gen_st);
-  if (e == hipSuccess) e = hipEventRecord(sl.start, s->gen_st);
+    e = hipMemcpyAsync(sl.d_tiles, sl.h_tiles, s->tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice, L.gen_st);
+  if (e == hipSuccess) e = hipEventRecord(sl.start, L.gen_st);
   if (e == hipSuccess)
-    e = launch_batch(s->ctx->T, sl.d_tiles, (uint32_t)s->tiles.size(), sl.d_tasks, sl.d_counter, s->blocks, s->gen_st);
-  if (e == hipSuccess) e = hipEventRecord(sl.end, s->gen_st);
+    e = launch_batch(s->ctx->T, sl.d_tiles, (uint32_t)s->tiles.size(), sl.d_tasks, sl.d_counter, s->blocks, L.gen_st);
+  if (e == hipSuccess) e = hipEventRecord(sl.end, L.gen_st);
   if (e != hipSuccess) return hipfail(s->ctx, e);
   sl.in_flight = true;
-  sl.seq = ++s->iter_seq;
+  sl.seq = ++L.iter_seq;
   *launched = true;
   return PRAND_OK;
 }
 
-// wait for slot sl and report the requests it finished
-int finish_slot(prand_server* s, IterSlot& sl) {
-  hipError_t e = hipEventSynchronize(sl.end);
-  if (e != hipSuccess) return hipfail(s->ctx, e);
+// slot sl of lane L has finished: report the requests it completed
+int finish_slot(prand_server* s, Lane& L, IterSlot& sl) {
   const double t = s->now();
   float ms = 0;
   (void)hipEventElapsedTime(&ms, sl.start, sl.end);
@@ -384,12 +410,67 @@ int finish_slot(prand_server* s, IterSlot& sl) {
     s->st.numbers += r->r.n;
   }
   if (!sl.finishing.empty()) {
-    s->active.erase(std::remove_if(s->active.begin(), s->active.end(),
-                                   [](const Req* r) { return r->complete; }),
-                    s->active.end());
+    L.active.erase(std::remove_if(L.active.begin(), L.active.end(), [](const Req* r) { return r->complete; }),
+                   L.active.end());
     s->cv_done.notify_all();
   }
   sl.finishing.clear();
+  return PRAND_OK;
+}
+
+// 1 when the event has completed, 0 when not yet, an error code otherwise
+int event_done(prand_server* s, hipEvent_t ev) {
+  const hipError_t e = hipEventQuery(ev);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  return hipfail(s->ctx, e);
+}
+
+// one turn of the worker: returns PRAND_OK and sets *progress when anything
+// moved
+int worker_turn(prand_server* s, bool* progress) {
+  *progress = false;
+  for (Lane& L : s->lane) {
+    // finished launches, oldest first
+    for (;;) {
+      IterSlot* oldest = nullptr;
+      for (IterSlot& sl : L.slot)
+        if (sl.in_flight && (!oldest || sl.seq < oldest->seq)) oldest = &sl;
+      if (!oldest) break;
+      const int d = event_done(s, oldest->end);
+      if (d < 0) return d;
+      if (!d) break;
+      int rc = finish_slot(s, L, *oldest);
+      if (rc) return rc;
+      *progress = true;
+    }
+    // finished initialisation: those requests may generate
+    if (L.init.in_flight) {
+      const int d = event_done(s, L.init.ev);
+      if (d < 0) return d;
+      if (d) {
+        for (Req* r : L.init.reqs) r->ready = true;
+        L.init.in_flight = false;
+        L.init.reqs.clear();
+        *progress = true;
+      }
+    }
+  }
+  for (int li = 0; li < kLanes; li++) {
+    Lane& L = s->lane[li];
+    if (!L.init.in_flight && !s->waiting.empty()) {
+      int rc = admit_and_init(s, li);
+      if (rc) return rc;
+      if (L.init.in_flight) *progress = true;
+    }
+    IterSlot* free_slot = !L.slot[0].in_flight ? &L.slot[0] : (!L.slot[1].in_flight ? &L.slot[1] : nullptr);
+    if (free_slot) {
+      bool launched = false;
+      int rc = enqueue_iteration(s, L, *free_slot, &launched);
+      if (rc) return rc;
+      if (launched) *progress = true;
+    }
+  }
   return PRAND_OK;
 }
 
@@ -397,6 +478,7 @@ void worker_main(prand_server* s) {
   DeviceGuard g(s->ctx->device);
   int rc = PRAND_OK;
   for (;;) {
+    bool device_busy = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       for (uint64_t t : s->release_q) {
@@ -418,59 +500,35 @@ void worker_main(prand_server* s) {
         s->waiting.clear();
       }
       s->st.waiting = (uint32_t)s->waiting.size();
-      s->st.active = (uint32_t)s->active.size();
-      const bool busy = !s->waiting.empty() || !s->active.empty() || s->init.in_flight || s->slot[0].in_flight ||
-                        s->slot[1].in_flight;
-      if (!busy) {
+      s->st.active = (uint32_t)active_total(s);
+      for (const Lane& L : s->lane)
+        device_busy |= L.init.in_flight || L.slot[0].in_flight || L.slot[1].in_flight || !L.active.empty();
+      if (!device_busy && s->waiting.empty()) {
         if (s->stop) break;
         s->cv_work.wait_for(lk, std::chrono::milliseconds(20));
         continue;
       }
     }
-    // initialisation finished: those requests may generate
-    if (s->init.in_flight && hipEventQuery(s->init.ev) == hipSuccess) {
-      for (Req* r : s->init.reqs) r->ready = true;
-      s->init.in_flight = false;
-      s->init.reqs.clear();
-    }
-    if (!s->init.in_flight && !s->waiting.empty()) {
-      rc = admit_and_init(s);
-      if (rc) break;
-      if (s->init.in_flight) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        for (Req* r : s->init.reqs) s->active.push_back(r);
+    bool progress = false;
+    rc = worker_turn(s, &progress);
+    if (rc) break;
+    if (!progress) {
+      if (device_busy) {
+        // launches in flight: poll again shortly
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+      } else {
+        // requests wait for memory and nothing runs: wait for a release
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->release_q.empty() && s->inbox.empty() && !s->stop)
+          s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
       }
-    }
-    // an iteration into a free slot (at most two in flight)
-    IterSlot* free_slot = !s->slot[0].in_flight ? &s->slot[0] : (!s->slot[1].in_flight ? &s->slot[1] : nullptr);
-    bool launched = false;
-    if (free_slot) {
-      rc = enqueue_iteration(s, *free_slot, &launched);
-      if (rc) break;
-    }
-    IterSlot* oldest = nullptr;
-    for (IterSlot& sl : s->slot)
-      if (sl.in_flight && (!oldest || sl.seq < oldest->seq)) oldest = &sl;
-    const bool both = s->slot[0].in_flight && s->slot[1].in_flight;
-    if (oldest && (both || !launched)) {
-      rc = finish_slot(s, *oldest);
-      if (rc) break;
-    } else if (!oldest && !launched && s->init.in_flight) {
-      hipError_t e = hipEventSynchronize(s->init.ev);
-      if (e != hipSuccess) {
-        rc = hipfail(s->ctx, e);
-        break;
-      }
-    } else if (!oldest && !launched) {
-      // admitted nothing (memory full) and nothing runs: wait for a release
-      std::unique_lock<std::mutex> lk(s->mu);
-      if (s->release_q.empty() && s->inbox.empty() && !s->stop)
-        s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
     }
   }
   if (rc) {
-    (void)hipStreamSynchronize(s->gen_st);
-    (void)hipStreamSynchronize(s->init_st);
+    for (Lane& L : s->lane) {
+      (void)hipStreamSynchronize(L.gen_st);
+      (void)hipStreamSynchronize(L.init_st);
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     s->error = rc;
     s->cv_done.notify_all();
@@ -480,28 +538,33 @@ void worker_main(prand_server* s) {
 void free_server(prand_server* s) {
   if (!s) return;
   DeviceGuard g(s->ctx->device);
-  if (s->gen_st) (void)hipStreamSynchronize(s->gen_st);
-  if (s->init_st) (void)hipStreamSynchronize(s->init_st);
-  for (IterSlot& sl : s->slot) {
-    (void)hipHostFree(sl.h_tasks);
-    (void)hipHostFree(sl.h_tiles);
-    (void)hipFree(sl.d_tasks);
-    (void)hipFree(sl.d_tiles);
-    (void)hipFree(sl.d_counter);
-    if (sl.start) (void)hipEventDestroy(sl.start);
-    if (sl.end) (void)hipEventDestroy(sl.end);
+  for (Lane& L : s->lane) {
+    if (L.gen_st) (void)hipStreamSynchronize(L.gen_st);
+    if (L.init_st) (void)hipStreamSynchronize(L.init_st);
   }
-  (void)hipHostFree(s->init.h_ids);
-  (void)hipHostFree(s->init.h_items);
-  (void)hipFree(s->init.d_ids);
-  (void)hipFree(s->init.d_items);
-  (void)hipFree(s->init.d_staging);
-  if (s->init.ev) (void)hipEventDestroy(s->init.ev);
-  if (s->gen_st) (void)hipStreamDestroy(s->gen_st);
-  if (s->init_st) (void)hipStreamDestroy(s->init_st);
+  for (Lane& L : s->lane) {
+    for (IterSlot& sl : L.slot) {
+      (void)hipHostFree(sl.h_tasks);
+      (void)hipHostFree(sl.h_tiles);
+      (void)hipFree(sl.d_tasks);
+      (void)hipFree(sl.d_tiles);
+      (void)hipFree(sl.d_counter);
+      if (sl.start) (void)hipEventDestroy(sl.start);
+      if (sl.end) (void)hipEventDestroy(sl.end);
+    }
+    InitBatch& ib = L.init;
+    (void)hipHostFree(ib.h_ids);
+    (void)hipHostFree(ib.h_items);
+    (void)hipFree(ib.d_ids);
+    (void)hipFree(ib.d_items);
+    (void)hipFree(ib.d_staging);
+    if (ib.ev) (void)hipEventDestroy(ib.ev);
+    if (L.gen_st) (void)hipStreamDestroy(L.gen_st);
+    if (L.init_st) (void)hipStreamDestroy(L.init_st);
+    for (Req* r : L.active) delete r;
+  }
   (void)hipFree(s->d_arena);
   for (Req* r : s->waiting) delete r;
-  for (Req* r : s->active) delete r;
   for (Req* r : s->inbox) delete r;
   for (auto& kv : s->finished) delete kv.second;
   delete s;
@@ -535,20 +598,22 @@ int prand_server_create(prand_ctx* c, const prand_server_config* cfg, prand_serv
   }
   s->arena.reset(s->cfg.hbm_budget);
   s->st.hbm_budget = s->cfg.hbm_budget;
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->gen_st, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->init_st, hipStreamNonBlocking);
-  InitBatch& ib = s->init;
-  if (e == hipSuccess) e = hipHostMalloc((void**)&ib.h_ids, kInitMax * sizeof(uint64_t), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&ib.h_items, kInitMax * sizeof(ScatterItem), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc((void**)&ib.d_ids, kInitMax * sizeof(uint64_t));
-  if (e == hipSuccess) e = hipMalloc((void**)&ib.d_items, kInitMax * sizeof(ScatterItem));
-  if (e == hipSuccess) e = hipMalloc((void**)&ib.d_staging, kInitMax * kStateSlot);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ib.ev, hipEventDisableTiming);
-  for (IterSlot& sl : s->slot) {
-    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_counter, 64);
-    if (e == hipSuccess) e = hipEventCreate(&sl.start);
-    if (e == hipSuccess) e = hipEventCreate(&sl.end);
-    if (e == hipSuccess) e = grow_slot(s, sl, 1024, 16384);
+  for (Lane& L : s->lane) {
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&L.gen_st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&L.init_st, hipStreamNonBlocking);
+    InitBatch& ib = L.init;
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ib.h_ids, kInitMax * sizeof(uint64_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ib.h_items, kInitMax * sizeof(ScatterItem), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&ib.d_ids, kInitMax * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&ib.d_items, kInitMax * sizeof(ScatterItem));
+    if (e == hipSuccess) e = hipMalloc((void**)&ib.d_staging, kInitMax * kStateSlot);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ib.ev, hipEventDisableTiming);
+    for (IterSlot& sl : L.slot) {
+      if (e == hipSuccess) e = hipMalloc((void**)&sl.d_counter, 64);
+      if (e == hipSuccess) e = hipEventCreate(&sl.start);
+      if (e == hipSuccess) e = hipEventCreate(&sl.end);
+      if (e == hipSuccess) e = grow_slot(s, sl, 1024, 16384);
+    }
   }
   if (e != hipSuccess) {
     free_server(s);
