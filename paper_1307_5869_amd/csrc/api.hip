@@ -89,10 +89,31 @@ hipError_t upload(T** dst, const T* src, size_t n) {
 hipError_t ensure_mt(prand_ctx* c) {
   // caller holds c->mu
   if (c->mt_ready) return hipSuccess;
-  std::vector<uint32_t> mt((size_t)kLadder * 624), dig((size_t)8 * 256 * 624);
-  if (!mt_build_polys(mt.data(), kLadder, dig.data(), kMtDigitE)) return hipErrorUnknown;
+  std::vector<uint32_t> mt((size_t)kLadder * 624), d12((size_t)kMtDig12Count * 4096 * 624),
+      d8((size_t)2 * 256 * 624);
+  if (!mt_build_polys(mt.data(), kLadder, d12.data(), d8.data(), kMtDigitE)) return hipErrorUnknown;
   hipError_t e = upload(&c->T.mt, mt.data(), mt.size());
-  if (e == hipSuccess) e = upload(&c->T.mtdig, dig.data(), dig.size());
+  if (e == hipSuccess) e = upload(&c->T.mtdig12, d12.data(), d12.size());
+  if (e == hipSuccess) e = upload(&c->T.mtdig8hi, d8.data(), d8.size());
+  // the default state jumped t * 2^(432 + 48) for every top-16-bit value t
+  // of an id, by the jump kernel's general digit path
+  uint64_t* d_ids = nullptr;
+  if (e == hipSuccess) e = hipMalloc(&c->T.mttop, (size_t)65536 * sizeof(MtState));
+  if (e == hipSuccess) e = hipMalloc((void**)&d_ids, 65536 * sizeof(uint64_t));
+  if (e == hipSuccess) {
+    std::vector<uint64_t> ids(65536);
+    for (uint64_t t = 0; t < 65536; t++) ids[t] = t << 48;
+    e = hipMemcpy(d_ids, ids.data(), ids.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) {
+    JumpSpec js;
+    js.ids = d_ids;
+    js.block_e = kMtDigitE;
+    e = launch_mt_jump(c->T, (MtState*)c->T.mttop, 65536, js,
+                       (const MtState*)((const char*)c->T.defaults + kDefaultStride * PRAND_MT19937), nullptr);
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  (void)hipFree(d_ids);
   if (e == hipSuccess) c->mt_ready = true;
   return e;
 }
@@ -243,7 +264,9 @@ int prand_ctx_destroy(prand_ctx* c) {
   (void)hipFree(c->T.lfsr);
   (void)hipFree(c->T.gm);
   (void)hipFree(c->T.mt);
-  (void)hipFree(c->T.mtdig);
+  (void)hipFree(c->T.mtdig12);
+  (void)hipFree(c->T.mtdig8hi);
+  (void)hipFree(c->T.mttop);
   (void)hipFree(c->T.defaults);
   (void)hipFree(c->scratch);
   delete c;
@@ -329,6 +352,7 @@ int prand_init_streams_dev(prand_ctx* c, int gen, int variant, const void* d_bas
   js.ids = d_ids;
   js.block_e = be;
   const void* base = d_base_state ? d_base_state : (const char*)c->T.defaults + kDefaultStride * gen;
+  if (!d_base_state && gen == PRAND_MT19937) js.mt_top = c->T.mttop;
   hipError_t e = launch_jump(c, gen, d_states, count, js, base, (hipStream_t)stream);
   return e == hipSuccess ? PRAND_OK : hipfail(c, e);
 }
@@ -347,6 +371,7 @@ int prand_init_stream(prand_ctx* c, int gen, int variant, uint64_t id, void* h_s
   JumpSpec js;
   js.ids = d_id;
   js.block_e = be;
+  if (gen == PRAND_MT19937) js.mt_top = c->T.mttop;
   if (e == hipSuccess)
     e = launch_jump(c, gen, d_state, 1, js, (const char*)c->T.defaults + kDefaultStride * gen, nullptr);
   if (e == hipSuccess) e = hipMemcpy(h_state, d_state, state_bytes(gen), hipMemcpyDeviceToHost);

@@ -14,12 +14,16 @@
 // being the raw-word sequence continued from the state.  A distance is applied
 // as one polynomial x^(2^b) mod phi (from the context ladder) per set bit b;
 // block splitting by id * 2^432 from a block-aligned state uses the context's
-// per-byte tables x^(d 2^(432 + 8j)) mod phi instead: at most 8 polynomials.
+// digit tables x^(d 2^(432 + position)) mod phi instead: four 12-bit digits for
+// the low 48 bits of the id and two bytes for the top 16 bits; from the
+// default state the top 16 bits come from a table of precomputed states, so a
+// stream costs at most 4 polynomials.
 // One wavefront does one stream: the sequence is produced 227 words at a time
 // into an LDS ring, and lane l accumulates outputs t = 10l .. 10l+9 while a
 // register window of 10 sequence words slides over the coefficients, so each
 // coefficient costs one LDS read per lane and, when set, 10 XORs.
 #include "dev_mt.h"
+#include "mt_poly.h"
 
 namespace prand {
 namespace {
@@ -98,13 +102,19 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
                                                      const uint64_t* __restrict__ dist, int nlimbs, int per_stream,
                                                      const uint64_t* __restrict__ ids, int block_e,
                                                      const MtState* __restrict__ base,
+                                                     const MtState* __restrict__ top,
                                                      const uint32_t* __restrict__ ladder,
-                                                     const uint32_t* __restrict__ digits) {
+                                                     const uint32_t* __restrict__ dig12,
+                                                     const uint32_t* __restrict__ dig8hi) {
   __shared__ uint32_t ring[kRing];
   const uint32_t s = blockIdx.x;
   if (s >= count) return;
   const int lane = threadIdx.x;
+  // block splitting from the default state: start from the precomputed
+  // state of the id's top 16 bits
+  const bool digit_path = ids && block_e == kMtDigitE;
   const MtState* src = base ? base : states + s;
+  if (digit_path && top) src = top + (ids[s] >> 48);
   uint64_t N[kMaxLimbs];
   for (int l = 0; l < kMaxLimbs; l++) N[l] = 0;
   if (ids) {
@@ -119,13 +129,22 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
   for (int i = lane; i < 624; i += 64) ring[i] = src->mt[i];
   uint32_t idx = src->idx < 624u ? src->idx : 624u;
   __syncthreads();
-  if (ids && block_e == kMtDigitE && idx == 624) {
-    // block splitting from a block-aligned state: id * 2^432 as 8 base-256
-    // digits, one table polynomial x^(d 2^(432 + 8j)) per nonzero digit
+  if (digit_path && idx == 624) {
+    // block splitting from a block-aligned state: id * 2^432 with the low 48
+    // bits of id as four 12-bit digits and the top 16 bits as two bytes, one
+    // table polynomial x^(d 2^(432 + position)) per nonzero digit; the top
+    // bytes are already in the start state when it came from the table of
+    // top-16-bit states
     const uint64_t id = ids[s];
-    for (int j = 0; j < 8; j++) {
-      const uint32_t d = (uint32_t)(id >> (8 * j)) & 255u;
-      if (d) apply_poly(ring, digits + ((size_t)j * 256 + d) * 624, lane);
+    for (int k = 0; k < kMtDig12Count; k++) {
+      const uint32_t d = (uint32_t)(id >> (12 * k)) & 4095u;
+      if (d) apply_poly(ring, dig12 + ((size_t)k * 4096 + d) * 624, lane);
+    }
+    if (!top) {
+      for (int j = 0; j < 2; j++) {
+        const uint32_t d = (uint32_t)(id >> (48 + 8 * j)) & 255u;
+        if (d) apply_poly(ring, dig8hi + ((size_t)j * 256 + d) * 624, lane);
+      }
     }
   } else {
     // consume the rest of the current block first
@@ -175,7 +194,7 @@ hipError_t launch_mt_generate(MtState* states, uint32_t count, uint64_t n, int d
 hipError_t launch_mt_jump(const DeviceTables& T, MtState* states, uint32_t count, const JumpSpec& js,
                           const MtState* base, hipStream_t st) {
   hipLaunchKernelGGL(mt_jump_kernel, dim3(count), dim3(64), 0, st, states, count, js.dist, js.nlimbs, js.per_stream,
-                     js.ids, js.block_e, base, T.mt, T.mtdig);
+                     js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdig12, T.mtdig8hi);
   return hipGetLastError();
 }
 

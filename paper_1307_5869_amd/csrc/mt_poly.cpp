@@ -14,6 +14,8 @@
 
 #include <wmmintrin.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -171,29 +173,69 @@ void store(const uint64_t* p, uint32_t* out) {
 
 }  // namespace
 
-bool mt_build_polys(uint32_t* ladder, int nladder, uint32_t* digits, int digit_e) {
+bool mt_build_polys(uint32_t* ladder, int nladder, uint32_t* dig12, uint32_t* dig8hi, int digit_e) {
   Field F;
   if (!F.init()) return false;
   std::vector<uint64_t> lad((size_t)nladder * kW, 0);
   lad[0] = 2;   // x
   for (int b = 0; b + 1 < nladder; b++) F.mulmod(&lad[(size_t)b * kW], &lad[(size_t)b * kW], &lad[(size_t)(b + 1) * kW]);
   for (int b = 0; b < nladder; b++) store(&lad[(size_t)b * kW], ladder + (size_t)b * kMtPolyWords);
-  if (digits) {
-    std::memset(digits, 0, sizeof(uint32_t) * 8 * 256 * kMtPolyWords);
-    std::vector<std::thread> th;
-    for (int j = 0; j < 8; j++) {
-      th.emplace_back([&, j]() {
-        const uint64_t* P = &lad[(size_t)(digit_e + 8 * j) * kW];
-        std::vector<uint64_t> g(P, P + kW), nxt(kW);
-        for (int d = 1; d < 256; d++) {
-          store(g.data(), digits + ((size_t)j * 256 + d) * kMtPolyWords);
+  if (!dig12 && !dig8hi) return true;
+  if (digit_e + 64 > nladder) return false;
+  // work items: (digit base exponent, digit width, first digit, last digit, output table)
+  struct Item {
+    int e, width;
+    uint32_t d0, d1;
+    uint32_t* out;
+  };
+  std::vector<Item> items;
+  if (dig12) {
+    std::memset(dig12, 0, sizeof(uint32_t) * kMtDig12Count * 4096 * kMtPolyWords);
+    for (int k = 0; k < kMtDig12Count; k++)
+      for (uint32_t d0 = 1; d0 < 4096; d0 += 256)
+        items.push_back({digit_e + 12 * k, 12, d0, std::min<uint32_t>(d0 + 256, 4096),
+                         dig12 + (size_t)k * 4096 * kMtPolyWords});
+  }
+  if (dig8hi) {
+    std::memset(dig8hi, 0, sizeof(uint32_t) * 2 * 256 * kMtPolyWords);
+    for (int j = 0; j < 2; j++)
+      items.push_back({digit_e + 12 * kMtDig12Count + 8 * j, 8, 1, 256, dig8hi + (size_t)j * 256 * kMtPolyWords});
+  }
+  // x^(d 2^e): the first digit of an item from the ladder (one factor per set
+  // bit), each next one by one more multiplication by x^(2^e)
+  std::atomic<size_t> next(0);
+  auto work = [&]() {
+    std::vector<uint64_t> g(kW), nxt(kW);
+    for (size_t i; (i = next.fetch_add(1)) < items.size();) {
+      const Item& it = items[i];
+      const uint64_t* P = &lad[(size_t)it.e * kW];
+      bool have = false;
+      for (int b = 0; b < it.width; b++) {
+        if (!((it.d0 >> b) & 1u)) continue;
+        const uint64_t* Q = &lad[(size_t)(it.e + b) * kW];
+        if (!have) {
+          std::copy(Q, Q + kW, g.begin());
+          have = true;
+        } else {
+          F.mulmod(g.data(), Q, nxt.data());
+          g.swap(nxt);
+        }
+      }
+      for (uint32_t d = it.d0; d < it.d1; d++) {
+        store(g.data(), it.out + (size_t)d * kMtPolyWords);
+        if (d + 1 < it.d1) {
           F.mulmod(g.data(), P, nxt.data());
           g.swap(nxt);
         }
-      });
+      }
     }
-    for (auto& t : th) t.join();
-  }
+  };
+  const unsigned hw = std::thread::hardware_concurrency();
+  const unsigned nth = std::max(1u, std::min(16u, hw ? hw : 1u));
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nth; t++) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
   return true;
 }
 

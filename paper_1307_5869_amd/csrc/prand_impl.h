@@ -72,7 +72,9 @@ struct DeviceTables {
   uint32_t* lfsr = nullptr;   // [kLadder][4][32]: columns of T_c^(2^b)
   uint64_t* gm = nullptr;     // [8][kLadder][4]: (a b; c d) = M^(2^b) mod p
   uint32_t* mt = nullptr;     // [kLadder][624]: bits of x^(2^b) mod phi (19937 used)
-  uint32_t* mtdig = nullptr;  // [8][256][624]: x^(d 2^(kMtDigitE + 8j)) mod phi
+  uint32_t* mtdig12 = nullptr;  // [4][4096][624]: x^(d 2^(kMtDigitE + 12k)) mod phi
+  uint32_t* mtdig8hi = nullptr; // [2][256][624]: x^(d 2^(kMtDigitE + 48 + 8j)) mod phi
+  void* mttop = nullptr;        // [65536] MtState: the default state jumped t 2^(kMtDigitE + 48)
   void* defaults = nullptr;   // default state of each generator, 11 x 2560 bytes
 };
 constexpr size_t kDefaultStride = 2560;
@@ -100,6 +102,9 @@ struct JumpSpec {
   int per_stream = 0;
   const uint64_t* ids = nullptr;
   int block_e = 0;
+  // MT19937 block splitting from the default state: the states of the top
+  // 16 bits of an id (DeviceTables::mttop), or null
+  const void* mt_top = nullptr;
 };
 
 hipError_t launch_mrg_generate(const DeviceTables& T, const MrgState* sin, MrgState* sout, uint32_t count,
