@@ -44,6 +44,7 @@ using namespace prand;
 namespace {
 
 constexpr uint32_t kInitMax = 4096;          // requests per initialisation batch
+constexpr uint32_t kInitItems = 16384;       // state slots filled per initialisation batch
 constexpr size_t kStateSlot = 2560;          // bytes per staged state (>= every state blob)
 constexpr uint64_t kAlign = 256;
 constexpr double kStarveS = 0.05;            // a waiting request older than this blocks bypassing
@@ -106,18 +107,30 @@ class Arena {
   uint64_t size_ = 0, used_ = 0, peak_ = 0;
 };
 
+// A contiguous run of a request's outputs, generated from its own state: a
+// request is one section, or (long MT19937 requests) up to kMaxSections that
+// start from jumped states and run in parallel.
+struct Section {
+  uint64_t start = 0, len = 0;
+  uint64_t issued = 0;           // outputs of the section enqueued
+  char* st[2] = {nullptr, nullptr};
+  int cur = 0;                   // slot holding the state after the enqueued chunks
+};
+
 struct Req {
   uint64_t ticket = 0;
   prand_request r{};
   double t_submit = 0, t_admit = 0, t_done = 0;
-  uint64_t off = 0, bytes = 0;   // arena block: output, then two state slots
+  uint64_t off = 0, bytes = 0;   // arena block: output, then the sections' state slots
   char* out = nullptr;
-  char* st[2] = {nullptr, nullptr};
-  int cur = 0;                   // slot holding the state after the enqueued chunks
-  uint64_t issued = 0;           // outputs enqueued
-  bool ready = false;            // stream initialised
+  std::vector<Section> secs;
+  uint64_t seclen = 0;           // outputs per section (all but the last)
+  uint64_t issued = 0;           // outputs enqueued over all sections
+  bool ready = false;            // streams initialised
   bool complete = false;         // last chunk finished
 };
+
+constexpr uint32_t kMaxSections = 64;
 
 struct ScatterItem {
   const uint32_t* src;
@@ -135,6 +148,8 @@ __global__ void scatter_states_kernel(const ScatterItem* __restrict__ items, uin
 struct InitBatch {
   uint64_t* h_ids = nullptr;     // pinned
   uint64_t* d_ids = nullptr;
+  uint64_t* h_dist = nullptr;    // pinned: section start distances
+  uint64_t* d_dist = nullptr;
   char* d_staging = nullptr;
   ScatterItem* h_items = nullptr;  // pinned
   ScatterItem* d_items = nullptr;
@@ -209,13 +224,53 @@ void fill_config(prand_server_config& c) {
   if (!c.iter_numbers) c.iter_numbers = 1ull << 28;
   if (!c.min_chunk) c.min_chunk = 1ull << 16;
   if (!c.mt_chunk) c.mt_chunk = 1ull << 20;
+  if (!c.mt_section) c.mt_section = 1ull << 22;
   if (!c.max_active) c.max_active = 8192;
   if (!c.max_queue) c.max_queue = 1u << 20;
 }
 
-uint64_t request_bytes(const prand_request& r) {
+// Sections of a request: MT19937 requests longer than mt_section are cut into
+// at most kMaxSections of 624 * 2^k outputs (k >= 12), so that every section
+// starts on a twist-block boundary of the stream (block-splitting states sit
+// on one) and its start distance has few set bits.  A jump yields the
+// canonical state, which differs from the sequentially reached one only in
+// bits the next twist overwrites; since every section starts with a twist,
+// outputs and the last section's final state equal sequential generation.
+uint64_t section_len(const prand_request& r, const prand_server_config& cfg) {
+  if (r.gen != PRAND_MT19937 || r.n <= cfg.mt_section) return r.n;
+  uint64_t len = 624ull << 12;
+  while ((r.n + len - 1) / len > kMaxSections) len <<= 1;
+  return len;
+}
+uint32_t section_count(const prand_request& r, const prand_server_config& cfg) {
+  const uint64_t len = section_len(r, cfg);
+  return (uint32_t)((r.n + len - 1) / len);
+}
+
+// arena block of a request: output, then the sections' first state slots
+// (contiguous, one state apart), then their second slots
+uint64_t request_bytes(const prand_request& r, const prand_server_config& cfg) {
   const uint64_t es = r.dtype == PRAND_F64 ? 8 : 4;
-  return align_up(r.n * es) + 2 * align_up(state_size(r.gen));
+  const uint64_t slots = align_up((uint64_t)section_count(r, cfg) * state_size(r.gen));
+  return align_up(r.n * es) + 2 * slots;
+}
+
+void layout_request(Req* r, char* base, const prand_server_config& cfg) {
+  const uint64_t es = r->r.dtype == PRAND_F64 ? 8 : 4;
+  const uint32_t ns = section_count(r->r, cfg);
+  const size_t sb = state_size(r->r.gen);
+  const uint64_t slots = align_up((uint64_t)ns * sb);
+  r->out = base;
+  r->seclen = section_len(r->r, cfg);
+  r->secs.assign(ns, Section{});
+  char* a = base + align_up(r->r.n * es);
+  for (uint32_t j = 0; j < ns; j++) {
+    Section& q = r->secs[j];
+    q.start = (uint64_t)j * r->seclen;
+    q.len = std::min<uint64_t>(r->seclen, r->r.n - q.start);
+    q.st[0] = a + (size_t)j * sb;
+    q.st[1] = a + slots + (size_t)j * sb;
+  }
 }
 
 hipError_t grow_slot(prand_server* s, IterSlot& sl, uint32_t ntasks, uint32_t ntiles) {
@@ -268,20 +323,20 @@ int admit_and_init(prand_server* s, int li) {
     const size_t act = active_total(s);
     size_t limit = s->cfg.max_active > act ? s->cfg.max_active - act : 0;
     limit = std::min<size_t>(limit, kInitMax);
+    uint32_t items = 0;
     for (auto it = s->waiting.begin(); it != s->waiting.end() && ib.reqs.size() < limit;) {
       Req* r = *it;
       if (lane_of(r->r.gen) != li) {
         ++it;
         continue;
       }
+      const uint32_t ns = section_count(r->r, s->cfg);
+      if (items + ns > kInitItems) break;
       uint64_t off;
       if (s->arena.alloc(r->bytes, &off)) {
         r->off = off;
-        r->out = s->d_arena + off;
-        const uint64_t ob = align_up(r->r.n * (r->r.dtype == PRAND_F64 ? 8 : 4));
-        const uint64_t sb = align_up(state_size(r->r.gen));
-        r->st[0] = r->out + ob;
-        r->st[1] = r->out + ob + sb;
+        layout_request(r, s->d_arena + off, s->cfg);
+        items += ns;
         r->t_admit = t;
         ib.reqs.push_back(r);
         it = s->waiting.erase(it);
@@ -303,6 +358,7 @@ int admit_and_init(prand_server* s, int li) {
   });
   const uint32_t n = (uint32_t)ib.reqs.size();
   std::vector<uint32_t> group_start;
+  uint32_t items = 0, dists = 0;
   for (uint32_t i = 0; i < n; i++) {
     const Req* r = ib.reqs[i];
     if (i == 0 || r->r.gen != ib.reqs[i - 1]->r.gen || r->r.variant != ib.reqs[i - 1]->r.variant)
@@ -310,14 +366,22 @@ int admit_and_init(prand_server* s, int li) {
     const uint32_t a = group_start.back();
     const size_t sb = state_size(r->r.gen);
     ib.h_ids[i] = r->r.stream_id;
-    ib.h_items[i].src = (const uint32_t*)(ib.d_staging + (size_t)a * kStateSlot + (size_t)(i - a) * sb);
-    ib.h_items[i].dst = (uint32_t*)r->st[0];
-    ib.h_items[i].words = sb / 4;
+    // every section's first slot starts as the stream's state
+    for (const Section& q : r->secs) {
+      ib.h_items[items].src = (const uint32_t*)(ib.d_staging + (size_t)a * kStateSlot + (size_t)(i - a) * sb);
+      ib.h_items[items].dst = (uint32_t*)q.st[0];
+      ib.h_items[items].words = sb / 4;
+      items++;
+    }
+    if (r->secs.size() > 1)
+      for (const Section& q : r->secs) ib.h_dist[dists++] = q.start;
   }
   group_start.push_back(n);
   hipError_t e = hipMemcpyAsync(ib.d_ids, ib.h_ids, n * sizeof(uint64_t), hipMemcpyHostToDevice, L.init_st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(ib.d_items, ib.h_items, n * sizeof(ScatterItem), hipMemcpyHostToDevice, L.init_st);
+    e = hipMemcpyAsync(ib.d_items, ib.h_items, items * sizeof(ScatterItem), hipMemcpyHostToDevice, L.init_st);
+  if (e == hipSuccess && dists)
+    e = hipMemcpyAsync(ib.d_dist, ib.h_dist, dists * sizeof(uint64_t), hipMemcpyHostToDevice, L.init_st);
   if (e != hipSuccess) return hipfail(s->ctx, e);
   for (size_t k = 0; k + 1 < group_start.size(); k++) {
     const uint32_t a = group_start[k], b = group_start[k + 1];
@@ -325,8 +389,20 @@ int admit_and_init(prand_server* s, int li) {
                                     ib.d_staging + (size_t)a * kStateSlot, L.init_st);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(scatter_states_kernel, dim3((n + 3) / 4), dim3(256), 0, L.init_st, ib.d_items, n);
+  hipLaunchKernelGGL(scatter_states_kernel, dim3((items + 3) / 4), dim3(256), 0, L.init_st, ib.d_items, items);
   e = hipGetLastError();
+  // sectioned requests: move each section's copy to its start, in place
+  uint32_t d0 = 0;
+  for (uint32_t i = 0; i < n && e == hipSuccess; i++) {
+    const Req* r = ib.reqs[i];
+    if (r->secs.size() <= 1) continue;
+    JumpSpec js;
+    js.dist = ib.d_dist + d0;
+    js.nlimbs = 1;
+    js.per_stream = 1;
+    e = launch_mt_jump(s->ctx->T, (MtState*)r->secs[0].st[0], (uint32_t)r->secs.size(), js, nullptr, L.init_st);
+    d0 += (uint32_t)r->secs.size();
+  }
   if (e == hipSuccess) e = hipEventRecord(ib.ev, L.init_st);
   if (e != hipSuccess) return hipfail(s->ctx, e);
   ib.in_flight = true;
@@ -339,26 +415,31 @@ int enqueue_iteration(prand_server* s, Lane& L, IterSlot& sl, bool* launched) {
   *launched = false;
   uint64_t m = 0;
   for (Req* r : L.active)
-    if (r->ready && r->issued < r->r.n) m++;
+    if (r->ready)
+      for (const Section& q : r->secs) m += q.issued < q.len;
   if (m == 0) return PRAND_OK;
   const uint64_t share = std::max<uint64_t>(s->cfg.min_chunk, s->cfg.iter_numbers / m);
   s->tasks.clear();
   sl.finishing.clear();
   for (Req* r : L.active) {
     if (!r->ready || r->issued >= r->r.n) continue;
-    uint64_t chunk = std::min<uint64_t>(r->r.n - r->issued, share);
-    if (r->r.gen == PRAND_MT19937) chunk = std::min<uint64_t>(chunk, s->cfg.mt_chunk);
     const uint64_t es = r->r.dtype == PRAND_F64 ? 8 : 4;
-    prand_task t;
-    t.gen = r->r.gen;
-    t.dtype = r->r.dtype;
-    t.n = chunk;
-    t.state_in = r->st[r->cur];
-    t.state_out = r->st[r->cur ^ 1];
-    t.out = r->out + r->issued * es;
-    s->tasks.push_back(t);
-    r->cur ^= 1;
-    r->issued += chunk;
+    for (Section& q : r->secs) {
+      if (q.issued >= q.len) continue;
+      uint64_t chunk = std::min<uint64_t>(q.len - q.issued, share);
+      if (r->r.gen == PRAND_MT19937) chunk = std::min<uint64_t>(chunk, s->cfg.mt_chunk);
+      prand_task t;
+      t.gen = r->r.gen;
+      t.dtype = r->r.dtype;
+      t.n = chunk;
+      t.state_in = q.st[q.cur];
+      t.state_out = q.st[q.cur ^ 1];
+      t.out = r->out + (q.start + q.issued) * es;
+      s->tasks.push_back(t);
+      q.cur ^= 1;
+      q.issued += chunk;
+      r->issued += chunk;
+    }
     if (r->issued == r->r.n) sl.finishing.push_back(r);
   }
   int rc = batch_plan(s->tasks.data(), (uint32_t)s->tasks.size(), s->bcfg, s->tiles);
@@ -400,7 +481,7 @@ int finish_slot(prand_server* s, Lane& L, IterSlot& sl) {
     c.gen = r->r.gen;
     c.dtype = r->r.dtype;
     c.out = r->out;
-    c.state = r->st[r->cur];
+    c.state = r->secs.back().st[r->secs.back().cur];
     c.t_submit = r->t_submit;
     c.t_admit = r->t_admit;
     c.t_done = t;
@@ -555,6 +636,8 @@ void free_server(prand_server* s) {
     InitBatch& ib = L.init;
     (void)hipHostFree(ib.h_ids);
     (void)hipHostFree(ib.h_items);
+    (void)hipHostFree(ib.h_dist);
+    (void)hipFree(ib.d_dist);
     (void)hipFree(ib.d_ids);
     (void)hipFree(ib.d_items);
     (void)hipFree(ib.d_staging);
@@ -603,9 +686,11 @@ int prand_server_create(prand_ctx* c, const prand_server_config* cfg, prand_serv
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&L.init_st, hipStreamNonBlocking);
     InitBatch& ib = L.init;
     if (e == hipSuccess) e = hipHostMalloc((void**)&ib.h_ids, kInitMax * sizeof(uint64_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&ib.h_items, kInitMax * sizeof(ScatterItem), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ib.h_items, kInitItems * sizeof(ScatterItem), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ib.h_dist, kInitItems * sizeof(uint64_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&ib.d_ids, kInitMax * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&ib.d_items, kInitMax * sizeof(ScatterItem));
+    if (e == hipSuccess) e = hipMalloc((void**)&ib.d_items, kInitItems * sizeof(ScatterItem));
+    if (e == hipSuccess) e = hipMalloc((void**)&ib.d_dist, kInitItems * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc((void**)&ib.d_staging, kInitMax * kStateSlot);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ib.ev, hipEventDisableTiming);
     for (IterSlot& sl : L.slot) {
@@ -643,7 +728,7 @@ int prand_server_submit(prand_server* s, const prand_request* req, uint64_t* tic
   if (r.n == 0) return PRAND_EINVAL;
   const int be = prand_block_log2(r.gen, r.variant);
   if (be < 0) return be;
-  if (r.n > (1ull << 40) || request_bytes(r) > s->cfg.hbm_budget) {
+  if (r.n > (1ull << 40) || request_bytes(r, s->cfg) > s->cfg.hbm_budget) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->st.rejected++;
     return PRAND_ERANGE;
@@ -651,7 +736,7 @@ int prand_server_submit(prand_server* s, const prand_request* req, uint64_t* tic
   Req* q = new (std::nothrow) Req;
   if (!q) return PRAND_ENOMEM;
   q->r = r;
-  q->bytes = request_bytes(r);
+  q->bytes = request_bytes(r, s->cfg);
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->error) {
