@@ -143,7 +143,6 @@ struct EngGQ {
   static constexpr int t = 29, v = V;
   static constexpr uint64_t p = 536870909ull;
   static constexpr uint64_t g = p << 29;
-  using F = double;
   __device__ static bool collapsed(uint64_t x) { return (x & 0x1FFFFFFFull) == 0; }
   __device__ static uint64_t slow_step(uint64_t xc, uint64_t xp) {
     const uint64_t s = (xc << 3) + 48ull * (g - xp);   // < 2^64
@@ -156,24 +155,28 @@ struct EngGQ {
     const uint64_t num = (x << V) >> 29, d0 = num >> 29;
     return (uint32_t)(d0 + ((d0 + 1) * p <= num));
   }
-  __device__ static F to_fast(uint64_t x) { return (double)(x >> 29); }
+  // fast recurrence on y = x / 2^29 mod p in 32-bit integers:
+  // 8 yc - 48 yp = 8 (yc + 6 (p - yp)) mod p, each factor folded with
+  // 2^29 = 3 (mod p); every intermediate stays below 2^32
+  using F = uint32_t;
+  static constexpr uint32_t kP = 536870909u, kM = 0x1FFFFFFFu;
+  __device__ static F to_fast(uint64_t x) { return (uint32_t)(x >> 29); }
   __device__ static uint64_t from_fast(F y) { return ((uint64_t)y) << 29; }
   __device__ static F step(F yc, F yp) {
-    const double pd = 536870909.0, inv = 1.0 / 536870909.0;
-    const double s = fma(8.0, yc, -48.0 * yp);
-    const double k = floor(s * inv);
-    double r = fma(-k, pd, s);
-    r = (r < 0.0) ? r + pd : r;
-    return (r >= pd) ? r - pd : r;
+    const uint32_t sv = kP - yp;                      // <= p
+    const uint32_t u = yc + ((sv + (sv << 1)) << 1);  // yc + 6 sv < 7 p < 2^32
+    uint32_t w = (u & kM) + __umul24(3u, u >> 29);    // < 2 p
+    w = min(w, w - kP);                               // < p
+    const uint32_t z = ((w << 3) & kM) + __umul24(3u, w >> 26);   // 8 w folded, < 2 p
+    return min(z, z - kP);
   }
+  // floor(2^v y / p): with d0 = floor(2^v y / 2^29) and r its remainder
+  // part, 2^v y - d0 p = r + 3 d0 < 2 p, so the digit is d0 or d0 + 1
   __device__ static uint32_t digit(F y) {
-    const double pd = 536870909.0;
-    if (V == 1) return y >= 268435455.0;   // 2y >= p
-    const double num = y * (double)(1 << V);
-    double d = floor(num * (1.0 / 536870909.0));
-    d = (d * pd > num) ? d - 1.0 : d;
-    d = ((d + 1.0) * pd <= num) ? d + 1.0 : d;
-    return (uint32_t)d;
+    if (V == 1) return y >= 268435455u;   // 2y >= p
+    const uint32_t d0 = y >> (29 - V);
+    const uint32_t r = (y & ((1u << (29 - V)) - 1u)) << V;
+    return d0 + ((r + __umul24(3u, d0)) >= kP ? 1u : 0u);
   }
 };
 template <> struct Eng<5> : EngGQ<1> {};
@@ -206,17 +209,36 @@ struct Elem {
       }
     }
   }
-  __device__ uint32_t step() {
-    if constexpr (E::kComposite) {
-      if (!fast) {
-        const uint64_t nx = E::slow_step(sc, sp);
-        sp = sc; sc = nx;
-        return E::slow_digit(nx);
-      }
-    }
+  __device__ bool is_fast() const {
+    if constexpr (E::kComposite) return fast;
+    else return true;
+  }
+  __device__ uint32_t step_fast() {
     const typename E::F nx = E::step(fc, fp);
     fp = fc; fc = nx;
     return E::digit(nx);
+  }
+  __device__ uint32_t step_slow() {
+    if constexpr (E::kComposite) {
+      const uint64_t nx = E::slow_step(sc, sp);
+      sp = sc; sc = nx;
+      return E::slow_digit(nx);
+    } else {
+      return step_fast();
+    }
+  }
+  __device__ uint32_t step() { return is_fast() ? step_fast() : step_slow(); }
+  // Run body(step) for a block of steps with the mode fixed for the whole
+  // block: the switch is taken at the block start, which is exact because a
+  // collapsed pair stays collapsed.  Steady state runs the fast body only.
+  template <class Body>
+  __device__ __forceinline__ void block(Body&& body) {
+    maybe_switch();
+    if (is_fast()) {
+      body([this]() { return step_fast(); });
+    } else {
+      if constexpr (E::kComposite) body([this]() { return step_slow(); });
+    }
   }
   __device__ void get(uint64_t& xc, uint64_t& xp) const {
     if (fast) { xc = E::from_fast(fc); xp = E::from_fast(fp); }
@@ -417,11 +439,12 @@ __device__ __forceinline__ void gen32_wave(bool live, const GmState* in, uint64_
   for (uint64_t t0 = 0; t0 < n; t0 += 32) {
     const int m = (n - t0) < 32 ? (int)(n - t0) : 32;
     if (m == 32) {
-      static_for<0, 32>([&](auto uc) {
-        constexpr int u = decltype(uc)::value;
-        el.maybe_switch();
-        const uint64_t mask = __ballot(el.step());
-        keep = writelane_pair<u>(keep, (uint32_t)mask, (uint32_t)(mask >> 32));
+      el.block([&](auto stepf) {
+        static_for<0, 32>([&](auto uc) {
+          constexpr int u = decltype(uc)::value;
+          const uint64_t mask = __ballot(stepf());
+          keep = writelane_pair<u>(keep, (uint32_t)mask, (uint32_t)(mask >> 32));
+        });
       });
     } else {
       for (int u = 0; u < m; u++) {
@@ -455,17 +478,21 @@ __device__ __forceinline__ void gen8_wave(bool live, const GmState* in, uint64_t
   uint32_t keep = 0;
   for (uint64_t t0 = 0; t0 < n; t0 += 8) {
     const int m = (n - t0) < 8 ? (int)(n - t0) : 8;
-    auto one = [&](int u) {
-      el.maybe_switch();
-      const uint32_t w = dpp_or8(el.step() << shift);
-      keep = (u == e) ? w : keep;
-    };
-    int u = 0;
-    for (; u + 2 <= m; u += 2) {
-      one(u);
-      one(u + 1);
+    if (m == 8) {
+      el.block([&](auto stepf) {
+        static_for<0, 8>([&](auto uc) {
+          constexpr int u = decltype(uc)::value;
+          const uint32_t w = dpp_or8(stepf() << shift);
+          keep = (u == e) ? w : keep;
+        });
+      });
+    } else {
+      for (int u = 0; u < m; u++) {
+        el.maybe_switch();
+        const uint32_t w = dpp_or8(el.step() << shift);
+        keep = (u == e) ? w : keep;
+      }
     }
-    if (u < m) one(u);
     if (live && e < m) put<DT>(out, t0 + e, keep);
   }
   if (live && sout) {
@@ -501,16 +528,18 @@ __device__ __forceinline__ void gq3_wave(bool live, const GmState* in, uint64_t 
   Elem<G> saved = el;
   const int shift = elem ? 33 - 3 * e : 0;
   for (uint64_t b = 0; b < nb; b++) {
-    el.maybe_switch();
-    saved = el;
     uint64_t keep = 0;
-    for (int u = 0; u < 8; u++) {
-      const uint32_t d = el.step();
-      uint64_t c = elem ? ((uint64_t)d << shift) : 0;
-      const uint32_t lo = dpp_or16((uint32_t)c), hi = dpp_or16((uint32_t)(c >> 32));
-      c = ((uint64_t)hi << 32) | lo;
-      keep = (u == e) ? c : keep;
-    }
+    el.block([&](auto stepf) {
+      saved = el;
+      static_for<0, 8>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        const uint32_t d = stepf();
+        uint64_t c = elem ? ((uint64_t)d << shift) : 0;
+        const uint32_t lo = dpp_or16((uint32_t)c), hi = dpp_or16((uint32_t)(c >> 32));
+        c = ((uint64_t)hi << 32) | lo;
+        keep = (u == e) ? c : keep;
+      });
+    });
     // word w (lane w < 9): bits [32w, 32w+32) of the 288-bit block
     const int w = e < 9 ? e : 8;
     const int ci = (32 * w) / 36, o = 32 * w - 36 * ci;
