@@ -44,18 +44,25 @@ __global__ void __launch_bounds__(64) mt_generate_kernel(MtState* states, uint32
 // ------------------------------------------------------------------ jump
 constexpr int kRing = 2048;                 // LDS ring of sequence words
 constexpr int kMask = kRing - 1;
+constexpr int kMirror = 16;                 // ring[0..15] repeated after the end
 constexpr int kDeg = 19937;
 constexpr int kSeqLen = kDeg - 1 + 624;     // words seq[0..20559] take part
 constexpr int kPer = 10;                    // outputs per lane: 64 * 10 >= 624
 
-// Extend the ring to hold seq[0..upto) (227 words per phase).
+// Extend the ring to hold seq[0..upto) (227 words per phase).  Words landing
+// in the first kMirror slots are also written after the ring's end, so that
+// kPer consecutive words can be read from any slot without wrapping.
 __device__ __forceinline__ void extend(uint32_t* ring, int& gen_hi, int upto, int lane) {
   if (upto > kSeqLen) upto = kSeqLen;
   while (gen_hi < upto) {
     const int g0 = gen_hi;
     const int g1 = (g0 + 227 < kSeqLen) ? g0 + 227 : kSeqLen;
-    for (int j = g0 + lane; j < g1; j += 64)
-      ring[j & kMask] = recur(ring[(j - 624) & kMask], ring[(j - 623) & kMask], ring[(j - 227) & kMask]);
+    for (int j = g0 + lane; j < g1; j += 64) {
+      const uint32_t v = recur(ring[(j - 624) & kMask], ring[(j - 623) & kMask], ring[(j - 227) & kMask]);
+      const int slot = j & kMask;
+      ring[slot] = v;
+      if (slot < kMirror) ring[slot + kRing] = v;
+    }
     __syncthreads();
     gen_hi = g1;
   }
@@ -63,14 +70,18 @@ __device__ __forceinline__ void extend(uint32_t* ring, int& gen_hi, int upto, in
 
 // ring[0..623] holds a window (next output = tempered successor); replace it
 // by g(A) applied to it, g = poly (624 words of coefficient bits).
+// Lane l accumulates outputs t = 10 l + r.  For the coefficients i0 .. i0 + 9
+// of a group it holds the sequence words seq[i0 + 10 l + k] (cur) and
+// seq[i0 + 10 + 10 l + k] (nxt), k < 10: coefficient i0 + u adds
+// seq[i0 + u + 10 l + r], which is cur[u + r] or nxt[u + r - 10].
 __device__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, int lane) {
   int gen_hi = 624;
   extend(ring, gen_hi, 660, lane);
-  uint32_t acc[kPer], c[kPer];
+  uint32_t acc[kPer], cur[kPer], nxt[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; r++) {
     acc[r] = 0;
-    c[r] = ring[(kPer * lane + r) & kMask];
+    cur[r] = ring[kPer * lane + r];
   }
   for (int i0 = 0; i0 < kDeg; i0 += kPer) {
     extend(ring, gen_hi, i0 + 660, lane);
@@ -78,16 +89,18 @@ __device__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, in
     const uint64_t pair = (uint64_t)poly[w] | ((w + 1 < 624) ? ((uint64_t)poly[w + 1] << 32) : 0ull);
     uint32_t bits = (uint32_t)(pair >> sh) & ((1u << kPer) - 1);
     if (i0 + kPer > kDeg) bits &= (1u << (kDeg - i0)) - 1;
+    const uint32_t* src = ring + ((i0 + kPer + kPer * lane) & kMask);   // + k < kRing + kMirror
+#pragma unroll
+    for (int k = 0; k < kPer; k++) nxt[k] = src[k];
 #pragma unroll
     for (int u = 0; u < kPer; u++) {
       if ((bits >> u) & 1u) {
 #pragma unroll
-        for (int r = 0; r < kPer; r++) acc[r] ^= c[(r + u) % kPer];
+        for (int r = 0; r < kPer; r++) acc[r] ^= (u + r < kPer) ? cur[u + r] : nxt[u + r - kPer];
       }
-      // element leaving the window is seq[i + 10 lane]; the one entering for
-      // the next coefficient is seq[i + 10 lane + 10]
-      c[u] = ring[(i0 + u + kPer * lane + kPer) & kMask];
     }
+#pragma unroll
+    for (int k = 0; k < kPer; k++) cur[k] = nxt[k];
   }
   __syncthreads();
 #pragma unroll
@@ -106,7 +119,7 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
                                                      const uint32_t* __restrict__ ladder,
                                                      const uint32_t* __restrict__ dig12,
                                                      const uint32_t* __restrict__ dig8hi) {
-  __shared__ uint32_t ring[kRing];
+  __shared__ uint32_t ring[kRing + kMirror];
   const uint32_t s = blockIdx.x;
   if (s >= count) return;
   const int lane = threadIdx.x;
