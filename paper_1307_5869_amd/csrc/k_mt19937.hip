@@ -83,24 +83,31 @@ __device__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, in
     acc[r] = 0;
     cur[r] = ring[kPer * lane + r];
   }
-  for (int i0 = 0; i0 < kDeg; i0 += kPer) {
-    extend(ring, gen_hi, i0 + 660, lane);
-    const int w = i0 >> 5, sh = i0 & 31;
+  // three groups (30 coefficients) share one 64-bit load of the polynomial:
+  // bits i1 .. i1 + 29 lie in the words i1 / 32 and i1 / 32 + 1
+  for (int i1 = 0; i1 < kDeg; i1 += 3 * kPer) {
+    const int w = i1 >> 5, sh = i1 & 31;
     const uint64_t pair = (uint64_t)poly[w] | ((w + 1 < 624) ? ((uint64_t)poly[w + 1] << 32) : 0ull);
-    uint32_t bits = (uint32_t)(pair >> sh) & ((1u << kPer) - 1);
-    if (i0 + kPer > kDeg) bits &= (1u << (kDeg - i0)) - 1;
-    const uint32_t* src = ring + ((i0 + kPer + kPer * lane) & kMask);   // + k < kRing + kMirror
 #pragma unroll
-    for (int k = 0; k < kPer; k++) nxt[k] = src[k];
+    for (int g = 0; g < 3; g++) {
+      const int i0 = i1 + g * kPer;
+      if (i0 >= kDeg) break;
+      extend(ring, gen_hi, i0 + 660, lane);
+      uint32_t bits = (uint32_t)(pair >> (sh + g * kPer)) & ((1u << kPer) - 1);
+      if (i0 + kPer > kDeg) bits &= (1u << (kDeg - i0)) - 1;
+      const uint32_t* src = ring + ((i0 + kPer + kPer * lane) & kMask);   // + k < kRing + kMirror
 #pragma unroll
-    for (int u = 0; u < kPer; u++) {
-      if ((bits >> u) & 1u) {
+      for (int k = 0; k < kPer; k++) nxt[k] = src[k];
 #pragma unroll
-        for (int r = 0; r < kPer; r++) acc[r] ^= (u + r < kPer) ? cur[u + r] : nxt[u + r - kPer];
+      for (int u = 0; u < kPer; u++) {
+        if ((bits >> u) & 1u) {
+#pragma unroll
+          for (int r = 0; r < kPer; r++) acc[r] ^= (u + r < kPer) ? cur[u + r] : nxt[u + r - kPer];
+        }
       }
-    }
 #pragma unroll
-    for (int k = 0; k < kPer; k++) cur[k] = nxt[k];
+      for (int k = 0; k < kPer; k++) cur[k] = nxt[k];
+    }
   }
   __syncthreads();
 #pragma unroll
