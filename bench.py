@@ -240,7 +240,7 @@ def recorded_traffic(kernel):
 
 def batched_vs_plain(ctx, ntasks, stream):
     """Many streams of mixed generators and uneven lengths (log-uniform in
-    [1e3, 1e7]) in f32: one autotuned persistent launch replayed from a HIP
+    [1e3, 1e7]) in f32: one autotuned batched launch replayed from a HIP
     graph, against plain per-stream launches timed on a sample of the tasks."""
     import torch
 
@@ -333,7 +333,7 @@ def batched_vs_plain(ctx, ntasks, stream):
             "plain_sectioned_s": round(sec_s, 3),
             "plain_sectioned_numbers_per_s": sec_numbers / sec_s,
             "speedup_vs_sectioned": (total / (ms * 1e-3)) / (sec_numbers / sec_s),
-            "config": {"waves_per_cu": best.waves_per_cu, "reg_section": best.reg_section,
+            "config": {"waves_per_block": best.waves_per_block, "reg_section": best.reg_section,
                        "gm_section": best.gm_section, "graph": bool(best.use_graph)},
             "autotune_s": round(tune_s, 2), "batched_ms": round(ms, 3),
             "batched_numbers_per_s": total / (ms * 1e-3),

@@ -166,11 +166,13 @@ int prand_generate_streams(prand_ctx* ctx, int gen, void* d_states, uint32_t cou
                            uint64_t n_per_stream, int dtype, void* d_out, void* stream);
 
 /* ------------------------------------------------------------------------
- * Batched persistent launch: many streams of uneven lengths and mixed
- * generators and dtypes in one fused launch, replayed from a HIP graph.
- * Each task is cut into sections that jump to their first output (the
- * sectioning of "Multi-threaded generation"), grouped into per-wavefront
- * tiles that a fixed grid of wavefronts pulls from a work queue.
+ * Batched launch: many streams of uneven lengths and mixed generators and
+ * dtypes in one launch, replayed from a HIP graph.  Each task is cut into
+ * sections that jump to their first output (the sectioning of "Multi-threaded
+ * generation"), grouped into per-wavefront tiles; a first kernel computes
+ * every section's start state, then one kernel per generator family
+ * (MT19937; MRG32K3A/LFSR113; GM/GQ) generates, the families running
+ * concurrently.
  * ------------------------------------------------------------------------ */
 typedef struct prand_task {
   int32_t gen;           /* enum prand_gen */
@@ -183,7 +185,7 @@ typedef struct prand_task {
 } prand_task;
 
 typedef struct prand_batch_config {
-  uint32_t waves_per_cu;   /* persistent wavefronts per compute unit (0: 16) */
+  uint32_t waves_per_block; /* tiles (wavefronts) per workgroup: 1, 2 or 4 (0: 4) */
   uint32_t reg_section;    /* MRG32K3A/LFSR113 outputs per lane section, multiple of 32 (0: 2048) */
   uint32_t gm_section;     /* GM/GQ outputs per element-group section (0: 4096) */
   uint32_t use_graph;      /* 1: capture the launch in a HIP graph and replay it */
@@ -192,10 +194,13 @@ typedef struct prand_batch_config {
 typedef struct prand_batch prand_batch;
 
 /* Plan a batch (tasks are read on the host; the device pointers they hold
-   must stay valid while the batch is launched).  cfg NULL: defaults. */
+   must stay valid while the batch is launched).  cfg NULL: defaults.  The
+   batch owns a device scratch area for the section start states (about 1.5 KB
+   per tile). */
 int prand_batch_create(prand_ctx* ctx, const prand_task* h_tasks, uint32_t ntasks, const prand_batch_config* cfg,
                        prand_batch** batch);
-/* Enqueue the batch on `stream` (a hipStream_t, NULL = default stream).
+/* Enqueue the batch on `stream` (a hipStream_t, NULL = default stream); the
+   work forks onto two private streams and joins back into `stream`.
    Launches of the same batch must not overlap each other. */
 int prand_batch_launch(prand_batch* batch, void* stream);
 /* Number of tiles (wavefront work items) the plan holds. */
@@ -215,7 +220,7 @@ int prand_batch_autotune(prand_ctx* ctx, const prand_task* h_tasks, uint32_t nta
  * thread admits them while their output and state fit in a fixed HBM budget,
  * initialises each request's stream by block splitting on a second HIP
  * stream, and runs continuous batching: every loop iteration is one batched
- * persistent launch holding the next chunk of every admitted request, so
+ * launch holding the next chunk of every admitted request, so
  * short requests finish while long ones are still running.  States stay on
  * the device between iterations; outputs stay on the device until released.
  * A request's output equals prand_init_stream(id) followed by generation of n
@@ -233,7 +238,7 @@ typedef struct prand_server_config {
                                start from jumped states and run in parallel (0: 2^22) */
   uint32_t max_active;      /* requests generating at once (0: 8192) */
   uint32_t max_queue;       /* waiting requests beyond which submissions are rejected (0: 2^20) */
-  uint32_t waves_per_cu;    /* batched-kernel shape, as prand_batch_config (0: defaults) */
+  uint32_t waves_per_block; /* batch kernel shape, as prand_batch_config (0: defaults) */
   uint32_t reg_section;
   uint32_t gm_section;
   uint32_t pad;

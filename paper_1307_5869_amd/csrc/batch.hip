@@ -1,12 +1,16 @@
-// Batched persistent launch: planning, HIP-graph replay and the autotuner.
+// Batched launch: planning, HIP-graph replay and the autotuner.
 //
 // The planner cuts each task into sections that jump to their first output
-// and groups them into per-wavefront tiles (see k_batch.hip); tiles are
-// sorted longest first so that the persistent wavefronts finish together.
-// The launch (counter reset + persistent kernel) is captured once in a HIP
-// graph on a private stream and replayed on the caller's stream.  The
-// autotuner times a small grid of (wavefronts per CU, MRG32K3A/LFSR113 lane
-// section, GM/GQ group section) on the actual task mix.
+// and groups them into per-wavefront tiles (see k_batch.hip), family by
+// family, each family sorted longest first so that the dispatcher starts the
+// long tiles early and the short ones fill the end.  Every MRG32K3A/LFSR113
+// and GM/GQ tile gets a slot in the batch's scratch area for its sections'
+// start states.  The launch is captured once in a HIP graph on a private
+// stream: the MT19937 kernel on one branch; the section-start kernel, then
+// the MRG32K3A/LFSR113 kernel and the three GM/GQ kernels on branches of
+// their own; it is replayed on the caller's stream.  The autotuner times a
+// small grid of (wavefronts per workgroup, MRG32K3A/LFSR113 lane section,
+// GM/GQ group section) on the actual task mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,11 +31,11 @@ struct prand_batch {
   prand_ctx* ctx = nullptr;
   prand_batch_config cfg{};
   BatchTile* d_tiles = nullptr;
-  uint32_t ntiles = 0;
+  BatchCounts n;
   BatchTask* d_tasks = nullptr;
-  uint32_t* d_counter = nullptr;
-  uint32_t blocks = 0;
-  hipStream_t cap = nullptr;
+  char* d_scratch = nullptr;
+  hipStream_t cap = nullptr, side[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -47,7 +51,7 @@ size_t state_size(int g) {
   }
 }
 
-// relative wavefront time per output a tile's longest lane sequence costs
+// relative wavefront time per output of a tile's longest lane sequence
 double per_output_cost(int gen) {
   switch (gen) {
     case PRAND_MT19937: return 0.35;   // 64 lanes share one stream
@@ -57,8 +61,8 @@ double per_output_cost(int gen) {
     case PRAND_GM29: return 11;
     case PRAND_GM31: return 16;
     case PRAND_GM61: return 24;
-    case PRAND_GQ58X1: return 20;
-    case PRAND_GQ58X3: return 27;
+    case PRAND_GQ58X1: return 15;
+    case PRAND_GQ58X3: return 20;
     default: return 25;   // GM55, GQ58.4
   }
 }
@@ -66,26 +70,170 @@ double per_output_cost(int gen) {
 uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
 
 void fill_defaults(prand_batch_config& c) {
-  if (!c.waves_per_cu) c.waves_per_cu = 16;
+  if (!c.waves_per_block) c.waves_per_block = 4;
   if (!c.reg_section) c.reg_section = 2048;
   if (!c.gm_section) c.gm_section = 4096;
+  c.waves_per_block = c.waves_per_block >= 4 ? 4 : (c.waves_per_block >= 2 ? 2 : 1);
   c.reg_section = (uint32_t)std::max<uint64_t>(32, round_up(c.reg_section, 32));
   c.gm_section = std::max<uint32_t>(32, c.gm_section);
 }
+
+bool is_reg(int g) { return g == PRAND_MRG32K3A || g == PRAND_LFSR113; }
+
+}  // namespace
+
+namespace prand {
+
+void batch_fill_defaults(prand_batch_config& c) { fill_defaults(c); }
+
+int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, BatchPlan& plan) {
+  // families in BatchCounts order: MRG32K3A/LFSR113, GM/GQ v = 1, v = 4,
+  // GQ58.3, MT19937, copies (n = 0)
+  std::vector<std::pair<double, BatchTile>> work[kBatchFamilies];
+  for (uint32_t k = 0; k < ntasks; k++) {
+    const prand_task& t = tasks[k];
+    if (t.gen < 0 || t.gen >= PRAND_NUM_GENERATORS || t.dtype < PRAND_U32 || t.dtype > PRAND_F64)
+      return PRAND_EINVAL;
+    if (!t.state_in || !t.state_out || (t.n && !t.out)) return PRAND_EINVAL;
+    if (t.n > (1ull << 40)) return PRAND_ERANGE;
+    BatchTile b{};
+    b.task = k;
+    if (t.n == 0) {
+      b.kind = kTileCopy;
+      b.len32 = state_size(t.gen) / 4;
+      work[5].push_back({0.0, b});
+      continue;
+    }
+    b.kind = kTileGen;
+    const uint64_t n = t.n, es = t.dtype == PRAND_F64 ? 8 : 4;
+    const double c = per_output_cost(t.gen);
+    if (t.gen == PRAND_MT19937) {
+      b.first = 0;
+      b.seclen = n;
+      b.nsec = 1;
+      work[4].push_back({c * (double)n, b});
+      continue;
+    }
+    if (is_reg(t.gen)) {
+      uint64_t sec = cfg.reg_section;
+      if (n < 64 * sec) sec = std::max<uint64_t>(32, round_up((n + 63) / 64, 32));
+      const uint64_t total = (n + sec - 1) / sec;
+      b.seclen = sec;
+      b.coalesce = ((uintptr_t)t.out % 16 == 0) && ((sec * es) % 16 == 0);
+      for (uint64_t f = 0; f < total; f += 64) {
+        b.first = f;
+        b.nsec = (uint32_t)std::min<uint64_t>(64, total - f);
+        work[0].push_back({c * (double)sec, b});
+      }
+      continue;
+    }
+    const bool v1 = t.gen == PRAND_GM19 || t.gen == PRAND_GM29 || t.gen == PRAND_GM31 || t.gen == PRAND_GM61 ||
+                    t.gen == PRAND_GQ58X1;
+    const uint64_t groups = v1 ? 2 : (t.gen == PRAND_GQ58X3 ? 4 : 8);
+    const int fam = v1 ? 1 : (t.gen == PRAND_GQ58X3 ? 3 : 2);
+    uint64_t sec = cfg.gm_section;
+    if (n < groups * sec) sec = std::max<uint64_t>(32, round_up((n + groups - 1) / groups, 32));
+    b.seclen = sec;
+    if (v1) {
+      // both halves of a wavefront run the same number of steps: pair the
+      // full sections, give the ragged last section a tile of its own
+      const uint64_t full = n / sec, part = n % sec;
+      for (uint64_t f = 0; f < full; f += 2) {
+        b.first = f;
+        b.nsec = (uint32_t)std::min<uint64_t>(2, full - f);
+        b.len32 = sec;
+        work[fam].push_back({c * (double)sec, b});
+      }
+      if (part) {
+        b.first = full;
+        b.nsec = 1;
+        b.len32 = part;
+        work[fam].push_back({c * (double)part, b});
+      }
+    } else {
+      const uint64_t total = (n + sec - 1) / sec;
+      for (uint64_t f = 0; f < total; f += groups) {
+        b.first = f;
+        b.nsec = (uint32_t)std::min<uint64_t>(groups, total - f);
+        work[fam].push_back({c * (double)sec, b});
+      }
+    }
+  }
+  size_t total = 0;
+  for (auto& w : work) total += w.size();
+  if (total > 0xFFFFFFF0ull) return PRAND_ERANGE;
+  plan.tiles.resize(total);
+  plan.scratch_bytes = 0;
+  size_t at = 0;
+  for (int f = 0; f < kBatchFamilies; f++) {
+    std::stable_sort(work[f].begin(), work[f].end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    for (auto& w : work[f]) {
+      BatchTile& tl = plan.tiles[at++];
+      tl = w.second;
+      if (f <= 3) {
+        // section start states: 64 register states or one GmState per section
+        const int gen = tasks[tl.task].gen;
+        const uint64_t bytes = f == 0 ? 64 * state_size(gen) : (uint64_t)tl.nsec * sizeof(GmState);
+        tl.starts = plan.scratch_bytes;
+        plan.scratch_bytes += round_up(bytes, 64);
+      }
+    }
+  }
+  plan.n.reg = (uint32_t)work[0].size();
+  plan.n.g32 = (uint32_t)work[1].size();
+  plan.n.g8 = (uint32_t)work[2].size();
+  plan.n.g3 = (uint32_t)work[3].size();
+  plan.n.mt = (uint32_t)work[4].size();
+  plan.n.copy = (uint32_t)work[5].size();
+  return PRAND_OK;
+}
+
+}  // namespace prand
+
+namespace {
 
 void free_batch(prand_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t s : b->side)
+    if (s) (void)hipStreamDestroy(s);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   (void)hipFree(b->d_tiles);
   (void)hipFree(b->d_tasks);
-  (void)hipFree(b->d_counter);
+  (void)hipFree(b->d_scratch);
   delete b;
 }
 
-hipError_t enqueue(prand_batch* b, hipStream_t st) {
-  return launch_batch(b->ctx->T, b->d_tiles, b->ntiles, b->d_tasks, b->d_counter, b->blocks, st);
+// The batch's kernels on stream a, forked onto the side streams and joined
+// back: MT19937 on side[0]; the section starts on a, then GM/GQ v = 1 on a,
+// v = 4 on side[1], GQ58.3 on side[2] and MRG32K3A/LFSR113 on side[3].
+hipError_t enqueue_forked(prand_batch* b, hipStream_t a) {
+  const DeviceTables& T = b->ctx->T;
+  const uint32_t w = b->cfg.waves_per_block;
+  const BatchCounts& n = b->n;
+  const BatchTile* reg = b->d_tiles;
+  const BatchTile* g32 = reg + n.reg;
+  const BatchTile* g8 = g32 + n.g32;
+  const BatchTile* g3 = g8 + n.g8;
+  const BatchTile* mt = g3 + n.g3;
+  hipError_t e = hipEventRecord(b->ev[0], a);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->side[0], b->ev[0], 0);
+  if (e == hipSuccess) e = launch_batch_mt(mt, n.mt + n.copy, b->d_tasks, w, b->side[0]);
+  if (e == hipSuccess) e = launch_batch_starts(T, reg, n.with_starts(), b->d_tasks, b->d_scratch, w, a);
+  if (e == hipSuccess) e = hipEventRecord(b->ev[1], a);
+  for (int i = 1; i < 4 && e == hipSuccess; i++) e = hipStreamWaitEvent(b->side[i], b->ev[1], 0);
+  if (e == hipSuccess) e = launch_batch_gm(2, g3, n.g3, b->d_tasks, b->d_scratch, w, b->side[2]);
+  if (e == hipSuccess) e = launch_batch_gm(1, g8, n.g8, b->d_tasks, b->d_scratch, w, b->side[1]);
+  if (e == hipSuccess) e = launch_batch_reg(reg, n.reg, b->d_tasks, b->d_scratch, w, b->side[3]);
+  if (e == hipSuccess) e = launch_batch_gm(0, g32, n.g32, b->d_tasks, b->d_scratch, w, a);
+  for (int i = 0; i < 4 && e == hipSuccess; i++) {
+    e = hipEventRecord(b->ev[2 + i], b->side[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(a, b->ev[2 + i], 0);
+  }
+  return e;
 }
 
 std::string signature(prand_ctx* c, const prand_task* tasks, uint32_t ntasks) {
@@ -119,7 +267,7 @@ bool cache_lookup(const std::string& key, prand_batch_config* cfg) {
     *tab = 0;
     unsigned w, r, g;
     if (key == line && std::sscanf(tab + 1, "%u %u %u", &w, &r, &g) == 3) {
-      cfg->waves_per_cu = w;
+      cfg->waves_per_block = w;
       cfg->reg_section = r;
       cfg->gm_section = g;
       cfg->use_graph = 1;
@@ -135,94 +283,11 @@ void cache_store(const std::string& key, const prand_batch_config& cfg) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s\t%u %u %u\n", key.c_str(), cfg.waves_per_cu, cfg.reg_section, cfg.gm_section);
+  std::fprintf(f, "%s\t%u %u %u\n", key.c_str(), cfg.waves_per_block, cfg.reg_section, cfg.gm_section);
   std::fclose(f);
 }
 
 }  // namespace
-
-namespace prand {
-
-void batch_fill_defaults(prand_batch_config& c) { fill_defaults(c); }
-
-int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, std::vector<BatchTile>& tiles) {
-  std::vector<std::pair<double, BatchTile>> work;
-  for (uint32_t k = 0; k < ntasks; k++) {
-    const prand_task& t = tasks[k];
-    if (t.gen < 0 || t.gen >= PRAND_NUM_GENERATORS || t.dtype < PRAND_U32 || t.dtype > PRAND_F64)
-      return PRAND_EINVAL;
-    if (!t.state_in || !t.state_out || (t.n && !t.out)) return PRAND_EINVAL;
-    if (t.n > (1ull << 40)) return PRAND_ERANGE;
-    BatchTile b{};
-    b.task = k;
-    if (t.n == 0) {
-      b.kind = kTileCopy;
-      b.len32 = state_size(t.gen) / 4;
-      work.push_back({0.0, b});
-      continue;
-    }
-    b.kind = kTileGen;
-    const uint64_t n = t.n, es = t.dtype == PRAND_F64 ? 8 : 4;
-    const double c = per_output_cost(t.gen);
-    if (t.gen == PRAND_MT19937) {
-      b.first = 0;
-      b.seclen = n;
-      b.nsec = 1;
-      work.push_back({c * (double)n, b});
-      continue;
-    }
-    if (t.gen == PRAND_MRG32K3A || t.gen == PRAND_LFSR113) {
-      uint64_t sec = cfg.reg_section;
-      if (n < 64 * sec) sec = std::max<uint64_t>(32, round_up((n + 63) / 64, 32));
-      const uint64_t total = (n + sec - 1) / sec;
-      b.seclen = sec;
-      b.coalesce = ((uintptr_t)t.out % 16 == 0) && ((sec * es) % 16 == 0);
-      for (uint64_t f = 0; f < total; f += 64) {
-        b.first = f;
-        b.nsec = (uint32_t)std::min<uint64_t>(64, total - f);
-        work.push_back({c * (double)sec, b});
-      }
-      continue;
-    }
-    const bool v1 = t.gen == PRAND_GM19 || t.gen == PRAND_GM29 || t.gen == PRAND_GM31 || t.gen == PRAND_GM61 ||
-                    t.gen == PRAND_GQ58X1;
-    const uint64_t groups = v1 ? 2 : (t.gen == PRAND_GQ58X3 ? 4 : 8);
-    uint64_t sec = cfg.gm_section;
-    if (n < groups * sec) sec = std::max<uint64_t>(32, round_up((n + groups - 1) / groups, 32));
-    b.seclen = sec;
-    if (v1) {
-      // both halves of a wavefront run the same number of steps: pair the
-      // full sections, give the ragged last section a tile of its own
-      const uint64_t full = n / sec, part = n % sec;
-      for (uint64_t f = 0; f < full; f += 2) {
-        b.first = f;
-        b.nsec = (uint32_t)std::min<uint64_t>(2, full - f);
-        b.len32 = sec;
-        work.push_back({c * (double)sec, b});
-      }
-      if (part) {
-        b.first = full;
-        b.nsec = 1;
-        b.len32 = part;
-        work.push_back({c * (double)part, b});
-      }
-    } else {
-      const uint64_t total = (n + sec - 1) / sec;
-      for (uint64_t f = 0; f < total; f += groups) {
-        b.first = f;
-        b.nsec = (uint32_t)std::min<uint64_t>(groups, total - f);
-        work.push_back({c * (double)sec, b});
-      }
-    }
-  }
-  if (work.size() > 0xFFFFFFF0ull) return PRAND_ERANGE;
-  std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-  tiles.resize(work.size());
-  for (size_t i = 0; i < work.size(); i++) tiles[i] = work[i].second;
-  return PRAND_OK;
-}
-
-}  // namespace prand
 
 extern "C" {
 
@@ -234,25 +299,30 @@ int prand_batch_create(prand_ctx* c, const prand_task* h_tasks, uint32_t ntasks,
   prand_batch_config conf{};
   if (cfg) conf = *cfg;
   fill_defaults(conf);
-  std::vector<BatchTile> tiles;
-  int rc = batch_plan(h_tasks, ntasks, conf, tiles);
+  BatchPlan plan;
+  int rc = batch_plan(h_tasks, ntasks, conf, plan);
   if (rc) return rc;
   DeviceGuard g(c->device);
   prand_batch* b = new (std::nothrow) prand_batch;
   if (!b) return PRAND_ENOMEM;
   b->ctx = c;
   b->cfg = conf;
-  b->ntiles = (uint32_t)tiles.size();
-  b->blocks = (uint32_t)std::max<uint64_t>(1, ((uint64_t)c->num_cus * conf.waves_per_cu + 3) / 4);
-  hipError_t e = hipMalloc((void**)&b->d_counter, 64);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_tiles, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile));
+  b->n = plan.n;
+  hipError_t e = hipMalloc((void**)&b->d_tiles, std::max<size_t>(1, plan.tiles.size()) * sizeof(BatchTile));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_tasks, std::max<size_t>(1, ntasks) * sizeof(BatchTask));
-  if (e == hipSuccess && !tiles.empty())
-    e = hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_scratch, std::max<uint64_t>(64, plan.scratch_bytes));
+  if (e == hipSuccess && !plan.tiles.empty())
+    e = hipMemcpy(b->d_tiles, plan.tiles.data(), plan.tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
   if (e == hipSuccess && ntasks) e = hipMemcpy(b->d_tasks, h_tasks, ntasks * sizeof(BatchTask), hipMemcpyHostToDevice);
   if (e == hipSuccess && conf.use_graph) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+  for (int i = 0; i < 6 && e == hipSuccess; i++) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     free_batch(b);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      return PRAND_ENOMEM;
+    }
     return hipfail(c, e);
   }
   *out = b;
@@ -261,29 +331,32 @@ int prand_batch_create(prand_ctx* c, const prand_task* h_tasks, uint32_t ntasks,
 
 int prand_batch_tiles(const prand_batch* b, uint32_t* ntiles) {
   if (!b || !ntiles) return PRAND_EINVAL;
-  *ntiles = b->ntiles;
+  *ntiles = b->n.total();
   return PRAND_OK;
 }
 
 int prand_batch_launch(prand_batch* b, void* stream) {
   if (!b) return PRAND_EINVAL;
-  if (b->ntiles == 0) return PRAND_OK;
+  if (b->n.total() == 0) return PRAND_OK;
   DeviceGuard g(b->ctx->device);
   hipStream_t st = (hipStream_t)stream;
   if (!b->cfg.use_graph) {
-    hipError_t e = enqueue(b, st);
+    hipError_t e = enqueue_forked(b, st);
     return e == hipSuccess ? PRAND_OK : hipfail(b->ctx, e);
   }
   if (!b->exec) {
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = enqueue(b, b->cap);
+      hipError_t le = enqueue_forked(b, b->cap);
       e = hipStreamEndCapture(b->cap, &b->graph);
       if (e == hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-      if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+      if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+      }
       return hipfail(b->ctx, e);
     }
   }
@@ -315,7 +388,7 @@ int prand_batch_autotune(prand_ctx* c, const prand_task* h_tasks, uint32_t ntask
   prand_batch_config pick{};
   fill_defaults(pick);
   pick.use_graph = 1;
-  const uint32_t waves[] = {8, 16, 32};
+  const uint32_t waves[] = {2, 4};
   const uint32_t regs[] = {512, 2048, 8192};
   const uint32_t gms[] = {1024, 4096, 16384};
   for (uint32_t w : waves)

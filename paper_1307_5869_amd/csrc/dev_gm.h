@@ -400,13 +400,14 @@ __device__ __forceinline__ void gq3_words_to_steps(uint64_t* N, uint32_t off, ui
 
 // Load element e of *in and move it `start` outputs ahead (start < 2^64).
 // Returns the word offset inside the GQ58.3 block (0 for the others).
-template <int G>
+// kJump = false: the caller guarantees start == 0 (no jump code is built).
+template <int G, bool kJump = true>
 __device__ __forceinline__ uint32_t load_at(const GmState* in, int e, uint64_t start, uint64_t& xc, uint64_t& xp,
                                             const uint64_t* __restrict__ ladder) {
   xc = in->xc[e];
   xp = in->xp[e];
   uint32_t off = (G == 6) ? in->off : 0;
-  if (start) {
+  if (kJump && start) {
     uint64_t N[kMaxLimbs + 1];
     for (int l = 0; l <= kMaxLimbs; l++) N[l] = 0;
     N[0] = start;
@@ -422,13 +423,13 @@ __device__ __forceinline__ uint32_t load_at(const GmState* in, int e, uint64_t s
 // (none when sout is null).
 // n must be the same for both halves (the ballot spans the wavefront); a dead
 // half (live = false) follows along without loads or stores.
-template <int G, int DT>
+template <int G, int DT, bool kJump = true>
 __device__ __forceinline__ void gen32_wave(bool live, const GmState* in, uint64_t start, uint64_t n, void* out,
                                            GmState* sout, const uint64_t* __restrict__ ladder) {
   const int li = threadIdx.x & 31;        // bit position of this element's digit
   const int e = 31 - li;                  // element index
   uint64_t xc = 0, xp = 0;
-  if (live) load_at<G>(in, e, start, xc, xp, ladder);
+  if (live) load_at<G, kJump>(in, e, start, xc, xp, ladder);
   Elem<G> el;
   el.load(xc, xp);
   // the word of step u goes to lane u of each half of the wavefront: a
@@ -466,12 +467,12 @@ __device__ __forceinline__ void gen32_wave(bool live, const GmState* in, uint64_
 
 // ---------------------------------------------- v = 4, s = 8: nibbles
 // Each aligned group of 8 lanes is one section (element e = lane & 7).
-template <int G, int DT>
+template <int G, int DT, bool kJump = true>
 __device__ __forceinline__ void gen8_wave(bool live, const GmState* in, uint64_t start, uint64_t n, void* out,
                                           GmState* sout, const uint64_t* __restrict__ ladder) {
   const int e = threadIdx.x & 7;
   uint64_t xc = 0, xp = 0;
-  if (live) load_at<G>(in, e, start, xc, xp, ladder);
+  if (live) load_at<G, kJump>(in, e, start, xc, xp, ladder);
   Elem<G> el;
   el.load(xc, xp);
   const int shift = 28 - 4 * e;
@@ -508,7 +509,7 @@ __device__ __forceinline__ void gen8_wave(bool live, const GmState* in, uint64_t
 // `off` words of the block consumed; a section emits block words from off on
 // and keeps the state at the start of the last, partially used block.
 // Groups of one wavefront may run different numbers of blocks.
-template <int DT>
+template <int DT, bool kJump = true>
 __device__ __forceinline__ void gq3_wave(bool live, const GmState* in, uint64_t start, uint64_t n, void* out,
                                          GmState* sout, const uint64_t* __restrict__ ladder) {
   constexpr int G = 6;
@@ -517,7 +518,7 @@ __device__ __forceinline__ void gq3_wave(bool live, const GmState* in, uint64_t 
   const bool elem = e < 12;
   uint64_t xc = 0, xp = 0;
   uint32_t off0 = 0;
-  if (live) off0 = load_at<G>(in, elem ? e : 0, start, xc, xp, ladder);
+  if (live) off0 = load_at<G, kJump>(in, elem ? e : 0, start, xc, xp, ladder);
   if (!elem) xc = xp = 0;
   Elem<G> el;
   el.load(xc, xp);

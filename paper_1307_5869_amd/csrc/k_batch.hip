@@ -1,15 +1,23 @@
-// Batched persistent generation: many tasks (generator, state, length,
-// dtype, output) of uneven sizes in one launch.
+// Batched generation: many tasks (generator, state, length, dtype, output) of
+// uneven sizes in one launch.
 //
 // The host cuts every task into tiles, one tile being the work of one
 // wavefront: 64 lane-sections of a MRG32K3A / LFSR113 task, 2 / 8 / 4
 // element-group sections of a GM/GQ task (32, 8 or 16 lanes per section), or
-// a whole MT19937 task (one wavefront per stream).  Sections start from the
-// task's state jumped to their first output, so tiles are independent.  A
-// fixed grid of wavefronts pulls tile indices from an atomic counter until
-// the list is exhausted -- every wavefront reaches that exit -- and runs the
-// generator family's wavefront routine, the same code the one-generator
-// kernels use.  The tile list is ordered longest first.
+// a whole MT19937 task (one wavefront per stream).  Sections are independent:
+// each starts from the task's state jumped to its first output.
+//
+// The launch is a small graph of kernels:
+//  - batch_starts_kernel jumps every MRG32K3A/LFSR113/GM/GQ section to its
+//    start and writes the state to the batch's scratch area (the jump code
+//    needs many registers, so it runs apart from the generation loops);
+//  - batch_reg_kernel, batch_gm_kernel<shape> (32-lane v = 1 ensembles,
+//    8-lane v = 4 ensembles, GQ58.3) and batch_mt_kernel generate, one
+//    wavefront per tile, from those states (or, for MT19937, from the task
+//    state) with the same wavefront routines as the one-generator kernels,
+//    and at their register counts.
+// The generation kernels are independent of each other; tiles within each
+// are ordered longest first, so the dispatcher starts the long ones early.
 #include "dev_gm.h"
 #include "dev_lfsr.h"
 #include "dev_mrg.h"
@@ -21,10 +29,6 @@ namespace prand {
 namespace {
 
 constexpr int kBatchCW = 32;
-
-// Each family's tile routine is kept out of line so that the fused kernel
-// needs the registers of the largest routine, not of all of them inlined
-// together.
 
 // section geometry of a tile: group gi of the wavefront takes section first + gi
 struct Sect {
@@ -42,94 +46,235 @@ __device__ __forceinline__ Sect section_of(const BatchTile& tl, const BatchTask&
   return s;
 }
 
-template <int DT>
-__device__ __noinline__ void run_mt(const BatchTask& tk, uint32_t* lds) {
-  mt::gen_wave<DT>(lds, (const MtState*)tk.state_in, (MtState*)tk.state_out, tk.n, tk.out);
+constexpr int gm_groups(int G) { return (G == 3 || G == 7) ? 8 : (G == 6 ? 4 : 2); }
+
+__device__ __forceinline__ uint32_t wave_index() { return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); }
+
+// ---------------------------------------------------------------- starts
+template <class G>
+__device__ __noinline__ void start_reg(const BatchTile& tl, const BatchTask& tk, char* scratch,
+                                       const uint32_t* ladder) {
+  const Sect s = section_of(tl, tk, 64);
+  if (!s.live) return;
+  typename G::State st = *(const typename G::State*)tk.state_in;
+  if (s.start) G::jump(st, s.start, ladder);
+  ((typename G::State*)(scratch + tl.starts))[threadIdx.x & 63] = st;
 }
 
+template <int G>
+__device__ __noinline__ void start_gm(const BatchTile& tl, const BatchTask& tk, char* scratch,
+                                      const uint64_t* ladder) {
+  constexpr int groups = gm_groups(G);
+  const Sect s = section_of(tl, tk, groups);
+  if (!s.live) return;
+  const int lane = threadIdx.x & 63;
+  const int gi = lane / (64 / groups);
+  int e;
+  if constexpr (groups == 2) e = 31 - (lane & 31);
+  else if constexpr (groups == 8) e = lane & 7;
+  else e = lane & 15;
+  if (G == 6 && e >= 12) return;   // GQ58.3: 12 elements in 16 lanes
+  uint64_t xc, xp;
+  const uint32_t off = gm::load_at<G>((const GmState*)tk.state_in, e, s.start, xc, xp, ladder);
+  GmState* dst = (GmState*)(scratch + tl.starts) + gi;
+  dst->xc[e] = xc;
+  dst->xp[e] = xp;
+  if (e == 0) {
+    dst->off = off;
+    dst->pad = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256) batch_starts_kernel(const BatchTile* __restrict__ tiles, uint32_t ntiles,
+                                                           const BatchTask* __restrict__ tasks, char* scratch,
+                                                           DeviceTables T) {
+  const uint32_t t = wave_index();
+  if (t >= ntiles) return;
+  const BatchTile tl = tiles[t];
+  const BatchTask tk = tasks[tl.task];
+  switch (tk.gen) {
+    case PRAND_MRG32K3A: start_reg<mrg::MrgGen>(tl, tk, scratch, T.mrg); break;
+    case PRAND_LFSR113: start_reg<lfsr::LfsrGen>(tl, tk, scratch, T.lfsr); break;
+    case PRAND_GM19: start_gm<0>(tl, tk, scratch, T.gm); break;
+    case PRAND_GM29: start_gm<1>(tl, tk, scratch, T.gm); break;
+    case PRAND_GM31: start_gm<2>(tl, tk, scratch, T.gm); break;
+    case PRAND_GM55: start_gm<3>(tl, tk, scratch, T.gm); break;
+    case PRAND_GM61: start_gm<4>(tl, tk, scratch, T.gm); break;
+    case PRAND_GQ58X1: start_gm<5>(tl, tk, scratch, T.gm); break;
+    case PRAND_GQ58X3: start_gm<6>(tl, tk, scratch, T.gm); break;
+    case PRAND_GQ58X4: start_gm<7>(tl, tk, scratch, T.gm); break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------------- MRG32K3A/LFSR113
 template <class G, int DT>
-__device__ __noinline__ void run_reg(const BatchTile& tl, const BatchTask& tk, uint32_t* lds, const uint32_t* ladder) {
+__device__ __forceinline__ void gen_reg(const BatchTile& tl, const BatchTask& tk, uint32_t* lds,
+                                        const char* scratch) {
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
   const Sect s = section_of(tl, tk, 64);
   void* o = (char*)tk.out + (s.live ? s.start : 0) * es;
-  regstream_wave<G, DT, kBatchCW>(lds, s.live, (const typename G::State*)tk.state_in, s.start, s.len, o,
-                                  s.last ? (typename G::State*)tk.state_out : nullptr, tl.coalesce != 0, ladder);
+  const typename G::State* in = (const typename G::State*)(scratch + tl.starts) + (threadIdx.x & 63);
+  regstream_wave<G, DT, kBatchCW, false>(lds, s.live, in, 0, s.len, o,
+                                         s.last ? (typename G::State*)tk.state_out : nullptr, tl.coalesce != 0,
+                                         nullptr);
 }
 
-// GM/GQ: a dead group follows along without loads or stores; the planner
-// gives both halves of a v = 1 tile the same length (tl.len32)
+__global__ void __launch_bounds__(256) batch_reg_kernel(const BatchTile* __restrict__ tiles, uint32_t ntiles,
+                                                        const BatchTask* __restrict__ tasks, const char* scratch) {
+  __shared__ __align__(16) uint32_t lds[4][RegStage<kBatchCW>::kWaveWords];
+  const uint32_t t = wave_index();
+  if (t >= ntiles) return;
+  uint32_t* mine = lds[(threadIdx.x >> 6) & 3];
+  const BatchTile tl = tiles[t];
+  const BatchTask tk = tasks[tl.task];
+  const bool mrg = tk.gen == PRAND_MRG32K3A;
+  switch (tk.dtype) {
+    case PRAND_U32:
+      if (mrg) gen_reg<mrg::MrgGen, PRAND_U32>(tl, tk, mine, scratch);
+      else gen_reg<lfsr::LfsrGen, PRAND_U32>(tl, tk, mine, scratch);
+      break;
+    case PRAND_F32:
+      if (mrg) gen_reg<mrg::MrgGen, PRAND_F32>(tl, tk, mine, scratch);
+      else gen_reg<lfsr::LfsrGen, PRAND_F32>(tl, tk, mine, scratch);
+      break;
+    default:
+      if (mrg) gen_reg<mrg::MrgGen, PRAND_F64>(tl, tk, mine, scratch);
+      else gen_reg<lfsr::LfsrGen, PRAND_F64>(tl, tk, mine, scratch);
+      break;
+  }
+}
+
+// ------------------------------------------------------------------ GM/GQ
+// A dead group follows along without loads or stores; the planner gives both
+// halves of a v = 1 tile the same length (tl.len32).
 template <int G, int DT>
-__device__ __noinline__ void run_gm(const BatchTile& tl, const BatchTask& tk, const uint64_t* ladder) {
+__device__ __forceinline__ void gen_gm(const BatchTile& tl, const BatchTask& tk, const char* scratch) {
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
-  constexpr int groups = (G == 3 || G == 7) ? 8 : (G == 6 ? 4 : 2);
+  constexpr int groups = gm_groups(G);
   const Sect s = section_of(tl, tk, groups);
   void* o = (char*)tk.out + (s.live ? s.start : 0) * es;
-  const GmState* in = (const GmState*)tk.state_in;
+  const int gi = (threadIdx.x & 63) / (64 / groups);
+  const GmState* in = (const GmState*)(scratch + tl.starts) + (s.live ? gi : 0);
   GmState* sout = s.last ? (GmState*)tk.state_out : nullptr;
-  if constexpr (G == 6) gm::gq3_wave<DT>(s.live, in, s.start, s.len, o, sout, ladder);
-  else if constexpr (groups == 8) gm::gen8_wave<G, DT>(s.live, in, s.start, s.len, o, sout, ladder);
-  else gm::gen32_wave<G, DT>(s.live, in, s.start, tl.len32, o, sout, ladder);
+  if constexpr (G == 6) gm::gq3_wave<DT, false>(s.live, in, 0, s.len, o, sout, nullptr);
+  else if constexpr (groups == 8) gm::gen8_wave<G, DT, false>(s.live, in, 0, s.len, o, sout, nullptr);
+  else gm::gen32_wave<G, DT, false>(s.live, in, 0, tl.len32, o, sout, nullptr);
 }
 
-template <int DT>
-__device__ __forceinline__ void run_tile_dt(const BatchTile& tl, const BatchTask& tk, uint32_t* lds,
-                                            const DeviceTables& T) {
-  switch (tk.gen) {
-    case PRAND_MT19937: run_mt<DT>(tk, lds); break;
-    case PRAND_MRG32K3A: run_reg<mrg::MrgGen, DT>(tl, tk, lds, T.mrg); break;
-    case PRAND_LFSR113: run_reg<lfsr::LfsrGen, DT>(tl, tk, lds, T.lfsr); break;
-    case PRAND_GM19: run_gm<0, DT>(tl, tk, T.gm); break;
-    case PRAND_GM29: run_gm<1, DT>(tl, tk, T.gm); break;
-    case PRAND_GM31: run_gm<2, DT>(tl, tk, T.gm); break;
-    case PRAND_GM55: run_gm<3, DT>(tl, tk, T.gm); break;
-    case PRAND_GM61: run_gm<4, DT>(tl, tk, T.gm); break;
-    case PRAND_GQ58X1: run_gm<5, DT>(tl, tk, T.gm); break;
-    case PRAND_GQ58X3: run_gm<6, DT>(tl, tk, T.gm); break;
-    default: run_gm<7, DT>(tl, tk, T.gm); break;
+// one kernel per ensemble shape, so each runs at its own register count:
+// S = 0: v = 1 (32 lanes per section), 1: v = 4 (8 lanes), 2: GQ58.3
+template <int S, int DT>
+__device__ __forceinline__ void gen_gm_dt(const BatchTile& tl, const BatchTask& tk, const char* scratch) {
+  if constexpr (S == 0) {
+    switch (tk.gen) {
+      case PRAND_GM19: gen_gm<0, DT>(tl, tk, scratch); break;
+      case PRAND_GM29: gen_gm<1, DT>(tl, tk, scratch); break;
+      case PRAND_GM31: gen_gm<2, DT>(tl, tk, scratch); break;
+      case PRAND_GM61: gen_gm<4, DT>(tl, tk, scratch); break;
+      default: gen_gm<5, DT>(tl, tk, scratch); break;
+    }
+  } else if constexpr (S == 1) {
+    if (tk.gen == PRAND_GM55) gen_gm<3, DT>(tl, tk, scratch);
+    else gen_gm<7, DT>(tl, tk, scratch);
+  } else {
+    gen_gm<6, DT>(tl, tk, scratch);
   }
 }
 
-__global__ void batch_reset_kernel(uint32_t* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+template <int S>
+__global__ void __launch_bounds__(256) batch_gm_kernel(const BatchTile* __restrict__ tiles, uint32_t ntiles,
+                                                       const BatchTask* __restrict__ tasks, const char* scratch) {
+  const uint32_t t = wave_index();
+  if (t >= ntiles) return;
+  const BatchTile tl = tiles[t];
+  const BatchTask tk = tasks[tl.task];
+  switch (tk.dtype) {
+    case PRAND_U32: gen_gm_dt<S, PRAND_U32>(tl, tk, scratch); break;
+    case PRAND_F32: gen_gm_dt<S, PRAND_F32>(tl, tk, scratch); break;
+    default: gen_gm_dt<S, PRAND_F64>(tl, tk, scratch); break;
+  }
 }
 
-__global__ void __launch_bounds__(256) batch_kernel(const BatchTile* __restrict__ tiles, uint32_t ntiles,
-                                                    const BatchTask* __restrict__ tasks, uint32_t* counter,
-                                                    DeviceTables T) {
-  __shared__ __align__(16) uint32_t lds[4][RegStage<kBatchCW>::kWaveWords];
-  uint32_t* mine = lds[threadIdx.x >> 6];
+// --------------------------------------------------- MT19937 and n = 0 tasks
+__global__ void __launch_bounds__(256) batch_mt_kernel(const BatchTile* __restrict__ tiles, uint32_t ntiles,
+                                                       const BatchTask* __restrict__ tasks) {
+  __shared__ uint32_t mt[4][624];
+  const uint32_t t = wave_index();
+  if (t >= ntiles) return;
   const int lane = threadIdx.x & 63;
-  for (;;) {
-    uint32_t t = 0;
-    if (lane == 0) t = atomicAdd(counter, 1u);
-    t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
-    if (t >= ntiles) break;
-    const BatchTile tl = tiles[t];
-    const BatchTask tk = tasks[tl.task];
-    if (tl.kind == kTileCopy) {
-      // n = 0: the output state is the input state
-      const uint32_t* a = (const uint32_t*)tk.state_in;
-      uint32_t* b = (uint32_t*)tk.state_out;
-      for (uint32_t i = lane; i < tl.len32; i += 64) b[i] = a[i];
-      continue;
-    }
-    switch (tk.dtype) {
-      case PRAND_U32: run_tile_dt<PRAND_U32>(tl, tk, mine, T); break;
-      case PRAND_F32: run_tile_dt<PRAND_F32>(tl, tk, mine, T); break;
-      default: run_tile_dt<PRAND_F64>(tl, tk, mine, T); break;
-    }
+  const BatchTile tl = tiles[t];
+  const BatchTask tk = tasks[tl.task];
+  if (tl.kind == kTileCopy) {
+    // n = 0: the output state is the input state
+    const uint32_t* a = (const uint32_t*)tk.state_in;
+    uint32_t* b = (uint32_t*)tk.state_out;
+    for (uint32_t i = lane; i < tl.len32; i += 64) b[i] = a[i];
+    return;
+  }
+  uint32_t* mine = mt[(threadIdx.x >> 6) & 3];
+  const MtState* in = (const MtState*)tk.state_in;
+  MtState* out = (MtState*)tk.state_out;
+  switch (tk.dtype) {
+    case PRAND_U32: mt::gen_wave<PRAND_U32>(mine, in, out, tk.n, tk.out); break;
+    case PRAND_F32: mt::gen_wave<PRAND_F32>(mine, in, out, tk.n, tk.out); break;
+    default: mt::gen_wave<PRAND_F64>(mine, in, out, tk.n, tk.out); break;
   }
 }
+
+uint32_t blocks_for(uint32_t ntiles, uint32_t waves) { return (ntiles + waves - 1) / waves; }
 
 }  // namespace
 
-hipError_t launch_batch(const DeviceTables& T, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
-                        uint32_t* counter, uint32_t blocks, hipStream_t st) {
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, counter);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(batch_kernel, dim3(blocks), dim3(256), 0, st, tiles, ntiles, tasks, counter, T);
+hipError_t launch_batch_starts(const DeviceTables& T, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
+                               char* scratch, uint32_t waves, hipStream_t st) {
+  if (!ntiles) return hipSuccess;
+  hipLaunchKernelGGL(batch_starts_kernel, dim3(blocks_for(ntiles, waves)), dim3(64 * waves), 0, st, tiles, ntiles,
+                     tasks, scratch, T);
   return hipGetLastError();
+}
+
+hipError_t launch_batch_reg(const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks, const char* scratch,
+                            uint32_t waves, hipStream_t st) {
+  if (!ntiles) return hipSuccess;
+  hipLaunchKernelGGL(batch_reg_kernel, dim3(blocks_for(ntiles, waves)), dim3(64 * waves), 0, st, tiles, ntiles,
+                     tasks, scratch);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gm(int shape, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
+                           const char* scratch, uint32_t waves, hipStream_t st) {
+  if (!ntiles) return hipSuccess;
+  const dim3 grid(blocks_for(ntiles, waves)), block(64 * waves);
+  switch (shape) {
+    case 0: hipLaunchKernelGGL(batch_gm_kernel<0>, grid, block, 0, st, tiles, ntiles, tasks, scratch); break;
+    case 1: hipLaunchKernelGGL(batch_gm_kernel<1>, grid, block, 0, st, tiles, ntiles, tasks, scratch); break;
+    default: hipLaunchKernelGGL(batch_gm_kernel<2>, grid, block, 0, st, tiles, ntiles, tasks, scratch); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_mt(const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks, uint32_t waves,
+                           hipStream_t st) {
+  if (!ntiles) return hipSuccess;
+  hipLaunchKernelGGL(batch_mt_kernel, dim3(blocks_for(ntiles, waves)), dim3(64 * waves), 0, st, tiles, ntiles, tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_serial(const DeviceTables& T, const BatchTile* tiles, const BatchCounts& n,
+                               const BatchTask* tasks, char* scratch, uint32_t waves, hipStream_t st) {
+  const BatchTile* reg = tiles;
+  const BatchTile* g32 = reg + n.reg;
+  const BatchTile* g8 = g32 + n.g32;
+  const BatchTile* g3 = g8 + n.g8;
+  const BatchTile* mt = g3 + n.g3;
+  hipError_t e = launch_batch_mt(mt, n.mt + n.copy, tasks, waves, st);
+  if (e == hipSuccess) e = launch_batch_starts(T, tiles, n.with_starts(), tasks, scratch, waves, st);
+  if (e == hipSuccess) e = launch_batch_gm(2, g3, n.g3, tasks, scratch, waves, st);
+  if (e == hipSuccess) e = launch_batch_gm(1, g8, n.g8, tasks, scratch, waves, st);
+  if (e == hipSuccess) e = launch_batch_gm(0, g32, n.g32, tasks, scratch, waves, st);
+  if (e == hipSuccess) e = launch_batch_reg(reg, n.reg, tasks, scratch, waves, st);
+  return e;
 }
 
 }  // namespace prand

@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(256) gm_gen32_kernel(const GmState* sin, GmSta
   const uint64_t s = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
   const bool live = s < count;
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
-  gen32_wave<G, DT>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
+  gen32_wave<G, DT, false>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
 }
 
 template <int G, int DT>
@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(256) gm_gen8_kernel(const GmState* sin, GmStat
   const uint64_t s = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const bool live = s < count;
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
-  gen8_wave<G, DT>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
+  gen8_wave<G, DT, false>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
 }
 
 template <int DT>
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) gq58x3_gen_kernel(const GmState* sin, GmS
   const uint64_t s = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const bool live = s < count;
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
-  gq3_wave<DT>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
+  gq3_wave<DT, false>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
 }
 
 // One lane per element slot (32 per stream): states[s] = base (or states[s])

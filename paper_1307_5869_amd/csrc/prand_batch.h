@@ -1,5 +1,5 @@
-// Batched persistent launch: task and tile records shared by the host
-// planner (batch.hip) and the persistent kernel (k_batch.hip).
+// Batched launch: task and tile records shared by the host planner
+// (batch.hip) and the batch kernels (k_batch.hip).
 #pragma once
 
 #include <vector>
@@ -32,14 +32,43 @@ struct BatchTile {
   uint32_t coalesce;   // MRG32K3A/LFSR113: every section start 16-byte aligned
   uint64_t len32;      // v = 1 GM/GQ tiles: the common length of the live
                        // sections; copy tiles: 32-bit words of the state
+  uint64_t starts;     // byte offset of the tile's section start states in
+                       // the batch scratch (MRG32K3A/LFSR113 and GM/GQ tiles)
+};
+
+// tiles are stored family by family: [reg | g32 | g8 | g3 | mt | copy]
+// (MRG32K3A/LFSR113; GM/GQ with v = 1, with v = 4, GQ58.3; MT19937; n = 0)
+struct BatchCounts {
+  uint32_t reg = 0, g32 = 0, g8 = 0, g3 = 0, mt = 0, copy = 0;
+  uint32_t with_starts() const { return reg + g32 + g8 + g3; }
+  uint32_t total() const { return with_starts() + mt + copy; }
+};
+constexpr int kBatchFamilies = 6;
+
+struct BatchPlan {
+  std::vector<BatchTile> tiles;
+  BatchCounts n;
+  uint64_t scratch_bytes = 0;
 };
 
 // zero fields of a configuration replaced by the defaults
 void batch_fill_defaults(prand_batch_config& c);
-// cut tasks into tiles, longest first (PRAND_OK or an error code)
-int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, std::vector<BatchTile>& tiles);
+// cut tasks into tiles, family by family, each family longest first
+// (PRAND_OK or an error code)
+int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, BatchPlan& plan);
 
-hipError_t launch_batch(const DeviceTables& T, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
-                        uint32_t* counter, uint32_t blocks, hipStream_t st);
+// the kernels of a batch, `waves` wavefronts (tiles) per workgroup
+hipError_t launch_batch_starts(const DeviceTables& T, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
+                               char* scratch, uint32_t waves, hipStream_t st);
+hipError_t launch_batch_reg(const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks, const char* scratch,
+                            uint32_t waves, hipStream_t st);
+// shape 0: v = 1 ensembles, 1: v = 4 ensembles, 2: GQ58.3
+hipError_t launch_batch_gm(int shape, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
+                           const char* scratch, uint32_t waves, hipStream_t st);
+hipError_t launch_batch_mt(const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks, uint32_t waves,
+                           hipStream_t st);
+// all of them on one stream: MT19937, section starts, GM/GQ, MRG32K3A/LFSR113
+hipError_t launch_batch_serial(const DeviceTables& T, const BatchTile* tiles, const BatchCounts& n,
+                               const BatchTask* tasks, char* scratch, uint32_t waves, hipStream_t st);
 
 }  // namespace prand

@@ -84,8 +84,8 @@ constexpr int kMtDigitE = 432;
 // Order a wavefront's LDS writes before its later LDS reads (and reads before
 // later writes) when the LDS block is private to the wavefront: LDS
 // instructions of one wavefront execute in order, so only the compiler must
-// be kept from reordering.  No workgroup barrier: wavefronts of a persistent
-// workgroup run different amounts of work.
+// be kept from reordering.  No workgroup barrier: wavefronts of one workgroup
+// may run different amounts of work (or leave early).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

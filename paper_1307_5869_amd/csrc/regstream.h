@@ -12,7 +12,7 @@
 // by lane.
 //
 // regstream_wave() is the wavefront routine shared by the many-stream kernel
-// below and by the batched persistent kernel.
+// below and by the batched generation kernel.
 #pragma once
 
 #include <cstdlib>
@@ -38,11 +38,12 @@ __device__ __forceinline__ void put_word(void* out, uint64_t i, uint32_t w, doub
 // ahead), write `len` values at `out` (element pointer of the run) and, when
 // `sout` is set, store the advanced state there.  `coalesce`: every run start
 // is 16-byte aligned (transposed stores allowed).  All 64 lanes must call.
+// kJump = false: the caller guarantees start == 0 (no jump code is built).
 //
 // G: State, Regs, static load(State) -> Regs, static save(Regs) -> State,
 // static jump(State&, uint64_t distance, const uint32_t* ladder),
 // static next(Regs&) -> uint32_t word, static f64(uint32_t) -> double.
-template <class G, int DT, int CW>
+template <class G, int DT, int CW, bool kJump = true>
 __device__ __forceinline__ void regstream_wave(uint32_t* rows, bool live, const typename G::State* in, uint64_t start,
                                                uint64_t len, void* out, typename G::State* sout, bool coalesce,
                                                const uint32_t* __restrict__ ladder) {
@@ -53,7 +54,7 @@ __device__ __forceinline__ void regstream_wave(uint32_t* rows, bool live, const 
   typename G::State st = {};
   if (live) {
     st = *in;
-    if (start) G::jump(st, start, ladder);
+    if (kJump && start) G::jump(st, start, ladder);
   }
   typename G::Regs r = G::load(st);
   // full chunks every live lane can still write (wavefront minimum)

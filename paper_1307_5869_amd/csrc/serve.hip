@@ -16,8 +16,8 @@
 //     group into a staging area, then a scatter into each request's first
 //     state slot;
 //  4. per lane, with fewer than two launches in flight, enqueues one loop
-//     iteration: a batched persistent launch holding the next chunk of every
-//     ready request of the lane.  Chunks are an equal share of the
+//     iteration: a batched launch (the batch kernels, in order on the lane's
+//     stream) holding the next chunk of every ready request of the lane.  Chunks are an equal share of the
 //     iteration's output budget (never below the minimum chunk; MT19937
 //     chunks are capped); a request's state ping-pongs between its two slots,
 //     so consecutive chunks continue the stream exactly.
@@ -164,7 +164,8 @@ struct IterSlot {
   BatchTile* h_tiles = nullptr;    // pinned
   BatchTile* d_tiles = nullptr;
   uint32_t task_cap = 0, tile_cap = 0;
-  uint32_t* d_counter = nullptr;
+  char* d_scratch = nullptr;     // section start states of the iteration's tiles
+  uint64_t scratch_cap = 0;
   hipEvent_t start = nullptr, end = nullptr;
   std::vector<Req*> finishing;
   bool in_flight = false;
@@ -189,7 +190,6 @@ struct prand_server {
   prand_ctx* ctx = nullptr;
   prand_server_config cfg{};
   prand_batch_config bcfg{};
-  uint32_t blocks = 0;
   std::chrono::steady_clock::time_point t0;
 
   std::thread worker;
@@ -209,7 +209,7 @@ struct prand_server {
   char* d_arena = nullptr;
   std::deque<Req*> waiting;
   Lane lane[kLanes];
-  std::vector<BatchTile> tiles;
+  BatchPlan plan;
   std::vector<prand_task> tasks;
 
   double now() const {
@@ -273,8 +273,8 @@ void layout_request(Req* r, char* base, const prand_server_config& cfg) {
   }
 }
 
-hipError_t grow_slot(prand_server* s, IterSlot& sl, uint32_t ntasks, uint32_t ntiles) {
-  if (ntasks <= sl.task_cap && ntiles <= sl.tile_cap) return hipSuccess;
+hipError_t grow_slot(prand_server* s, IterSlot& sl, uint32_t ntasks, uint32_t ntiles, uint64_t scratch) {
+  if (ntasks <= sl.task_cap && ntiles <= sl.tile_cap && scratch <= sl.scratch_cap) return hipSuccess;
   // the slot is idle (its last launch has been waited for)
   hipError_t e = hipSuccess;
   if (ntasks > sl.task_cap) {
@@ -298,6 +298,14 @@ hipError_t grow_slot(prand_server* s, IterSlot& sl, uint32_t ntasks, uint32_t nt
     e = hipHostMalloc((void**)&sl.h_tiles, cap * sizeof(BatchTile), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_tiles, cap * sizeof(BatchTile));
     if (e == hipSuccess) sl.tile_cap = cap;
+  }
+  if (e == hipSuccess && scratch > sl.scratch_cap) {
+    const uint64_t cap = std::max<uint64_t>(scratch, sl.scratch_cap * 2);
+    (void)hipFree(sl.d_scratch);
+    sl.d_scratch = nullptr;
+    sl.scratch_cap = 0;
+    e = hipMalloc((void**)&sl.d_scratch, cap);
+    if (e == hipSuccess) sl.scratch_cap = cap;
   }
   (void)s;
   return e;
@@ -442,18 +450,20 @@ int enqueue_iteration(prand_server* s, Lane& L, IterSlot& sl, bool* launched) {
     }
     if (r->issued == r->r.n) sl.finishing.push_back(r);
   }
-  int rc = batch_plan(s->tasks.data(), (uint32_t)s->tasks.size(), s->bcfg, s->tiles);
+  BatchPlan& plan = s->plan;
+  int rc = batch_plan(s->tasks.data(), (uint32_t)s->tasks.size(), s->bcfg, plan);
   if (rc) return rc;
-  hipError_t e = grow_slot(s, sl, (uint32_t)s->tasks.size(), (uint32_t)s->tiles.size());
+  hipError_t e = grow_slot(s, sl, (uint32_t)s->tasks.size(), (uint32_t)plan.tiles.size(), plan.scratch_bytes);
   if (e != hipSuccess) return hipfail(s->ctx, e);
   std::memcpy(sl.h_tasks, s->tasks.data(), s->tasks.size() * sizeof(prand_task));
-  std::memcpy(sl.h_tiles, s->tiles.data(), s->tiles.size() * sizeof(BatchTile));
+  std::memcpy(sl.h_tiles, plan.tiles.data(), plan.tiles.size() * sizeof(BatchTile));
   e = hipMemcpyAsync(sl.d_tasks, sl.h_tasks, s->tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice, L.gen_st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(sl.d_tiles, sl.h_tiles, s->tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice, L.gen_st);
+    e = hipMemcpyAsync(sl.d_tiles, sl.h_tiles, plan.tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice, L.gen_st);
   if (e == hipSuccess) e = hipEventRecord(sl.start, L.gen_st);
   if (e == hipSuccess)
-    e = launch_batch(s->ctx->T, sl.d_tiles, (uint32_t)s->tiles.size(), sl.d_tasks, sl.d_counter, s->blocks, L.gen_st);
+    e = launch_batch_serial(s->ctx->T, sl.d_tiles, plan.n, sl.d_tasks, sl.d_scratch, s->bcfg.waves_per_block,
+                            L.gen_st);
   if (e == hipSuccess) e = hipEventRecord(sl.end, L.gen_st);
   if (e != hipSuccess) return hipfail(s->ctx, e);
   sl.in_flight = true;
@@ -629,7 +639,7 @@ void free_server(prand_server* s) {
       (void)hipHostFree(sl.h_tiles);
       (void)hipFree(sl.d_tasks);
       (void)hipFree(sl.d_tiles);
-      (void)hipFree(sl.d_counter);
+      (void)hipFree(sl.d_scratch);
       if (sl.start) (void)hipEventDestroy(sl.start);
       if (sl.end) (void)hipEventDestroy(sl.end);
     }
@@ -666,11 +676,10 @@ int prand_server_create(prand_ctx* c, const prand_server_config* cfg, prand_serv
   s->ctx = c;
   if (cfg) s->cfg = *cfg;
   fill_config(s->cfg);
-  s->bcfg.waves_per_cu = s->cfg.waves_per_cu;
+  s->bcfg.waves_per_block = s->cfg.waves_per_block;
   s->bcfg.reg_section = s->cfg.reg_section;
   s->bcfg.gm_section = s->cfg.gm_section;
   batch_fill_defaults(s->bcfg);
-  s->blocks = (uint32_t)std::max<uint64_t>(1, ((uint64_t)c->num_cus * s->bcfg.waves_per_cu + 3) / 4);
   s->t0 = std::chrono::steady_clock::now();
   DeviceGuard g(c->device);
   hipError_t e = hipMalloc((void**)&s->d_arena, s->cfg.hbm_budget);
@@ -694,10 +703,9 @@ int prand_server_create(prand_ctx* c, const prand_server_config* cfg, prand_serv
     if (e == hipSuccess) e = hipMalloc((void**)&ib.d_staging, kInitMax * kStateSlot);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ib.ev, hipEventDisableTiming);
     for (IterSlot& sl : L.slot) {
-      if (e == hipSuccess) e = hipMalloc((void**)&sl.d_counter, 64);
       if (e == hipSuccess) e = hipEventCreate(&sl.start);
       if (e == hipSuccess) e = hipEventCreate(&sl.end);
-      if (e == hipSuccess) e = grow_slot(s, sl, 1024, 16384);
+      if (e == hipSuccess) e = grow_slot(s, sl, 1024, 16384, 16384 * 1536);
     }
   }
   if (e != hipSuccess) {

@@ -62,7 +62,7 @@ class Task(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     """struct prand_batch_config (zeros select the defaults)"""
-    _fields_ = [("waves_per_cu", ctypes.c_uint32), ("reg_section", ctypes.c_uint32),
+    _fields_ = [("waves_per_block", ctypes.c_uint32), ("reg_section", ctypes.c_uint32),
                 ("gm_section", ctypes.c_uint32), ("use_graph", ctypes.c_uint32)]
 
 
@@ -71,7 +71,7 @@ class ServerConfig(ctypes.Structure):
     """struct prand_server_config (zeros select the defaults)"""
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("iter_numbers", ctypes.c_uint64), ("min_chunk", ctypes.c_uint64),
                 ("mt_chunk", ctypes.c_uint64), ("mt_section", ctypes.c_uint64), ("max_active", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
-                ("waves_per_cu", ctypes.c_uint32), ("reg_section", ctypes.c_uint32),
+                ("waves_per_block", ctypes.c_uint32), ("reg_section", ctypes.c_uint32),
                 ("gm_section", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 

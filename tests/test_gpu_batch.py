@@ -1,4 +1,4 @@
-"""Batched persistent launch: every task's output and advanced state equal
+"""Batched launch: every task's output and advanced state equal
 the oracle's sequential generation and the plain per-stream launches, for
 mixed generators, dtypes and uneven lengths, across configurations and HIP
 graph replays."""
@@ -58,7 +58,7 @@ def mixed_specs():
     return specs
 
 
-@pytest.mark.parametrize("cfg", [None, (8, 512, 1024, 1), (32, 8192, 16384, 0), (4, 32, 32, 1)])
+@pytest.mark.parametrize("cfg", [None, (2, 512, 1024, 1), (4, 8192, 16384, 0), (1, 32, 32, 1)])
 def test_batch_matches_oracle(ctx, oracle, cfg):
     tasks, refs = make_tasks(oracle, mixed_specs())
     conf = P.BatchConfig(*cfg) if cfg else None
@@ -74,7 +74,7 @@ def test_batch_graph_replays(ctx, oracle):
     """Replays of the captured graph, with eager work between them, all give
     the same result (the input states are never written)."""
     tasks, refs = make_tasks(oracle, mixed_specs()[::3], seed0=900)
-    b = P.Batch(ctx, tasks, P.BatchConfig(16, 2048, 4096, 1))
+    b = P.Batch(ctx, tasks, P.BatchConfig(4, 2048, 4096, 1))
     for rep in range(4):
         for (_, _, _, _, sout, out) in tasks:
             out.zero_()
@@ -137,10 +137,10 @@ def test_autotune_returns_a_working_config(ctx, oracle, tmp_path, monkeypatch):
     specs = [(g, P.F32, 20000 + 1000 * g) for g in range(11)]
     tasks, refs = make_tasks(oracle, specs, seed0=1300)
     best = P.autotune(ctx, tasks)
-    assert best.waves_per_cu in (8, 16, 32) and best.use_graph == 1
+    assert best.waves_per_block in (2, 4) and best.use_graph == 1
     again = P.autotune(ctx, tasks)          # second call: from the cache file
-    assert (again.waves_per_cu, again.reg_section, again.gm_section) == \
-        (best.waves_per_cu, best.reg_section, best.gm_section)
+    assert (again.waves_per_block, again.reg_section, again.gm_section) == \
+        (best.waves_per_block, best.reg_section, best.gm_section)
     assert (tmp_path / "tune.txt").read_text().count("\n") == 1
     b = P.Batch(ctx, tasks, best)
     b.launch()
