@@ -24,7 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit lane ops/s: 256 CUs x 64 lanes x 2.4 GHz
+# 32-bit integer VALU lane-ops/s: the fp32 vector peak (157.3 TFLOP/s, an FMA
+# counted as two) is 78.6 T lane-ops/s = 256 CUs x 128 lanes x 2.4 GHz, and
+# 32-bit integer XOR/ADD/shift/compare issue at that rate
+VALU_PEAK_TOPS = 157.3 / 2
 
 
 def log(msg):

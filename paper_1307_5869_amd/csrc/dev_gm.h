@@ -68,22 +68,21 @@ struct Eng<1> {
   __device__ static uint32_t digit(F x) { return x >= (g + 1) / 2; }
 };
 
-// GM31: g = 2^31 - 1, k = 11, q = 14; exact in FP64 (|k x - q x'| < 2^36)
+// GM31: g = 2^31 - 1, k = 11, q = 14: one 64-bit product sum (< 25 * 2^31)
+// folded with 2^31 = 1 (mod g)
 template <>
 struct Eng<2> {
   static constexpr bool kComposite = false;
-  using F = double;
-  __device__ static F to_fast(uint64_t x) { return (double)x; }
-  __device__ static uint64_t from_fast(F y) { return (uint64_t)y; }
+  using F = uint32_t;
+  static constexpr uint32_t g = 2147483647u;
+  __device__ static F to_fast(uint64_t x) { return (F)x; }
+  __device__ static uint64_t from_fast(F y) { return y; }
   __device__ static F step(F xc, F xp) {
-    const double g = 2147483647.0, inv = 1.0 / 2147483647.0;
-    const double t = fma(11.0, xc, -14.0 * xp);
-    const double k = floor(t * inv);
-    double r = fma(-k, g, t);
-    r = (r < 0.0) ? r + g : r;
-    return (r >= g) ? r - g : r;
+    const uint64_t t = (uint64_t)11u * xc + (uint64_t)14u * (g - xp);
+    const uint32_t r = ((uint32_t)t & g) + (uint32_t)(t >> 31);   // < 2^31 + 25
+    return min(r, r - g);
   }
-  __device__ static uint32_t digit(F x) { return x >= 1073741824.0; }
+  __device__ static uint32_t digit(F x) { return x >= (1u << 30); }
 };
 
 // GM61: g = 2^61 - 1, k = 24, q = 74
