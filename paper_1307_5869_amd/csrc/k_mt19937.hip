@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(64) mt_generate_kernel(MtState* states, uint32
 }
 
 // ------------------------------------------------------------------ jump
-constexpr int kRing = 2048;                 // LDS ring of sequence words
+constexpr int kRing = 1024;                 // LDS ring of sequence words (< 900 live at a time)
 constexpr int kMask = kRing - 1;
 constexpr int kMirror = 16;                 // ring[0..15] repeated after the end
 constexpr int kDeg = 19937;
