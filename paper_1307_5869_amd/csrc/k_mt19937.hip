@@ -68,46 +68,47 @@ __device__ __forceinline__ void extend(uint32_t* ring, int& gen_hi, int upto, in
   }
 }
 
-// ring[0..623] holds a window (next output = tempered successor); replace it
-// by g(A) applied to it, g = poly (624 words of coefficient bits).
+// ring[0..623] holds a window (next output = tempered successor); apply_poly
+// replaces it by g(A) applied to it, g = poly (624 words of coefficient bits).
 // Lane l accumulates outputs t = 10 l + r.  For the coefficients i0 .. i0 + 9
 // of a group it holds the sequence words seq[i0 + 10 l + k] (cur) and
 // seq[i0 + 10 + 10 l + k] (nxt), k < 10: coefficient i0 + u adds
-// seq[i0 + u + 10 l + r], which is cur[u + r] or nxt[u + r - 10].
+// seq[i0 + u + 10 l + r], which is cur[u + r] or nxt[u + r - 10].  Groups
+// come in pairs that swap the roles of two register windows, so no window
+// is ever copied.
+__device__ __forceinline__ void group(uint32_t* ring, int& gen_hi, int i0, uint32_t bits, int lane,
+                                      uint32_t (&acc)[kPer], const uint32_t (&cur)[kPer], uint32_t (&nxt)[kPer]) {
+  extend(ring, gen_hi, i0 + 660, lane);
+  if (i0 + kPer > kDeg) bits &= (1u << (kDeg - i0)) - 1;
+  const uint32_t* src = ring + ((i0 + kPer + kPer * lane) & kMask);   // + k < kRing + kMirror
+#pragma unroll
+  for (int k = 0; k < kPer; k++) nxt[k] = src[k];
+#pragma unroll
+  for (int u = 0; u < kPer; u++) {
+    if ((bits >> u) & 1u) {
+#pragma unroll
+      for (int r = 0; r < kPer; r++) acc[r] ^= (u + r < kPer) ? cur[u + r] : nxt[u + r - kPer];
+    }
+  }
+}
+
 __device__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, int lane) {
   int gen_hi = 624;
   extend(ring, gen_hi, 660, lane);
-  uint32_t acc[kPer], cur[kPer], nxt[kPer];
+  uint32_t acc[kPer], wa[kPer], wb[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; r++) {
     acc[r] = 0;
-    cur[r] = ring[kPer * lane + r];
+    wa[r] = ring[kPer * lane + r];
   }
-  // three groups (30 coefficients) share one 64-bit load of the polynomial:
-  // bits i1 .. i1 + 29 lie in the words i1 / 32 and i1 / 32 + 1
-  for (int i1 = 0; i1 < kDeg; i1 += 3 * kPer) {
+  // two groups (20 coefficients) per 64-bit load of the polynomial: bits
+  // i1 .. i1 + 19 lie in the words i1 / 32 and i1 / 32 + 1
+  for (int i1 = 0; i1 < kDeg; i1 += 2 * kPer) {
     const int w = i1 >> 5, sh = i1 & 31;
     const uint64_t pair = (uint64_t)poly[w] | ((w + 1 < 624) ? ((uint64_t)poly[w + 1] << 32) : 0ull);
-#pragma unroll
-    for (int g = 0; g < 3; g++) {
-      const int i0 = i1 + g * kPer;
-      if (i0 >= kDeg) break;
-      extend(ring, gen_hi, i0 + 660, lane);
-      uint32_t bits = (uint32_t)(pair >> (sh + g * kPer)) & ((1u << kPer) - 1);
-      if (i0 + kPer > kDeg) bits &= (1u << (kDeg - i0)) - 1;
-      const uint32_t* src = ring + ((i0 + kPer + kPer * lane) & kMask);   // + k < kRing + kMirror
-#pragma unroll
-      for (int k = 0; k < kPer; k++) nxt[k] = src[k];
-#pragma unroll
-      for (int u = 0; u < kPer; u++) {
-        if ((bits >> u) & 1u) {
-#pragma unroll
-          for (int r = 0; r < kPer; r++) acc[r] ^= (u + r < kPer) ? cur[u + r] : nxt[u + r - kPer];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kPer; k++) cur[k] = nxt[k];
-    }
+    const uint32_t bits = (uint32_t)(pair >> sh);
+    group(ring, gen_hi, i1, bits & ((1u << kPer) - 1), lane, acc, wa, wb);
+    if (i1 + kPer < kDeg) group(ring, gen_hi, i1 + kPer, (bits >> kPer) & ((1u << kPer) - 1), lane, acc, wb, wa);
   }
   __syncthreads();
 #pragma unroll
