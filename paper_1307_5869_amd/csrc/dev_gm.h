@@ -499,6 +499,12 @@ __device__ __forceinline__ void gen8_wave(bool live, const GmState* in, uint64_t
     el.get(xc, xp);
     sout->xc[e] = xc;
     sout->xp[e] = xp;
+    // the blob's unused element slots (8 .. 31) are zero
+#pragma unroll
+    for (int z = e + 8; z < 32; z += 8) {
+      sout->xc[z] = 0;
+      sout->xp[z] = 0;
+    }
     if (e == 0) { sout->off = 0; sout->pad = 0; }
   }
 }
@@ -559,6 +565,16 @@ __device__ __forceinline__ void gq3_wave(bool live, const GmState* in, uint64_t 
     if (rem && nb > 0) saved.get(xc, xp); else el.get(xc, xp);
     sout->xc[e] = xc;
     sout->xp[e] = xp;
+  }
+  if (live && sout) {
+    // the blob's unused element slots (12 .. 31) are zero: lanes 12 .. 15
+    // clear their own slot, every lane the slot 16 + e
+    if (!elem) {
+      sout->xc[e] = 0;
+      sout->xp[e] = 0;
+    }
+    sout->xc[16 + e] = 0;
+    sout->xp[16 + e] = 0;
   }
   if (live && sout && e == 0) { sout->off = rem; sout->pad = 0; }
 }

@@ -30,7 +30,8 @@ def make_tasks(oracle, specs, seed0=500):
         if gen in (0, 9) and k % 3 == 1:
             oracle.generate(gen, st, 5 + k % 7)   # start inside a block
         sin = torch.from_numpy(st.copy()).cuda()
-        sout = torch.zeros_like(sin)
+        # garbage in the output state: every byte of the blob must be written
+        sout = torch.full_like(sin, 0xA5)
         out = torch.empty(max(n, 1), dtype=TDT[dt], device="cuda")
         ref_state = st.copy()
         ref = oracle.generate(gen, ref_state, n, dt) if n else np.empty(0, NPDT[dt])
@@ -78,7 +79,7 @@ def test_batch_graph_replays(ctx, oracle):
     for rep in range(4):
         for (_, _, _, _, sout, out) in tasks:
             out.zero_()
-            sout.zero_()
+            sout.fill_(0x5A)
         b.launch()
         torch.cuda.synchronize()
         check(tasks, refs)
