@@ -133,12 +133,12 @@ def main():
                     "peak": VALU_PEAK_TOPS, "unit": "Tops/s"}
     else:
         if g == P.MT19937:
-            # XOR-sum: per stream one table polynomial per nonzero 12-bit digit
+            # XOR-sum: per stream one table polynomial per nonzero 16-bit digit
             # of the id's low 48 bits (its top 16 bits select a precomputed
             # start state), each costing (set coefficients ~ 19937/2) x 624
             # word XORs
             idv = W.stream_ids(S, g)
-            apps = int(sum(sum(1 for k in range(4) if (int(x) >> (12 * k)) & 4095) for x in idv))
+            apps = int(sum(sum(1 for k in range(3) if (int(x) >> (16 * k)) & 0xFFFF) for x in idv))
             ops = apps * (19937 // 2) * 624
             roof = {"kernel": "MT19937 jump", "bound": "alu", "achieved": ops / t / 1e12, "peak": VALU_PEAK_TOPS,
                     "unit": "Tops/s"}

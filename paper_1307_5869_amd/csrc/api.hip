@@ -89,11 +89,11 @@ hipError_t upload(T** dst, const T* src, size_t n) {
 hipError_t ensure_mt(prand_ctx* c) {
   // caller holds c->mu
   if (c->mt_ready) return hipSuccess;
-  std::vector<uint32_t> mt((size_t)kLadder * 624), d12((size_t)kMtDig12Count * 4096 * 624),
+  std::vector<uint32_t> mt((size_t)kLadder * 624), dlo((size_t)kMtLoDigits * kMtLoSize * 624),
       d8((size_t)2 * 256 * 624);
-  if (!mt_build_polys(mt.data(), kLadder, d12.data(), d8.data(), kMtDigitE)) return hipErrorUnknown;
+  if (!mt_build_polys(mt.data(), kLadder, dlo.data(), d8.data(), kMtDigitE)) return hipErrorUnknown;
   hipError_t e = upload(&c->T.mt, mt.data(), mt.size());
-  if (e == hipSuccess) e = upload(&c->T.mtdig12, d12.data(), d12.size());
+  if (e == hipSuccess) e = upload(&c->T.mtdiglo, dlo.data(), dlo.size());
   if (e == hipSuccess) e = upload(&c->T.mtdig8hi, d8.data(), d8.size());
   // the default state jumped t * 2^(432 + 48) for every top-16-bit value t
   // of an id, by the jump kernel's general digit path
@@ -264,7 +264,7 @@ int prand_ctx_destroy(prand_ctx* c) {
   (void)hipFree(c->T.lfsr);
   (void)hipFree(c->T.gm);
   (void)hipFree(c->T.mt);
-  (void)hipFree(c->T.mtdig12);
+  (void)hipFree(c->T.mtdiglo);
   (void)hipFree(c->T.mtdig8hi);
   (void)hipFree(c->T.mttop);
   (void)hipFree(c->T.defaults);

@@ -14,10 +14,10 @@
 // being the raw-word sequence continued from the state.  A distance is applied
 // as one polynomial x^(2^b) mod phi (from the context ladder) per set bit b;
 // block splitting by id * 2^432 from a block-aligned state uses the context's
-// digit tables x^(d 2^(432 + position)) mod phi instead: four 12-bit digits for
-// the low 48 bits of the id and two bytes for the top 16 bits; from the
+// digit tables x^(d 2^(432 + position)) mod phi instead: three 16-bit digits
+// for the low 48 bits of the id and two bytes for the top 16 bits; from the
 // default state the top 16 bits come from a table of precomputed states, so a
-// stream costs at most 4 polynomials.
+// stream costs at most 3 polynomials.
 // One wavefront does one stream: the sequence is produced 227 words at a time
 // into an LDS ring, and lane l accumulates outputs t = 10l .. 10l+9 while a
 // register window of 10 sequence words slides over the coefficients, so each
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
                                                      const MtState* __restrict__ base,
                                                      const MtState* __restrict__ top,
                                                      const uint32_t* __restrict__ ladder,
-                                                     const uint32_t* __restrict__ dig12,
+                                                     const uint32_t* __restrict__ diglo,
                                                      const uint32_t* __restrict__ dig8hi) {
   __shared__ uint32_t ring[kRing + kMirror];
   const uint32_t s = blockIdx.x;
@@ -152,14 +152,14 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
   __syncthreads();
   if (digit_path && idx == 624) {
     // block splitting from a block-aligned state: id * 2^432 with the low 48
-    // bits of id as four 12-bit digits and the top 16 bits as two bytes, one
+    // bits of id as 16-bit digits and the top 16 bits as two bytes, one
     // table polynomial x^(d 2^(432 + position)) per nonzero digit; the top
     // bytes are already in the start state when it came from the table of
     // top-16-bit states
     const uint64_t id = ids[s];
-    for (int k = 0; k < kMtDig12Count; k++) {
-      const uint32_t d = (uint32_t)(id >> (12 * k)) & 4095u;
-      if (d) apply_poly(ring, dig12 + ((size_t)k * 4096 + d) * 624, lane);
+    for (int k = 0; k < kMtLoDigits; k++) {
+      const uint32_t d = (uint32_t)(id >> (kMtLoBits * k)) & (uint32_t)(kMtLoSize - 1);
+      if (d) apply_poly(ring, diglo + ((size_t)k * kMtLoSize + d) * 624, lane);
     }
     if (!top) {
       for (int j = 0; j < 2; j++) {
@@ -215,7 +215,7 @@ hipError_t launch_mt_generate(MtState* states, uint32_t count, uint64_t n, int d
 hipError_t launch_mt_jump(const DeviceTables& T, MtState* states, uint32_t count, const JumpSpec& js,
                           const MtState* base, hipStream_t st) {
   hipLaunchKernelGGL(mt_jump_kernel, dim3(count), dim3(64), 0, st, states, count, js.dist, js.nlimbs, js.per_stream,
-                     js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdig12, T.mtdig8hi);
+                     js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi);
   return hipGetLastError();
 }
 

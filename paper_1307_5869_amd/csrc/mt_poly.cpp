@@ -5,11 +5,11 @@
 // generator's F2-linear transition; computing g_v is sequential work, so the
 // paper precomputes polynomials for v = 2^n.  Here phi is found by
 // Berlekamp-Massey on 2 * 19937 output bits, and products modulo phi use the
-// x86 carry-less multiply with Barrett reduction (mu = floor(x^(2n) / phi)),
-// about a millisecond per product, so that besides the 2^b ladder the
-// context can hold per-byte digit tables x^(d * 2^(e + 8j)) mod phi: a stream
-// id then costs one polynomial application per nonzero byte instead of one
-// per set bit.
+// x86 carry-less multiply (Karatsuba over a schoolbook base) with Barrett
+// reduction (mu = floor(x^(2n) / phi)), about 0.1 ms per product, so that
+// besides the 2^b ladder the context can hold digit tables
+// x^(d * 2^(e + position)) mod phi: a stream id then costs one polynomial
+// application per nonzero digit instead of one per set bit.
 #include "mt_poly.h"
 
 #include <wmmintrin.h>
@@ -117,6 +117,65 @@ __attribute__((target("pclmul,sse2"))) void clmul(const uint64_t* a, int na, con
   }
 }
 
+// r[0..2n) = a * b for n <= kBase words: every word product added into a
+// 128-bit column, then the columns folded into 64-bit words
+constexpr int kBase = 24;
+__attribute__((target("pclmul,sse2"))) void mul_base(const uint64_t* a, const uint64_t* b, int n, uint64_t* r) {
+  __m128i col[2 * kBase];
+  for (int k = 0; k < 2 * n; k++) col[k] = _mm_setzero_si128();
+  for (int i = 0; i < n; i++) {
+    const __m128i A = _mm_set_epi64x(0, (long long)a[i]);
+    for (int j = 0; j < n; j++)
+      col[i + j] = _mm_xor_si128(col[i + j], _mm_clmulepi64_si128(A, _mm_set_epi64x(0, (long long)b[j]), 0x00));
+  }
+  uint64_t carry = 0;
+  for (int k = 0; k < 2 * n; k++) {
+    r[k] = (uint64_t)_mm_cvtsi128_si64(col[k]) ^ carry;
+    carry = (uint64_t)_mm_cvtsi128_si64(_mm_unpackhi_epi64(col[k], col[k]));
+  }
+}
+
+// r[0..2n) = a * b (n words each) by Karatsuba down to mul_base; tmp holds
+// at least 8 n words
+void kmul(const uint64_t* a, const uint64_t* b, int n, uint64_t* r, uint64_t* tmp) {
+  if (n <= kBase) {
+    mul_base(a, b, n, r);
+    return;
+  }
+  const int h = (n + 1) / 2, l = n - h;   // a = a0 + x^(64 h) a1, a1 of l <= h words
+  uint64_t* sa = tmp;                      // a0 + a1 (h words)
+  uint64_t* sb = tmp + h;                  // b0 + b1
+  uint64_t* z1 = tmp + 2 * h;              // (a0 + a1)(b0 + b1), 2 h words
+  uint64_t* sub = tmp + 4 * h;             // scratch of the recursive calls
+  for (int i = 0; i < h; i++) {
+    sa[i] = a[i] ^ (i < l ? a[h + i] : 0);
+    sb[i] = b[i] ^ (i < l ? b[h + i] : 0);
+  }
+  kmul(a, b, h, r, sub);                   // z0 -> r[0 .. 2h)
+  if (l == h) {
+    kmul(a + h, b + h, l, r + 2 * h, sub); // z2 -> r[2h .. 2n)
+  } else {
+    // odd split: z2 of the shorter halves, padded to h words
+    uint64_t* pa = sub;
+    uint64_t* pb = sub + h;
+    uint64_t* pz = sub + 2 * h;
+    for (int i = 0; i < h; i++) {
+      pa[i] = i < l ? a[h + i] : 0;
+      pb[i] = i < l ? b[h + i] : 0;
+    }
+    kmul(pa, pb, h, pz, sub + 4 * h);
+    for (int i = 0; i < 2 * l; i++) r[2 * h + i] = pz[i];
+  }
+  kmul(sa, sb, h, z1, sub);
+  // middle term z1 - z0 - z2 at word offset h
+  for (int i = 0; i < 2 * h; i++) {
+    const uint64_t z0 = r[i];
+    const uint64_t z2 = i < 2 * l ? r[2 * h + i] : 0;
+    z1[i] ^= z0 ^ z2;
+  }
+  for (int i = 0; i < 2 * h && h + i < 2 * n; i++) r[h + i] ^= z1[i];
+}
+
 // a >> s into out (nout words)
 void shr(const uint64_t* a, int na, int s, uint64_t* out, int nout) {
   const int q = s >> 6, r = s & 63;
@@ -153,12 +212,12 @@ struct Field {
 
   // r = a * b mod phi (a, b, r: kW words, degree < n)
   void mulmod(const uint64_t* a, const uint64_t* b, uint64_t* r) const {
-    uint64_t c[2 * kW], hi[kW + 1], t[2 * kW + 2], q[kW + 1], s[2 * kW + 2];
-    clmul(a, kW, b, kW, c);                 // degree < 2n - 1
+    uint64_t c[2 * kW + 2], hi[kW + 1], t[2 * kW + 2], q[kW + 1], s[2 * kW + 2], tmp[8 * (kW + 1)];
+    kmul(a, b, kW, c, tmp);                 // degree < 2n - 1
     shr(c, 2 * kW, kN, hi, kW + 1);         // c div x^n
-    clmul(hi, kW + 1, mu.data(), kW + 1, t);
+    kmul(hi, mu.data(), kW + 1, t, tmp);
     shr(t, 2 * kW + 2, kN, q, kW + 1);      // quotient
-    clmul(q, kW + 1, phi.data(), kW + 1, s);
+    kmul(q, phi.data(), kW + 1, s, tmp);
     for (int w = 0; w < kW; w++) r[w] = c[w] ^ s[w];
     r[kW - 1] &= (1ull << (kN - 64 * (kW - 1))) - 1;   // keep bits < n
   }
@@ -173,14 +232,14 @@ void store(const uint64_t* p, uint32_t* out) {
 
 }  // namespace
 
-bool mt_build_polys(uint32_t* ladder, int nladder, uint32_t* dig12, uint32_t* dig8hi, int digit_e) {
+bool mt_build_polys(uint32_t* ladder, int nladder, uint32_t* dig_lo, uint32_t* dig8hi, int digit_e) {
   Field F;
   if (!F.init()) return false;
   std::vector<uint64_t> lad((size_t)nladder * kW, 0);
   lad[0] = 2;   // x
   for (int b = 0; b + 1 < nladder; b++) F.mulmod(&lad[(size_t)b * kW], &lad[(size_t)b * kW], &lad[(size_t)(b + 1) * kW]);
   for (int b = 0; b < nladder; b++) store(&lad[(size_t)b * kW], ladder + (size_t)b * kMtPolyWords);
-  if (!dig12 && !dig8hi) return true;
+  if (!dig_lo && !dig8hi) return true;
   if (digit_e + 64 > nladder) return false;
   // work items: (digit base exponent, digit width, first digit, last digit, output table)
   struct Item {
@@ -189,17 +248,17 @@ bool mt_build_polys(uint32_t* ladder, int nladder, uint32_t* dig12, uint32_t* di
     uint32_t* out;
   };
   std::vector<Item> items;
-  if (dig12) {
-    std::memset(dig12, 0, sizeof(uint32_t) * kMtDig12Count * 4096 * kMtPolyWords);
-    for (int k = 0; k < kMtDig12Count; k++)
-      for (uint32_t d0 = 1; d0 < 4096; d0 += 256)
-        items.push_back({digit_e + 12 * k, 12, d0, std::min<uint32_t>(d0 + 256, 4096),
-                         dig12 + (size_t)k * 4096 * kMtPolyWords});
+  if (dig_lo) {
+    std::memset(dig_lo, 0, sizeof(uint32_t) * kMtLoDigits * kMtLoSize * kMtPolyWords);
+    for (int k = 0; k < kMtLoDigits; k++)
+      for (uint32_t d0 = 1; d0 < (uint32_t)kMtLoSize; d0 += 256)
+        items.push_back({digit_e + kMtLoBits * k, kMtLoBits, d0, std::min<uint32_t>(d0 + 256, kMtLoSize),
+                         dig_lo + (size_t)k * kMtLoSize * kMtPolyWords});
   }
   if (dig8hi) {
     std::memset(dig8hi, 0, sizeof(uint32_t) * 2 * 256 * kMtPolyWords);
     for (int j = 0; j < 2; j++)
-      items.push_back({digit_e + 12 * kMtDig12Count + 8 * j, 8, 1, 256, dig8hi + (size_t)j * 256 * kMtPolyWords});
+      items.push_back({digit_e + 48 + 8 * j, 8, 1, 256, dig8hi + (size_t)j * 256 * kMtPolyWords});
   }
   // x^(d 2^e): the first digit of an item from the ladder (one factor per set
   // bit), each next one by one more multiplication by x^(2^e)

@@ -10,15 +10,18 @@ constexpr int kMtDeg = 19937;      // degree of the characteristic polynomial ph
 constexpr int kMtPolyWords = 624;  // 32-bit words per reduced polynomial
 
 // Digit tables for block splitting by id * 2^e (e = the block exponent): the
-// low 48 bits of an id as four 12-bit digits, the top 16 bits as two bytes.
-constexpr int kMtDig12Count = 4;
+// low 48 bits of an id as kMtLoDigits digits of kMtLoBits bits, the top 16
+// bits as two bytes.
+constexpr int kMtLoBits = 16;
+constexpr int kMtLoDigits = 48 / kMtLoBits;
+constexpr int kMtLoSize = 1 << kMtLoBits;
 
 // ladder: nladder polynomials x^(2^b) mod phi, b < nladder (624 words each).
-// dig12 (may be null): 4 x 4096 polynomials x^(d * 2^(digit_e + 12 k)) mod phi
-// for k < 4, d < 4096; dig8hi (may be null): 2 x 256 polynomials
-// x^(d * 2^(digit_e + 48 + 8 j)) mod phi for j < 2, d < 256 (d = 0 left zero
-// in both).  phi comes from Berlekamp-Massey on MT19937 output bits.  Returns
+// dig_lo (may be null): kMtLoDigits x kMtLoSize polynomials
+// x^(d * 2^(digit_e + kMtLoBits k)) mod phi; dig8hi (may be null): 2 x 256
+// polynomials x^(d * 2^(digit_e + 48 + 8 j)) mod phi (d = 0 left zero in
+// both).  phi comes from Berlekamp-Massey on MT19937 output bits.  Returns
 // false if phi has the wrong degree or the ladder is too short.
-bool mt_build_polys(uint32_t* ladder, int nladder, uint32_t* dig12, uint32_t* dig8hi, int digit_e);
+bool mt_build_polys(uint32_t* ladder, int nladder, uint32_t* dig_lo, uint32_t* dig8hi, int digit_e);
 
 }  // namespace prand

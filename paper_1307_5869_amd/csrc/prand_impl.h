@@ -72,7 +72,7 @@ struct DeviceTables {
   uint32_t* lfsr = nullptr;   // [kLadder][4][32]: columns of T_c^(2^b)
   uint64_t* gm = nullptr;     // [8][kLadder][4]: (a b; c d) = M^(2^b) mod p
   uint32_t* mt = nullptr;     // [kLadder][624]: bits of x^(2^b) mod phi (19937 used)
-  uint32_t* mtdig12 = nullptr;  // [4][4096][624]: x^(d 2^(kMtDigitE + 12k)) mod phi
+  uint32_t* mtdiglo = nullptr;  // [3][65536][624]: x^(d 2^(kMtDigitE + 16k)) mod phi
   uint32_t* mtdig8hi = nullptr; // [2][256][624]: x^(d 2^(kMtDigitE + 48 + 8j)) mod phi
   void* mttop = nullptr;        // [65536] MtState: the default state jumped t 2^(kMtDigitE + 48)
   void* defaults = nullptr;   // default state of each generator, 11 x 2560 bytes

@@ -153,9 +153,9 @@ VARIANTS = {g: [v for v in range(5) if P.block_log2(g, v) >= 0] for g in GENS}
 def test_init_streams_match_oracle(ctx, oracle, gen):
     ids = [0, 1, 2, 3, 10**19 - 1, 2**64 - 1, 123456789012345678]
     if gen == 0:
-        # digit boundaries of the MT19937 tables: 12-bit digits below bit 48,
+        # digit boundaries of the MT19937 tables: 16-bit digits below bit 48,
         # precomputed states above it
-        ids = [0, 1, 10**19 - 1, 987654321, 2**64 - 1, 1 << 48, (1 << 48) - 1]
+        ids = [0, 1, 10**19 - 1, 987654321, 2**64 - 1, 1 << 48, (1 << 48) - 1, 1 << 32, 65535]
     for v in VARIANTS[gen]:
         t = torch.tensor(np.array(ids, dtype=np.uint64).view(np.int64), device="cuda")
         d = torch.empty(len(ids) * P.state_bytes(gen), dtype=torch.uint8, device="cuda")
