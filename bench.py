@@ -151,7 +151,18 @@ def main():
     roof["traffic"] = recorded_traffic(roof["kernel"])
 
     extra = {}
+    write_probe = None
     if not args.no_dtype_sweep:
+        # context for the HBM-bound kernels: a plain device fill of the same
+        # 4 GiB (torch's fill kernel), outside the timed region
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        out.fill_(1)
+        a.record(stream)
+        out.fill_(2)
+        b.record(stream)
+        b.synchronize()
+        write_probe = {"bytes": out.numel() * 4, "ms": round(a.elapsed_time(b), 4),
+                       "GBs": out.numel() * 4 / (a.elapsed_time(b) * 1e-3) / 1e9}
         # outside the timed region: every dtype for every generator, one launch each
         big = torch.empty(S * N * 2, dtype=torch.int32, device=dev)
         for g in gens:
@@ -207,6 +218,7 @@ def main():
         "roofline": roof,
         "per_generator": per_gen,
         "dtype_sweep": extra,
+        "fill_probe": write_probe,
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,
