@@ -38,12 +38,18 @@ HOST_SOURCES = {"mt_poly.cpp"}
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-mpclmul", "-msse4.1", "-pthread", "-I", CSRC]
 
 
+# per-source extra device flags: the MT19937 jump kernel scans jump
+# coefficients with uniform branches joined by gotos; left unstructured they
+# compile to one scalar compare and branch per coefficient
+SOURCE_FLAGS = {"k_mt19937.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"]}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if os.path.basename(src) in HOST_SOURCES:
         cmd = [HOST_CXX] + HOST_FLAGS + ["-c", src, "-o", obj]
     else:
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
+        cmd = [HIPCC] + FLAGS + SOURCE_FLAGS.get(os.path.basename(src), []) + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -21,7 +21,8 @@
 // One wavefront does one stream: the sequence is produced 227 words at a time
 // into an LDS ring, and lane l accumulates outputs t = 10l .. 10l+9 while a
 // register window of 10 sequence words slides over the coefficients, so each
-// coefficient costs one LDS read per lane and, when set, 10 XORs.
+// coefficient costs one LDS read per lane and set coefficients cost 10
+// three-input XORs per two.
 #include "dev_mt.h"
 #include "mt_poly.h"
 
@@ -69,32 +70,44 @@ __device__ __forceinline__ void extend(uint32_t* ring, int& gen_hi, int upto, in
 }
 
 // ring[0..623] holds a window (next output = tempered successor); apply_poly
-// replaces it by g(A) applied to it, g = poly (624 words of coefficient bits).
-// Lane l accumulates outputs t = 10 l + r.  For the coefficients i0 .. i0 + 9
-// of a group it holds the sequence words seq[i0 + 10 l + k] (cur) and
-// seq[i0 + 10 + 10 l + k] (nxt), k < 10: coefficient i0 + u adds
-// seq[i0 + u + 10 l + r], which is cur[u + r] or nxt[u + r - 10].  Groups
-// come in pairs that swap the roles of two register windows, so no window
-// is ever copied.
-__device__ __forceinline__ void group(uint32_t* ring, int& gen_hi, int i0, uint32_t bits, int lane,
-                                      uint32_t (&acc)[kPer], const uint32_t (&cur)[kPer], uint32_t (&nxt)[kPer]) {
-  extend(ring, gen_hi, i0 + 660, lane);
-  if (i0 + kPer > kDeg) bits &= (1u << (kDeg - i0)) - 1;
-  const uint32_t* src = ring + ((i0 + kPer + kPer * lane) & kMask);   // + k < kRing + kMirror
+// replaces it by g(A) applied to it, g = poly (624 words of coefficient bits,
+// reduced: no bit at or above 19937 is set).  Lane l accumulates outputs
+// t = 10 l + r.  For the coefficients i0 .. i0 + 9 of a group it holds the
+// sequence words seq[i0 + 10 l + k] (cur) and seq[i0 + 10 + 10 l + k] (nxt),
+// k < 10: coefficient i0 + u adds seq[i0 + u + 10 l + r], which is
+// cur[u + r] or nxt[u + r - 10].  Groups come in pairs that swap the roles
+// of two register windows, so no window is ever copied.
+//
+// The coefficient bits are uniform across the wavefront, so the scan over
+// them is scalar branching.  Each bit is tested once; a set bit waits for the
+// next set bit of its group and the two are added with one three-input XOR
+// (gfx950 v_bitop3_b32, truth table 0x96) per output word: a group with c set
+// coefficients costs ceil(c / 2) instead of c vector instructions per output
+// word.  The scan is a chain of labels joined by gotos (mt_pairs.inc), built
+// with the structurizer told to leave uniform regions alone, so every test is
+// one scalar compare and branch.
+__device__ __forceinline__ void group(uint32_t* ring, uint32_t i0, uint32_t bits, int lane, uint32_t (&acc)[kPer],
+                                      const uint32_t (&cur)[kPer], uint32_t (&nxt)[kPer]) {
+  // i0 + 10 + 10 lane is even, so the window is read in 8-byte pairs
+  const uint32_t* src = ring + ((i0 + kPer + kPer * lane) & (kMask & ~1));   // + k < kRing + kMirror
 #pragma unroll
   for (int k = 0; k < kPer; k++) nxt[k] = src[k];
-#pragma unroll
-  for (int u = 0; u < kPer; u++) {
-    if ((bits >> u) & 1u) {
-#pragma unroll
-      for (int r = 0; r < kPer; r++) acc[r] ^= (u + r < kPer) ? cur[u + r] : nxt[u + r - kPer];
-    }
-  }
+#define MT_W2(k) (((k) < kPer) ? cur[(k)] : nxt[(k) - kPer])
+#define MT_BIT(u) ((bits >> (u)) & 1u)
+#define MT_PAIR(p, q)                                                                              \
+  _Pragma("unroll") for (int r = 0; r < kPer; r++) acc[r] =                                        \
+      __builtin_amdgcn_bitop3_b32(acc[r], MT_W2((p) + r), MT_W2((q) + r), 0x96);
+#define MT_ONE(p) _Pragma("unroll") for (int r = 0; r < kPer; r++) acc[r] ^= MT_W2((p) + r);
+#include "mt_pairs.inc"
+#undef MT_ONE
+#undef MT_PAIR
+#undef MT_BIT
+#undef MT_W2
 }
 
-__device__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, int lane) {
+__device__ __forceinline__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, int lane) {
   int gen_hi = 624;
-  extend(ring, gen_hi, 660, lane);
+  extend(ring, gen_hi, 680, lane);
   uint32_t acc[kPer], wa[kPer], wb[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; r++) {
@@ -102,13 +115,24 @@ __device__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, in
     wa[r] = ring[kPer * lane + r];
   }
   // two groups (20 coefficients) per 64-bit load of the polynomial: bits
-  // i1 .. i1 + 19 lie in the words i1 / 32 and i1 / 32 + 1
-  for (int i1 = 0; i1 < kDeg; i1 += 2 * kPer) {
-    const int w = i1 >> 5, sh = i1 & 31;
-    const uint64_t pair = (uint64_t)poly[w] | ((w + 1 < 624) ? ((uint64_t)poly[w + 1] << 32) : 0ull);
-    const uint32_t bits = (uint32_t)(pair >> sh);
-    group(ring, gen_hi, i1, bits & ((1u << kPer) - 1), lane, acc, wa, wb);
-    if (i1 + kPer < kDeg) group(ring, gen_hi, i1 + kPer, (bits >> kPer) & ((1u << kPer) - 1), lane, acc, wb, wa);
+  // i1 .. i1 + 19 lie in the words i1 / 32 and i1 / 32 + 1 (i1 <= 19920, so
+  // both exist).  A pair of groups at i1 reads sequence words below
+  // i1 + 660; the ring is extended 227 words at a time and every pair that
+  // its words allow runs before the next extension (near the end the
+  // sequence stops at kSeqLen: the words past it meet only coefficients at
+  // or above 19937, which are zero, or outputs t >= 624, which are dropped).
+  uint32_t i1 = 0;
+  while (i1 < (uint32_t)kDeg) {
+    extend(ring, gen_hi, (int)i1 + 680, lane);
+    const uint32_t lim = (gen_hi >= kSeqLen) ? (uint32_t)kDeg : (uint32_t)(gen_hi - 660);
+    do {
+      const uint32_t w = i1 >> 5, sh = i1 & 31;
+      const uint64_t pair = (uint64_t)poly[w] | ((uint64_t)poly[w + 1] << 32);
+      const uint32_t bits = (uint32_t)(pair >> sh);
+      group(ring, i1, bits & ((1u << kPer) - 1), lane, acc, wa, wb);
+      group(ring, i1 + kPer, (bits >> kPer) & ((1u << kPer) - 1), lane, acc, wb, wa);
+      i1 += 2 * kPer;
+    } while (i1 <= lim && i1 < (uint32_t)kDeg);
   }
   __syncthreads();
 #pragma unroll
@@ -119,6 +143,19 @@ __device__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, in
   __syncthreads();
 }
 
+// Lowest set bit of the multi-limb number N at or above bit `from`, or -1.
+__device__ __forceinline__ int next_bit(const uint64_t (&N)[kMaxLimbs], int from) {
+#pragma unroll
+  for (int l = 0; l < kMaxLimbs; l++) {
+    if (from < 64 * (l + 1)) {
+      uint64_t w = N[l];
+      if (from > 64 * l) w &= ~0ull << (from - 64 * l);
+      if (w) return 64 * l + __builtin_ctzll(w);
+    }
+  }
+  return -1;
+}
+
 __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ states, uint32_t count,
                                                      const uint64_t* __restrict__ dist, int nlimbs, int per_stream,
                                                      const uint64_t* __restrict__ ids, int block_e,
@@ -127,7 +164,7 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
                                                      const uint32_t* __restrict__ ladder,
                                                      const uint32_t* __restrict__ diglo,
                                                      const uint32_t* __restrict__ dig8hi) {
-  __shared__ uint32_t ring[kRing + kMirror];
+  __shared__ __align__(16) uint32_t ring[kRing + kMirror];
   const uint32_t s = blockIdx.x;
   if (s >= count) return;
   const int lane = threadIdx.x;
@@ -150,31 +187,24 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
   for (int i = lane; i < 624; i += 64) ring[i] = src->mt[i];
   uint32_t idx = src->idx < 624u ? src->idx : 624u;
   __syncthreads();
-  if (digit_path && idx == 624) {
-    // block splitting from a block-aligned state: id * 2^432 with the low 48
-    // bits of id as 16-bit digits and the top 16 bits as two bytes, one
-    // table polynomial x^(d 2^(432 + position)) per nonzero digit; the top
-    // bytes are already in the start state when it came from the table of
-    // top-16-bit states
-    const uint64_t id = ids[s];
-    for (int k = 0; k < kMtLoDigits; k++) {
-      const uint32_t d = (uint32_t)(id >> (kMtLoBits * k)) & (uint32_t)(kMtLoSize - 1);
-      if (d) apply_poly(ring, diglo + ((size_t)k * kMtLoSize + d) * 624, lane);
-    }
-    if (!top) {
-      for (int j = 0; j < 2; j++) {
-        const uint32_t d = (uint32_t)(id >> (48 + 8 * j)) & 255u;
-        if (d) apply_poly(ring, dig8hi + ((size_t)j * 256 + d) * 624, lane);
-      }
-    }
-  } else {
-    // consume the rest of the current block first
+  // the polynomials to apply, in order: for block splitting from a
+  // block-aligned state, id * 2^432 with the low 48 bits of id as 16-bit
+  // digits and the top 16 bits as two bytes, one table polynomial
+  // x^(d 2^(432 + position)) per nonzero digit (the top bytes are already in
+  // the start state when it came from the table of top-16-bit states);
+  // otherwise one ladder polynomial x^(2^b) per set bit b of the distance
+  // left after the rest of the current block.  One call site keeps a single
+  // copy of the polynomial code.
+  const bool use_digits = digit_path && idx == 624;
+  const uint64_t id = ids ? ids[s] : 0;
+  if (!use_digits) {
     const uint64_t rest = 624 - idx;
     bool small = true;
     for (int l = 1; l < kMaxLimbs; l++) small = small && (N[l] == 0);
     small = small && (N[0] <= rest);
     if (small) {
       idx += (uint32_t)N[0];
+      for (int l = 0; l < kMaxLimbs; l++) N[l] = 0;
     } else {
       uint64_t borrow = rest;
       for (int l = 0; l < kMaxLimbs && borrow; l++) {
@@ -183,15 +213,32 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
         borrow = old < borrow ? 1 : 0;
       }
       idx = 624;
-      for (int l = 0; l < kMaxLimbs; l++) {
-        uint64_t wd = N[l];
-        while (wd) {
-          const int b = __builtin_ctzll(wd) + 64 * l;
-          wd &= wd - 1;
-          apply_poly(ring, ladder + (size_t)b * 624, lane);
+    }
+  }
+  const int ndig = top ? kMtLoDigits : kMtLoDigits + 2;
+  int pos = 0;
+  for (;;) {
+    const uint32_t* poly = nullptr;
+    if (use_digits) {
+      for (; pos < ndig && !poly; pos++) {
+        if (pos < kMtLoDigits) {
+          const uint32_t d = (uint32_t)(id >> (kMtLoBits * pos)) & (uint32_t)(kMtLoSize - 1);
+          if (d) poly = diglo + ((size_t)pos * kMtLoSize + d) * 624;
+        } else {
+          const int j = pos - kMtLoDigits;
+          const uint32_t d = (uint32_t)(id >> (48 + 8 * j)) & 255u;
+          if (d) poly = dig8hi + ((size_t)j * 256 + d) * 624;
         }
       }
+    } else {
+      const int b = next_bit(N, pos);
+      if (b >= 0) {
+        poly = ladder + (size_t)b * 624;
+        pos = b + 1;
+      }
     }
+    if (!poly) break;
+    apply_poly(ring, poly, lane);
   }
   MtState* dst = states + s;
   for (int i = lane; i < 624; i += 64) dst->mt[i] = ring[i];
