@@ -93,10 +93,16 @@ struct Eng<4> {
   static constexpr uint64_t g = 2305843009213693951ull;
   __device__ static F to_fast(uint64_t x) { return x; }
   __device__ static uint64_t from_fast(F y) { return y; }
+  // 24 xc + 74 s with s = g - xp (g is 61 one bits: a complement), in
+  // 32-bit halves: A = 24 xc_lo + 74 s_lo < 2^39 and B = 24 xc_hi + 74 s_hi
+  // < 2^36 give B 2^32 + A = (B mod 2^29) 2^32 + (B >> 29) + A (mod g), a
+  // sum below 2^61 + 2^40 < 2 g: one conditional subtraction
   __device__ static F step(F xc, F xp) {
-    const u128 t = (u128)24u * xc + (u128)74u * (g - xp);   // < 2^68
-    const uint64_t lo = (uint64_t)t, hi = (uint64_t)(t >> 64);
-    uint64_t r = (lo & g) + ((lo >> 61) | (hi << 3));
+    const uint64_t s = xp ^ g;
+    const uint64_t A = (uint64_t)(uint32_t)xc * 24u + (uint64_t)(uint32_t)s * 74u;
+    const uint64_t B = (uint64_t)(uint32_t)(xc >> 32) * 24u + (uint64_t)(uint32_t)(s >> 32) * 74u;
+    const uint32_t bhi = __builtin_amdgcn_alignbit((uint32_t)(B >> 32), (uint32_t)B, 29);   // B >> 29 < 2^7
+    const uint64_t r = A + bhi + ((B & 0x1FFFFFFFull) << 32);
     return r >= g ? r - g : r;
   }
   __device__ static uint32_t digit(F x) { return x >= (1ull << 60); }
@@ -155,19 +161,17 @@ struct EngGQ {
     return (uint32_t)(d0 + ((d0 + 1) * p <= num));
   }
   // fast recurrence on y = x / 2^29 mod p in 32-bit integers:
-  // 8 yc - 48 yp = 8 (yc + 6 (p - yp)) mod p, each factor folded with
-  // 2^29 = 3 (mod p); every intermediate stays below 2^32
+  // 8 yc - 48 yp = 8 u mod p with u = yc + 6 (p - yp) < 7 p < 2^32.  With
+  // u = a 2^26 + b (b < 2^26), 8 u = a 2^29 + 8 b = 3 a + 8 b (mod p), and
+  // 3 a + 8 b < 2^29 + 189 < 2 p: one fold and one conditional subtraction
   using F = uint32_t;
   static constexpr uint32_t kP = 536870909u, kM = 0x1FFFFFFFu;
   __device__ static F to_fast(uint64_t x) { return (uint32_t)(x >> 29); }
   __device__ static uint64_t from_fast(F y) { return ((uint64_t)y) << 29; }
   __device__ static F step(F yc, F yp) {
-    const uint32_t sv = kP - yp;                      // <= p
-    const uint32_t u = yc + ((sv + (sv << 1)) << 1);  // yc + 6 sv < 7 p < 2^32
-    uint32_t w = (u & kM) + __umul24(3u, u >> 29);    // < 2 p
-    w = min(w, w - kP);                               // < p
-    const uint32_t z = ((w << 3) & kM) + __umul24(3u, w >> 26);   // 8 w folded, < 2 p
-    return min(z, z - kP);
+    const uint32_t u = yc + 6u * (kP - yp);                         // < 7 p < 2^32
+    const uint32_t w = ((u << 3) & kM) + __umul24(3u, u >> 26);     // = 8 u mod p, < 2 p
+    return min(w, w - kP);
   }
   // floor(2^v y / p): with d0 = floor(2^v y / 2^29) and r its remainder
   // part, 2^v y - d0 p = r + 3 d0 < 2 p, so the digit is d0 or d0 + 1
