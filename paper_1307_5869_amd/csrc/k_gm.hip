@@ -20,6 +20,7 @@
 // kernel runs exact mod-g steps only until every element of the wavefront has
 // collapsed and then switches to the mod-p recurrence.
 #include "dev_gm.h"
+#include "dev_gmlane.h"
 
 namespace prand {
 namespace {
@@ -35,22 +36,26 @@ __global__ void __launch_bounds__(256) gm_gen32_kernel(const GmState* sin, GmSta
   gen32_wave<G, DT, false>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
 }
 
-template <int G, int DT>
-__global__ void __launch_bounds__(256) gm_gen8_kernel(const GmState* sin, GmState* sout, uint32_t count, uint64_t n,
-                                                      void* __restrict__ out) {
-  const uint64_t s = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-  const bool live = s < count;
+// GM55, GQ58.3, GQ58.4: lane gid owns section gid & (nsec - 1) of stream
+// gid >> nsec_log2; the sections of a stream cover [j seclen, min((j + 1)
+// seclen, n)) and sit in one wavefront (nsec <= 64), so the state read of
+// every section precedes the write-back of the last.
+template <int G, int DT, int CW>
+__global__ void __launch_bounds__(256) gm_lane_kernel(const GmState* sin, GmState* sout, uint32_t count, uint64_t n,
+                                                      int nsec_log2, uint64_t seclen, void* __restrict__ out,
+                                                      const uint64_t* __restrict__ ladder, int coalesce) {
+  __shared__ __align__(16) uint32_t stage[4][RegStage<CW>::kWaveWords];
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t nsec = 1ull << nsec_log2;
+  const uint64_t jlast = (n == 0) ? 0 : (n - 1) / seclen;
+  const uint64_t s = gid >> nsec_log2, j = gid & (nsec - 1);
+  const uint64_t start = j * seclen;
+  const bool live = s < count && j <= jlast;
+  const uint64_t len = live ? ((j == jlast) ? n - start : seclen) : 0;
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
-  gen8_wave<G, DT, false>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
-}
-
-template <int DT>
-__global__ void __launch_bounds__(256) gq58x3_gen_kernel(const GmState* sin, GmState* sout, uint32_t count,
-                                                         uint64_t n, void* __restrict__ out) {
-  const uint64_t s = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-  const bool live = s < count;
-  constexpr int es = (DT == PRAND_F64) ? 8 : 4;
-  gq3_wave<DT, false>(live, sin + (live ? s : 0), 0, n, (char*)out + s * n * es, sout + (live ? s : 0), nullptr);
+  void* o = (char*)out + (live ? (s * n + start) * es : 0);
+  gmlane_wave<G, DT, CW, true>(stage[threadIdx.x >> 6], live, sin + (live ? s : 0), start, len, o,
+                               (live && j == jlast) ? sout + s : nullptr, coalesce != 0, ladder);
 }
 
 // One lane per element slot (32 per stream): states[s] = base (or states[s])
@@ -91,27 +96,44 @@ __global__ void __launch_bounds__(256) gm_jump_kernel(GmState* __restrict__ stat
   if (e == 0) { dst->off = new_off; dst->pad = 0; }
 }
 
+constexpr int kLaneCW = 16;   // chunk words of the lane-per-section kernels
+
 template <int G, int DT>
-hipError_t launch_gen(const GmState* sin, GmState* sout, uint32_t count, uint64_t n, void* out, hipStream_t st) {
-  const int lps = (G == 3 || G == 7) ? 8 : (G == 6 ? 16 : 32);
-  const uint64_t lanes = (uint64_t)count * lps;
-  const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
-  if constexpr (G == 6)
-    hipLaunchKernelGGL(gq58x3_gen_kernel<DT>, dim3(blocks), dim3(256), 0, st, sin, sout, count, n, out);
-  else if constexpr (G == 3 || G == 7)
-    hipLaunchKernelGGL((gm_gen8_kernel<G, DT>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n, out);
-  else
+hipError_t launch_gen(const uint64_t* ladder, const GmState* sin, GmState* sout, uint32_t count, uint64_t n, void* out,
+                      hipStream_t st) {
+  if constexpr (G == 3 || G == 6 || G == 7) {
+    // enough lanes to fill the chip: up to 64 sections per stream, each at
+    // least 64 outputs long; section lengths are multiples of 4 (16-byte
+    // aligned starts) and, for GQ58.3, of 9 (every section starts at the
+    // same place in the 9-word block)
+    const uint64_t unit = (G == 6) ? 36 : 4;
+    int nsec_log2 = 0;
+    while (nsec_log2 < 6 && ((uint64_t)count << nsec_log2) < (1ull << 19) && (n >> (nsec_log2 + 1)) >= 64)
+      nsec_log2++;
+    uint64_t seclen = (n + (1ull << nsec_log2) - 1) >> nsec_log2;
+    seclen = (seclen + unit - 1) / unit * unit;
+    if (seclen == 0) seclen = unit;
+    const uint64_t es = DT == PRAND_F64 ? 8 : 4;
+    const int coalesce = ((uintptr_t)out % 16 == 0) && ((n * es) % 16 == 0) && ((seclen * es) % 16 == 0);
+    const uint64_t lanes = (uint64_t)count << nsec_log2;
+    const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
+    hipLaunchKernelGGL((gm_lane_kernel<G, DT, kLaneCW>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
+                       nsec_log2, seclen, out, ladder, coalesce);
+  } else {
+    const uint64_t lanes = (uint64_t)count * 32;
+    const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
     hipLaunchKernelGGL((gm_gen32_kernel<G, DT>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n, out);
+  }
   return hipGetLastError();
 }
 
 template <int G>
-hipError_t launch_gen_g(int dtype, const GmState* sin, GmState* sout, uint32_t count, uint64_t n, void* out,
-                        hipStream_t st) {
+hipError_t launch_gen_g(const uint64_t* ladder, int dtype, const GmState* sin, GmState* sout, uint32_t count,
+                        uint64_t n, void* out, hipStream_t st) {
   switch (dtype) {
-    case PRAND_U32: return launch_gen<G, PRAND_U32>(sin, sout, count, n, out, st);
-    case PRAND_F32: return launch_gen<G, PRAND_F32>(sin, sout, count, n, out, st);
-    default: return launch_gen<G, PRAND_F64>(sin, sout, count, n, out, st);
+    case PRAND_U32: return launch_gen<G, PRAND_U32>(ladder, sin, sout, count, n, out, st);
+    case PRAND_F32: return launch_gen<G, PRAND_F32>(ladder, sin, sout, count, n, out, st);
+    default: return launch_gen<G, PRAND_F64>(ladder, sin, sout, count, n, out, st);
   }
 }
 
@@ -129,16 +151,15 @@ hipError_t launch_jump_g(const DeviceTables& T, GmState* states, uint32_t count,
 
 hipError_t launch_gm_generate(const DeviceTables& T, int gen, const GmState* sin, GmState* sout, uint32_t count,
                               uint64_t n, int dtype, void* out, hipStream_t st) {
-  (void)T;
   switch (gen - PRAND_GM19) {
-    case 0: return launch_gen_g<0>(dtype, sin, sout, count, n, out, st);
-    case 1: return launch_gen_g<1>(dtype, sin, sout, count, n, out, st);
-    case 2: return launch_gen_g<2>(dtype, sin, sout, count, n, out, st);
-    case 3: return launch_gen_g<3>(dtype, sin, sout, count, n, out, st);
-    case 4: return launch_gen_g<4>(dtype, sin, sout, count, n, out, st);
-    case 5: return launch_gen_g<5>(dtype, sin, sout, count, n, out, st);
-    case 6: return launch_gen_g<6>(dtype, sin, sout, count, n, out, st);
-    default: return launch_gen_g<7>(dtype, sin, sout, count, n, out, st);
+    case 0: return launch_gen_g<0>(T.gm, dtype, sin, sout, count, n, out, st);
+    case 1: return launch_gen_g<1>(T.gm, dtype, sin, sout, count, n, out, st);
+    case 2: return launch_gen_g<2>(T.gm, dtype, sin, sout, count, n, out, st);
+    case 3: return launch_gen_g<3>(T.gm, dtype, sin, sout, count, n, out, st);
+    case 4: return launch_gen_g<4>(T.gm, dtype, sin, sout, count, n, out, st);
+    case 5: return launch_gen_g<5>(T.gm, dtype, sin, sout, count, n, out, st);
+    case 6: return launch_gen_g<6>(T.gm, dtype, sin, sout, count, n, out, st);
+    default: return launch_gen_g<7>(T.gm, dtype, sin, sout, count, n, out, st);
   }
 }
 
