@@ -40,11 +40,11 @@ __global__ void __launch_bounds__(256) gm_gen32_kernel(const GmState* sin, GmSta
 // gid >> nsec_log2; the sections of a stream cover [j seclen, min((j + 1)
 // seclen, n)) and sit in one wavefront (nsec <= 64), so the state read of
 // every section precedes the write-back of the last.
-template <int G, int DT, int CW>
+template <int G, int DT>
 __global__ void __launch_bounds__(256) gm_lane_kernel(const GmState* sin, GmState* sout, uint32_t count, uint64_t n,
                                                       int nsec_log2, uint64_t seclen, void* __restrict__ out,
-                                                      const uint64_t* __restrict__ ladder, int coalesce) {
-  __shared__ __align__(16) uint32_t stage[4][RegStage<CW>::kWaveWords];
+                                                      const uint64_t* __restrict__ ladder) {
+  __shared__ __align__(16) uint32_t stage[4][kLaneWaveWords];
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t nsec = 1ull << nsec_log2;
   const uint64_t jlast = (n == 0) ? 0 : (n - 1) / seclen;
@@ -54,8 +54,8 @@ __global__ void __launch_bounds__(256) gm_lane_kernel(const GmState* sin, GmStat
   const uint64_t len = live ? ((j == jlast) ? n - start : seclen) : 0;
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
   void* o = (char*)out + (live ? (s * n + start) * es : 0);
-  gmlane_wave<G, DT, CW, true>(stage[threadIdx.x >> 6], live, sin + (live ? s : 0), start, len, o,
-                               (live && j == jlast) ? sout + s : nullptr, coalesce != 0, ladder);
+  gmlane_wave<G, DT, true>(stage[threadIdx.x >> 6], live, sin + (live ? s : 0), start, len, o,
+                           (live && j == jlast) ? sout + s : nullptr, ladder);
 }
 
 // One lane per element slot (32 per stream): states[s] = base (or states[s])
@@ -96,8 +96,6 @@ __global__ void __launch_bounds__(256) gm_jump_kernel(GmState* __restrict__ stat
   if (e == 0) { dst->off = new_off; dst->pad = 0; }
 }
 
-constexpr int kLaneCW = 16;   // chunk words of the lane-per-section kernels
-
 template <int G, int DT>
 hipError_t launch_gen(const uint64_t* ladder, const GmState* sin, GmState* sout, uint32_t count, uint64_t n, void* out,
                       hipStream_t st) {
@@ -105,7 +103,7 @@ hipError_t launch_gen(const uint64_t* ladder, const GmState* sin, GmState* sout,
     // enough lanes to fill the chip: up to 64 sections per stream, each at
     // least 64 outputs long; section lengths are multiples of 4 (16-byte
     // aligned starts) and, for GQ58.3, of 9 (every section starts at the
-    // same place in the 9-word block)
+    // same place in the 9-word block as the stream)
     const uint64_t unit = (G == 6) ? 36 : 4;
     int nsec_log2 = 0;
     while (nsec_log2 < 6 && ((uint64_t)count << nsec_log2) < (1ull << 19) && (n >> (nsec_log2 + 1)) >= 64)
@@ -113,12 +111,10 @@ hipError_t launch_gen(const uint64_t* ladder, const GmState* sin, GmState* sout,
     uint64_t seclen = (n + (1ull << nsec_log2) - 1) >> nsec_log2;
     seclen = (seclen + unit - 1) / unit * unit;
     if (seclen == 0) seclen = unit;
-    const uint64_t es = DT == PRAND_F64 ? 8 : 4;
-    const int coalesce = ((uintptr_t)out % 16 == 0) && ((n * es) % 16 == 0) && ((seclen * es) % 16 == 0);
     const uint64_t lanes = (uint64_t)count << nsec_log2;
     const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
-    hipLaunchKernelGGL((gm_lane_kernel<G, DT, kLaneCW>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
-                       nsec_log2, seclen, out, ladder, coalesce);
+    hipLaunchKernelGGL((gm_lane_kernel<G, DT>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n, nsec_log2,
+                       seclen, out, ladder);
   } else {
     const uint64_t lanes = (uint64_t)count * 32;
     const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
