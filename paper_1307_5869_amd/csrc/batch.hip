@@ -129,10 +129,18 @@ int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_confi
     }
     const bool v1 = t.gen == PRAND_GM19 || t.gen == PRAND_GM29 || t.gen == PRAND_GM31 || t.gen == PRAND_GM61 ||
                     t.gen == PRAND_GQ58X1;
-    const uint64_t groups = v1 ? 2 : (t.gen == PRAND_GQ58X3 ? 4 : 8);
+    // v = 1: two 32-lane sections per tile; GM55, GQ58.3, GQ58.4: one lane
+    // per section, section lengths a multiple of 4 (16-byte aligned starts)
+    // and, for GQ58.3, of 9 (every section at the task's place in the
+    // 9-word block)
+    // (a lane then steps all 8 or 12 elements of its section: a lane's
+    // section is an eighth of gm_section, which keeps a tile's time near a
+    // v = 1 tile's)
+    const uint64_t groups = v1 ? 2 : 64;
+    const uint64_t unit = v1 ? 32 : (t.gen == PRAND_GQ58X3 ? 36 : 4);
     const int fam = v1 ? 1 : (t.gen == PRAND_GQ58X3 ? 3 : 2);
-    uint64_t sec = cfg.gm_section;
-    if (n < groups * sec) sec = std::max<uint64_t>(32, round_up((n + groups - 1) / groups, 32));
+    uint64_t sec = round_up(v1 ? cfg.gm_section : std::max<uint32_t>(cfg.gm_section / 8, 32), unit);
+    if (n < groups * sec) sec = std::max<uint64_t>(unit, round_up((n + groups - 1) / groups, unit));
     b.seclen = sec;
     if (v1) {
       // both halves of a wavefront run the same number of steps: pair the

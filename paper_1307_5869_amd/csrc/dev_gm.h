@@ -5,20 +5,18 @@
 // significant bit first, into 32-bit words (GQ58.3: 36 bits per step, 9 words
 // per 8 steps).
 //
-// One lane per element: v = 1 ensembles (s = 32) take half a wavefront per
-// stream and pack a word with one ballot; v = 4 ensembles (s = 8) take 8
-// lanes and OR their nibbles with three xor-shuffles; GQ58.3 (s = 12) takes 16
-// lanes (the OR-reductions use DPP row permutes).  Each lane keeps the word
-// of one step of every 32 (8), so a flush writes consecutive words from
-// consecutive lanes.
+// This header holds the per-generator arithmetic, the jumps, and the v = 1
+// ensembles' (s = 32) wavefront routine: one lane per element, half a
+// wavefront per stream, one ballot per step packs a word.  The v >= 3
+// ensembles (GM55, GQ58.3, GQ58.4) run one lane per section (dev_gmlane.h).
 //
 // Arithmetic is exact: special-form reductions (2^19-1, 2^29-3, 2^61-1,
-// 2^51-129) in integers, or FP64 where all values stay below 2^53 (GM31,
-// GQ58).  For g = p 2^t (GM55: t = 4, GQ58: t = 29) the even k and q kill the
-// 2-adic part within n0 steps; from then on x = 2^t y with y following the
-// same recurrence mod p and the digit equal to floor(2^v y / p), so the
-// kernel runs exact mod-g steps only until every element of the wavefront has
-// collapsed and then switches to the mod-p recurrence.
+// 2^51-129) in integers.  For g = p 2^t (GM55: t = 4, GQ58: t = 29) the even
+// k and q kill the 2-adic part within n0 steps; from then on x = 2^t y with y
+// following the same recurrence mod p and the digit equal to
+// floor(2^v y / p), so the kernels run exact mod-g steps only until every
+// element of the wavefront has collapsed and then switch to the mod-p
+// recurrence.
 // GM/GQ device code shared by the GM/GQ kernels and the batched kernel.
 #pragma once
 
@@ -277,20 +275,6 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-// OR over aligned groups of 8 / 16 lanes with DPP row permutes (no LDS):
-// quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror (lane i of
-// an 8-lane half reads lane 7-i) and row_mirror (lane i of a row reads 15-i)
-__device__ __forceinline__ uint32_t dpp_or8(uint32_t w) {
-  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0xB1, 0xF, 0xF, false);
-  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x4E, 0xF, 0xF, false);
-  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x141, 0xF, 0xF, false);
-  return w;
-}
-__device__ __forceinline__ uint32_t dpp_or16(uint32_t w) {
-  w = dpp_or8(w);
-  return w | (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x140, 0xF, 0xF, false);
-}
-
 // -------------------------------------------------------------- jumping
 template <int G>
 __device__ __forceinline__ uint64_t fold_special(u128 x, int e, uint64_t c, uint64_t p) {
@@ -466,121 +450,6 @@ __device__ __forceinline__ void gen32_wave(bool live, const GmState* in, uint64_
     sout->xp[e] = xp;
     if (li == 0) { sout->off = 0; sout->pad = 0; }
   }
-}
-
-// ---------------------------------------------- v = 4, s = 8: nibbles
-// Each aligned group of 8 lanes is one section (element e = lane & 7).
-template <int G, int DT, bool kJump = true>
-__device__ __forceinline__ void gen8_wave(bool live, const GmState* in, uint64_t start, uint64_t n, void* out,
-                                          GmState* sout, const uint64_t* __restrict__ ladder) {
-  const int e = threadIdx.x & 7;
-  uint64_t xc = 0, xp = 0;
-  if (live) load_at<G, kJump>(in, e, start, xc, xp, ladder);
-  Elem<G> el;
-  el.load(xc, xp);
-  const int shift = 28 - 4 * e;
-  uint32_t keep = 0;
-  for (uint64_t t0 = 0; t0 < n; t0 += 8) {
-    const int m = (n - t0) < 8 ? (int)(n - t0) : 8;
-    if (m == 8) {
-      el.block([&](auto stepf) {
-        static_for<0, 8>([&](auto uc) {
-          constexpr int u = decltype(uc)::value;
-          const uint32_t w = dpp_or8(stepf() << shift);
-          keep = (u == e) ? w : keep;
-        });
-      });
-    } else {
-      for (int u = 0; u < m; u++) {
-        el.maybe_switch();
-        const uint32_t w = dpp_or8(el.step() << shift);
-        keep = (u == e) ? w : keep;
-      }
-    }
-    if (live && e < m) put<DT>(out, t0 + e, keep);
-  }
-  if (live && sout) {
-    el.get(xc, xp);
-    sout->xc[e] = xc;
-    sout->xp[e] = xp;
-    // the blob's unused element slots (8 .. 31) are zero
-#pragma unroll
-    for (int z = e + 8; z < 32; z += 8) {
-      sout->xc[z] = 0;
-      sout->xp[z] = 0;
-    }
-    if (e == 0) { sout->off = 0; sout->pad = 0; }
-  }
-}
-
-// ---------------------------- GQ58.3: v = 3, s = 12, 16 lanes per section
-// 8 steps of 36 bits = 9 words.  The state sits at a block boundary with
-// `off` words of the block consumed; a section emits block words from off on
-// and keeps the state at the start of the last, partially used block.
-// Groups of one wavefront may run different numbers of blocks.
-template <int DT, bool kJump = true>
-__device__ __forceinline__ void gq3_wave(bool live, const GmState* in, uint64_t start, uint64_t n, void* out,
-                                         GmState* sout, const uint64_t* __restrict__ ladder) {
-  constexpr int G = 6;
-  const int e = threadIdx.x & 15;
-  const int gbase = threadIdx.x & 48;     // first lane of this group within the wavefront
-  const bool elem = e < 12;
-  uint64_t xc = 0, xp = 0;
-  uint32_t off0 = 0;
-  if (live) off0 = load_at<G, kJump>(in, elem ? e : 0, start, xc, xp, ladder);
-  if (!elem) xc = xp = 0;
-  Elem<G> el;
-  el.load(xc, xp);
-  const uint64_t total = live ? off0 + n : 0;
-  const uint64_t full = total / 9;
-  const uint32_t rem = (uint32_t)(total % 9);
-  const uint64_t nb = full + (rem ? 1 : 0);
-  Elem<G> saved = el;
-  const int shift = elem ? 33 - 3 * e : 0;
-  for (uint64_t b = 0; b < nb; b++) {
-    uint64_t keep = 0;
-    el.block([&](auto stepf) {
-      saved = el;
-      static_for<0, 8>([&](auto uc) {
-        constexpr int u = decltype(uc)::value;
-        const uint32_t d = stepf();
-        uint64_t c = elem ? ((uint64_t)d << shift) : 0;
-        const uint32_t lo = dpp_or16((uint32_t)c), hi = dpp_or16((uint32_t)(c >> 32));
-        c = ((uint64_t)hi << 32) | lo;
-        keep = (u == e) ? c : keep;
-      });
-    });
-    // word w (lane w < 9): bits [32w, 32w+32) of the 288-bit block
-    const int w = e < 9 ? e : 8;
-    const int ci = (32 * w) / 36, o = 32 * w - 36 * ci;
-    const uint32_t alo = __shfl((uint32_t)keep, gbase + ci);
-    const uint32_t ahi = __shfl((uint32_t)(keep >> 32), gbase + ci);
-    const int cj = ci + 1 < 8 ? ci + 1 : 7;
-    const uint32_t blo = __shfl((uint32_t)keep, gbase + cj);
-    const uint32_t bhi = __shfl((uint32_t)(keep >> 32), gbase + cj);
-    const uint64_t A = ((uint64_t)ahi << 32) | alo;
-    const uint64_t B = (ci + 1 < 8) ? (((uint64_t)bhi << 32) | blo) : 0;
-    const int k = 40 - o;   // the word is (A:B >> k) & (2^32 - 1) of the 72-bit A:B
-    const uint32_t word = (k > 36) ? (uint32_t)(A >> (k - 36)) : (uint32_t)((A << (36 - k)) | (B >> k));
-    const int64_t q = (int64_t)(b * 9 + w) - (int64_t)off0;
-    if (live && e < 9 && q >= 0 && (uint64_t)q < n) put<DT>(out, (uint64_t)q, word);
-  }
-  if (live && sout && elem) {
-    if (rem && nb > 0) saved.get(xc, xp); else el.get(xc, xp);
-    sout->xc[e] = xc;
-    sout->xp[e] = xp;
-  }
-  if (live && sout) {
-    // the blob's unused element slots (12 .. 31) are zero: lanes 12 .. 15
-    // clear their own slot, every lane the slot 16 + e
-    if (!elem) {
-      sout->xc[e] = 0;
-      sout->xp[e] = 0;
-    }
-    sout->xc[16 + e] = 0;
-    sout->xp[16 + e] = 0;
-  }
-  if (live && sout && e == 0) { sout->off = rem; sout->pad = 0; }
 }
 
 }  // namespace gm

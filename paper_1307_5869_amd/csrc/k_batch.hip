@@ -2,9 +2,9 @@
 // uneven sizes in one launch.
 //
 // The host cuts every task into tiles, one tile being the work of one
-// wavefront: 64 lane-sections of a MRG32K3A / LFSR113 task, 2 / 8 / 4
-// element-group sections of a GM/GQ task (32, 8 or 16 lanes per section), or
-// a whole MT19937 task (one wavefront per stream).  Sections are independent:
+// wavefront: 64 lane-sections of a MRG32K3A / LFSR113 / GM55 / GQ58.3 /
+// GQ58.4 task, 2 element-group sections of a v = 1 GM/GQ task (32 lanes per
+// section), or a whole MT19937 task (one wavefront per stream).  Sections are independent:
 // each starts from the task's state jumped to its first output.
 //
 // The launch is a small graph of kernels:
@@ -12,13 +12,14 @@
 //    start and writes the state to the batch's scratch area (the jump code
 //    needs many registers, so it runs apart from the generation loops);
 //  - batch_reg_kernel, batch_gm_kernel<shape> (32-lane v = 1 ensembles,
-//    8-lane v = 4 ensembles, GQ58.3) and batch_mt_kernel generate, one
+//    lane-per-section v = 4 ensembles, GQ58.3) and batch_mt_kernel generate, one
 //    wavefront per tile, from those states (or, for MT19937, from the task
 //    state) with the same wavefront routines as the one-generator kernels,
 //    and at their register counts.
 // The generation kernels are independent of each other; tiles within each
 // are ordered longest first, so the dispatcher starts the long ones early.
 #include "dev_gm.h"
+#include "dev_gmlane.h"
 #include "dev_lfsr.h"
 #include "dev_mrg.h"
 #include "dev_mt.h"
@@ -46,7 +47,7 @@ __device__ __forceinline__ Sect section_of(const BatchTile& tl, const BatchTask&
   return s;
 }
 
-constexpr int gm_groups(int G) { return (G == 3 || G == 7) ? 8 : (G == 6 ? 4 : 2); }
+constexpr int gm_groups(int G) { return (G == 3 || G == 6 || G == 7) ? 64 : 2; }
 
 __device__ __forceinline__ uint32_t wave_index() { return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); }
 
@@ -68,20 +69,50 @@ __device__ __noinline__ void start_gm(const BatchTile& tl, const BatchTask& tk, 
   const Sect s = section_of(tl, tk, groups);
   if (!s.live) return;
   const int lane = threadIdx.x & 63;
-  const int gi = lane / (64 / groups);
-  int e;
-  if constexpr (groups == 2) e = 31 - (lane & 31);
-  else if constexpr (groups == 8) e = lane & 7;
-  else e = lane & 15;
-  if (G == 6 && e >= 12) return;   // GQ58.3: 12 elements in 16 lanes
-  uint64_t xc, xp;
-  const uint32_t off = gm::load_at<G>((const GmState*)tk.state_in, e, s.start, xc, xp, ladder);
-  GmState* dst = (GmState*)(scratch + tl.starts) + gi;
-  dst->xc[e] = xc;
-  dst->xp[e] = xp;
-  if (e == 0) {
+  if constexpr (groups == 64) {
+    // one lane per section: every element of the section's start state; a
+    // jump past n0 steps runs in the fast (mod p) representation
+    using E = gm::Eng<G>;
+    const GmState* in = (const GmState*)tk.state_in;
+    GmState* dst = (GmState*)(scratch + tl.starts) + lane;
+    constexpr int S = (G == 6) ? 12 : 8;
+    uint64_t nsteps = s.start;
+    uint32_t off = (G == 6) ? in->off : 0;
+    if (G == 6 && s.start) {   // words from the block start -> whole blocks of 8 steps
+      const uint64_t w = (uint64_t)off + s.start;
+      nsteps = 8 * (w / 9);
+      off = (uint32_t)(w % 9);
+    }
+    for (int e = 0; e < S; e++) {
+      uint64_t xc = in->xc[e], xp = in->xp[e];
+      if (nsteps >= (uint64_t)kGmParams[G].n0 || (nsteps && E::collapsed(xc) && E::collapsed(xp))) {
+        const gm::FastPair<G> j = gm::lane_jump_fast<G>(in, e, nsteps, ladder);
+        xc = E::from_fast(j.yc);
+        xp = E::from_fast(j.yp);
+      } else if (nsteps) {
+        for (uint64_t i = 0; i < nsteps; i++) {
+          const uint64_t nx = E::slow_step(xc, xp);
+          xp = xc;
+          xc = nx;
+        }
+      }
+      dst->xc[e] = xc;
+      dst->xp[e] = xp;
+    }
     dst->off = off;
     dst->pad = 0;
+  } else {
+    const int gi = lane / (64 / groups);
+    const int e = 31 - (lane & 31);
+    uint64_t xc, xp;
+    const uint32_t off = gm::load_at<G>((const GmState*)tk.state_in, e, s.start, xc, xp, ladder);
+    GmState* dst = (GmState*)(scratch + tl.starts) + gi;
+    dst->xc[e] = xc;
+    dst->xp[e] = xp;
+    if (e == 0) {
+      dst->off = off;
+      dst->pad = 0;
+    }
   }
 }
 
@@ -149,7 +180,8 @@ __global__ void __launch_bounds__(256) batch_reg_kernel(const BatchTile* __restr
 // A dead group follows along without loads or stores; the planner gives both
 // halves of a v = 1 tile the same length (tl.len32).
 template <int G, int DT>
-__device__ __forceinline__ void gen_gm(const BatchTile& tl, const BatchTask& tk, const char* scratch) {
+__device__ __forceinline__ void gen_gm(const BatchTile& tl, const BatchTask& tk, const char* scratch,
+                                       uint32_t* rows) {
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
   constexpr int groups = gm_groups(G);
   const Sect s = section_of(tl, tk, groups);
@@ -157,42 +189,51 @@ __device__ __forceinline__ void gen_gm(const BatchTile& tl, const BatchTask& tk,
   const int gi = (threadIdx.x & 63) / (64 / groups);
   const GmState* in = (const GmState*)(scratch + tl.starts) + (s.live ? gi : 0);
   GmState* sout = s.last ? (GmState*)tk.state_out : nullptr;
-  if constexpr (G == 6) gm::gq3_wave<DT, false>(s.live, in, 0, s.len, o, sout, nullptr);
-  else if constexpr (groups == 8) gm::gen8_wave<G, DT, false>(s.live, in, 0, s.len, o, sout, nullptr);
+  if constexpr (groups == 64) gm::gmlane_wave<G, DT, false>(rows, s.live, in, 0, s.len, o, sout, nullptr);
   else gm::gen32_wave<G, DT, false>(s.live, in, 0, tl.len32, o, sout, nullptr);
 }
 
 // one kernel per ensemble shape, so each runs at its own register count:
-// S = 0: v = 1 (32 lanes per section), 1: v = 4 (8 lanes), 2: GQ58.3
+// S = 0: v = 1 (32 lanes per section), 1: v = 4 (a lane per section), 2:
+// GQ58.3 (a lane per section)
 template <int S, int DT>
-__device__ __forceinline__ void gen_gm_dt(const BatchTile& tl, const BatchTask& tk, const char* scratch) {
+__device__ __forceinline__ void gen_gm_dt(const BatchTile& tl, const BatchTask& tk, const char* scratch,
+                                          uint32_t* rows) {
   if constexpr (S == 0) {
     switch (tk.gen) {
-      case PRAND_GM19: gen_gm<0, DT>(tl, tk, scratch); break;
-      case PRAND_GM29: gen_gm<1, DT>(tl, tk, scratch); break;
-      case PRAND_GM31: gen_gm<2, DT>(tl, tk, scratch); break;
-      case PRAND_GM61: gen_gm<4, DT>(tl, tk, scratch); break;
-      default: gen_gm<5, DT>(tl, tk, scratch); break;
+      case PRAND_GM19: gen_gm<0, DT>(tl, tk, scratch, rows); break;
+      case PRAND_GM29: gen_gm<1, DT>(tl, tk, scratch, rows); break;
+      case PRAND_GM31: gen_gm<2, DT>(tl, tk, scratch, rows); break;
+      case PRAND_GM61: gen_gm<4, DT>(tl, tk, scratch, rows); break;
+      default: gen_gm<5, DT>(tl, tk, scratch, rows); break;
     }
   } else if constexpr (S == 1) {
-    if (tk.gen == PRAND_GM55) gen_gm<3, DT>(tl, tk, scratch);
-    else gen_gm<7, DT>(tl, tk, scratch);
+    if (tk.gen == PRAND_GM55) gen_gm<3, DT>(tl, tk, scratch, rows);
+    else gen_gm<7, DT>(tl, tk, scratch, rows);
   } else {
-    gen_gm<6, DT>(tl, tk, scratch);
+    gen_gm<6, DT>(tl, tk, scratch, rows);
   }
 }
+
+// LDS only for the lane-per-section shapes
+template <int S>
+struct GmRows {
+  static constexpr int kWords = (S == 0) ? 1 : gm::kLaneWaveWords;
+};
 
 template <int S>
 __global__ void __launch_bounds__(256) batch_gm_kernel(const BatchTile* __restrict__ tiles, uint32_t ntiles,
                                                        const BatchTask* __restrict__ tasks, const char* scratch) {
+  __shared__ __align__(16) uint32_t lds[4][GmRows<S>::kWords];
   const uint32_t t = wave_index();
   if (t >= ntiles) return;
+  uint32_t* rows = lds[(threadIdx.x >> 6) & 3];
   const BatchTile tl = tiles[t];
   const BatchTask tk = tasks[tl.task];
   switch (tk.dtype) {
-    case PRAND_U32: gen_gm_dt<S, PRAND_U32>(tl, tk, scratch); break;
-    case PRAND_F32: gen_gm_dt<S, PRAND_F32>(tl, tk, scratch); break;
-    default: gen_gm_dt<S, PRAND_F64>(tl, tk, scratch); break;
+    case PRAND_U32: gen_gm_dt<S, PRAND_U32>(tl, tk, scratch, rows); break;
+    case PRAND_F32: gen_gm_dt<S, PRAND_F32>(tl, tk, scratch, rows); break;
+    default: gen_gm_dt<S, PRAND_F64>(tl, tk, scratch, rows); break;
   }
 }
 

@@ -5,20 +5,20 @@
 // significant bit first, into 32-bit words (GQ58.3: 36 bits per step, 9 words
 // per 8 steps).
 //
-// One lane per element: v = 1 ensembles (s = 32) take half a wavefront per
-// stream and pack a word with one ballot; v = 4 ensembles (s = 8) take 8
-// lanes and OR their nibbles with three xor-shuffles; GQ58.3 (s = 12) takes 16
-// lanes (the OR-reductions use DPP row permutes).  Each lane keeps the word
-// of one step of every 32 (8), so a flush writes consecutive words from
-// consecutive lanes.
+// v = 1 ensembles (s = 32): one lane per element, half a wavefront per
+// stream, one ballot per step packs a word; each lane keeps the word of one
+// step of every 32, so a flush writes consecutive words from consecutive
+// lanes.  GM55, GQ58.3, GQ58.4: one lane per section, every element stepped
+// in that lane (dev_gmlane.h); a stream is cut into up to 64 sections that
+// start by jumps.
 //
 // Arithmetic is exact: special-form reductions (2^19-1, 2^29-3, 2^61-1,
-// 2^51-129) in integers, or FP64 where all values stay below 2^53 (GM31,
-// GQ58).  For g = p 2^t (GM55: t = 4, GQ58: t = 29) the even k and q kill the
-// 2-adic part within n0 steps; from then on x = 2^t y with y following the
-// same recurrence mod p and the digit equal to floor(2^v y / p), so the
-// kernel runs exact mod-g steps only until every element of the wavefront has
-// collapsed and then switches to the mod-p recurrence.
+// 2^51-129) in integers.  For g = p 2^t (GM55: t = 4, GQ58: t = 29) the even
+// k and q kill the 2-adic part within n0 steps; from then on x = 2^t y with y
+// following the same recurrence mod p and the digit equal to
+// floor(2^v y / p), so the kernels run exact mod-g steps only until every
+// element of the wavefront has collapsed and then switch to the mod-p
+// recurrence.
 #include "dev_gm.h"
 #include "dev_gmlane.h"
 
