@@ -285,6 +285,22 @@ __device__ __forceinline__ uint64_t fold_special(u128 x, int e, uint64_t c, uint
   r = r >= p ? r - p : r;
   return r;
 }
+// m0 a + m1 b mod p = 2^e - c with every operand below p: below 2^32
+// (GM19, GM29, GM31, GQ58) the products and their sum fit 64 bits, so the
+// folds run in 64-bit arithmetic; GM55 and GM61 need 128 bits
+template <int G>
+__device__ __forceinline__ uint64_t mulsum_mod(uint64_t m0, uint64_t a, uint64_t m1, uint64_t b, int e,
+                                               uint64_t c, uint64_t p) {
+  if constexpr (G == 3 || G == 4) {
+    return fold_special<G>((u128)m0 * a + (u128)m1 * b, e, c, p);
+  } else {
+    const uint64_t mask = (1ull << e) - 1;
+    uint64_t x = m0 * a + m1 * b;   // < 2^63
+    for (int i = 0; i < 3; i++) x = (x & mask) + c * (x >> e);
+    x = x >= p ? x - p : x;
+    return x >= p ? x - p : x;
+  }
+}
 // prime part p = 2^e - c of each generator's modulus
 __device__ __forceinline__ void prime_form(int G, int& e, uint64_t& c) {
   switch (G) {
@@ -335,8 +351,8 @@ __device__ __forceinline__ void jump_steps_elem(uint64_t& xc, uint64_t& xp, uint
         const int b = __builtin_ctzll(wd) + 64 * l;
         wd &= wd - 1;
         const uint64_t* M = L + (size_t)b * 4;
-        const uint64_t nc = fold_special<G>((u128)M[0] * yc + (u128)M[1] * yp, pe, pc, p);
-        const uint64_t np = fold_special<G>((u128)M[2] * yc + (u128)M[3] * yp, pe, pc, p);
+        const uint64_t nc = mulsum_mod<G>(M[0], yc, M[1], yp, pe, pc, p);
+        const uint64_t np = mulsum_mod<G>(M[2], yc, M[3], yp, pe, pc, p);
         yc = nc; yp = np;
       }
     }
@@ -349,8 +365,8 @@ __device__ __forceinline__ void jump_steps_elem(uint64_t& xc, uint64_t& xp, uint
         const int b = __builtin_ctzll(wd) + 64 * l;
         wd &= wd - 1;
         const uint64_t* M = L + (size_t)b * 4;
-        const uint64_t nc = fold_special<G>((u128)M[0] * xc + (u128)M[1] * xp, pe, pc, p);
-        const uint64_t np = fold_special<G>((u128)M[2] * xc + (u128)M[3] * xp, pe, pc, p);
+        const uint64_t nc = mulsum_mod<G>(M[0], xc, M[1], xp, pe, pc, p);
+        const uint64_t np = mulsum_mod<G>(M[2], xc, M[3], xp, pe, pc, p);
         xc = nc; xp = np;
       }
     }
