@@ -29,81 +29,98 @@ namespace gm {
 
 typedef unsigned __int128 u128;
 
+// An empty asm that the optimiser cannot see through: the value is taken as
+// computed, so a constant folded into it is not re-associated into a later
+// sum (which would cost an extra add instead of a multiply-add's addend).
+template <class T>
+__device__ __forceinline__ T pin(T v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
 // ------------------------------------------------------------ per generator
 template <int G>
 struct Eng;
 
-// GM19: g = 2^19 - 1, k = 15, q = 28
+// The v = 1 ensembles keep each element in a redundant range [0, g + d)
+// (GM29 and GQ58.1: shifted by a constant c, the stored value congruent to
+// x + c), so no step pays for a final conditional subtraction; the digit is
+// read off the redundant value with two compares, and from_fast returns the
+// exact value.  The bounds below hold for every input in the range.
+
+// GM19: g = 2^19 - 1, k = 15, q = 28; z in [0, g + 71].
+// t = 15 zc + 56 g - 28 zp < 71 g + 1066 < 2^26, and t - floor(t / 2^19) g =
+// (t mod 2^19) + floor(t / 2^19) <= g + 70; all multiplies 24-bit
 template <>
 struct Eng<0> {
   static constexpr bool kComposite = false;
   using F = uint32_t;
   static constexpr uint32_t g = 524287u;
   __device__ static F to_fast(uint64_t x) { return (F)x; }
-  __device__ static uint64_t from_fast(F y) { return y; }
-  __device__ static F step(F xc, F xp) {
-    // operands < 2^19: 24-bit multiplies (full rate)
-    uint32_t t = __umul24(15u, xc) + __umul24(28u, g - xp);   // < 43 * 2^19
-    t = (t & g) + (t >> 19);
-    return min(t, t - g);
+  __device__ static uint64_t from_fast(F z) { return z >= g ? z - g : z; }
+  __device__ static F step(F zc, F zp) {
+    const uint32_t t = __umul24(15u, zc) + (uint32_t)pin(__mul24((int)zp, -28) + (int)(56u * g));
+    return t + (uint32_t)__mul24((int)(t >> 19), -(int)g);
   }
-  __device__ static uint32_t digit(F x) { return x >= (g + 1) / 2; }
+  __device__ static bool digit(F z) { return (z >= (1u << 18)) & (z < g); }
 };
 
-// GM29: g = 2^29 - 3, k = 4, q = 2
+// GM29: g = 2^29 - 3, k = 4, q = 2; z in [0, g + 19], z = x - 38 (mod g).
+// a = 2 zc + (g + 19) - zp < 3 g + 58 < 2^31 and 2 a = 3 floor(a / 2^28) +
+// 2 (a mod 2^28) (mod g) <= g + 16; the constant g + 19 adds 38 = -2 c
 template <>
 struct Eng<1> {
   static constexpr bool kComposite = false;
   using F = uint32_t;
   static constexpr uint32_t g = 536870909u;
-  __device__ static F to_fast(uint64_t x) { return (F)x; }
-  __device__ static uint64_t from_fast(F y) { return y; }
-  __device__ static F step(F xc, F xp) {
-    uint32_t t = (xc << 2) + ((g - xp) << 1);   // < 6 * 2^29
-    t = (t & 0x1FFFFFFFu) + 3u * (t >> 29);
-    return min(t, t - g);
+  __device__ static F to_fast(uint64_t x) { return x >= 38u ? (F)x - 38u : (F)x + (g - 38u); }
+  __device__ static uint64_t from_fast(F z) { return z + 38u < g ? z + 38u : z + 38u - g; }
+  __device__ static F step(F zc, F zp) {
+    const uint32_t a = 2u * zc + pin((g + 19u) - zp);
+    return ((a & 0x0FFFFFFFu) << 1) + __umul24(3u, a >> 28);
   }
-  __device__ static uint32_t digit(F x) { return x >= (g + 1) / 2; }
+  // x >= (g + 1) / 2 with x = z + 38 (mod g)
+  __device__ static bool digit(F z) { return (z >= (g + 1) / 2 - 38u) & (z < g - 38u); }
 };
 
-// GM31: g = 2^31 - 1, k = 11, q = 14: one 64-bit product sum (< 25 * 2^31)
-// folded with 2^31 = 1 (mod g)
+// GM31: g = 2^31 - 1, k = 11, q = 14; z in [0, g + 39].
+// t = 11 zc + 14 (2 g - zp) < 39 g + 430, folded with 2^31 = 1 (mod g) to at
+// most g + 38
 template <>
 struct Eng<2> {
   static constexpr bool kComposite = false;
   using F = uint32_t;
   static constexpr uint32_t g = 2147483647u;
   __device__ static F to_fast(uint64_t x) { return (F)x; }
-  __device__ static uint64_t from_fast(F y) { return y; }
-  __device__ static F step(F xc, F xp) {
-    const uint64_t t = (uint64_t)11u * xc + (uint64_t)14u * (g - xp);
-    const uint32_t r = ((uint32_t)t & g) + (uint32_t)(t >> 31);   // < 2^31 + 25
-    return min(r, r - g);
+  __device__ static uint64_t from_fast(F z) { return z >= g ? z - g : z; }
+  __device__ static F step(F zc, F zp) {
+    const uint64_t t = (uint64_t)11u * zc + (uint64_t)14u * (2u * g - zp);
+    return ((uint32_t)t & g) + (uint32_t)(t >> 31);
   }
-  __device__ static uint32_t digit(F x) { return x >= (1u << 30); }
+  __device__ static bool digit(F z) { return (z >= (1u << 30)) & (z < g); }
 };
 
-// GM61: g = 2^61 - 1, k = 24, q = 74
+// GM61: g = 2^61 - 1, k = 24, q = 74; z in [0, 2^61 + 98 2^32).
+// 24 zc + 74 s with s = 2 g - zp < 2^62, in 32-bit halves: B = 24 zc_hi +
+// 74 s_hi < 2^37 and B 2^32 = floor(B / 2^29) + (B mod 2^29) 2^32 (mod g);
+// A = 24 zc_lo + 74 s_lo + floor(B / 2^29) < 98 2^32 + 196, and the result
+// A + (B mod 2^29) 2^32 only adds to the high word
 template <>
 struct Eng<4> {
   static constexpr bool kComposite = false;
   using F = uint64_t;
   static constexpr uint64_t g = 2305843009213693951ull;
   __device__ static F to_fast(uint64_t x) { return x; }
-  __device__ static uint64_t from_fast(F y) { return y; }
-  // 24 xc + 74 s with s = g - xp (g is 61 one bits: a complement), in
-  // 32-bit halves: A = 24 xc_lo + 74 s_lo < 2^39 and B = 24 xc_hi + 74 s_hi
-  // < 2^36 give B 2^32 + A = (B mod 2^29) 2^32 + (B >> 29) + A (mod g), a
-  // sum below 2^61 + 2^40 < 2 g: one conditional subtraction
-  __device__ static F step(F xc, F xp) {
-    const uint64_t s = xp ^ g;
-    const uint64_t A = (uint64_t)(uint32_t)xc * 24u + (uint64_t)(uint32_t)s * 74u;
-    const uint64_t B = (uint64_t)(uint32_t)(xc >> 32) * 24u + (uint64_t)(uint32_t)(s >> 32) * 74u;
-    const uint32_t bhi = __builtin_amdgcn_alignbit((uint32_t)(B >> 32), (uint32_t)B, 29);   // B >> 29 < 2^7
-    const uint64_t r = A + bhi + ((B & 0x1FFFFFFFull) << 32);
-    return r >= g ? r - g : r;
+  __device__ static uint64_t from_fast(F z) { return z >= g ? z - g : z; }
+  __device__ static F step(F zc, F zp) {
+    const uint64_t s = 2 * g - zp;
+    const uint64_t B = (uint64_t)(uint32_t)(zc >> 32) * 24u + (uint64_t)(uint32_t)(s >> 32) * 74u;
+    const uint32_t bhi = __builtin_amdgcn_alignbit((uint32_t)(B >> 32), (uint32_t)B, 29);
+    const uint64_t A = (uint64_t)(uint32_t)zc * 24u + pin((uint64_t)(uint32_t)s * 74u + bhi);
+    const uint32_t hi = pin((uint32_t)(A >> 32)) + ((uint32_t)B & 0x1FFFFFFFu);
+    return ((uint64_t)hi << 32) | (uint32_t)A;
   }
-  __device__ static uint32_t digit(F x) { return x >= (1ull << 60); }
+  __device__ static bool digit(F z) { return ((uint32_t)(z >> 32) >= (1u << 28)) & (z < g); }
 };
 
 // GM55: g = 2^4 p, p = 2^51 - 129, k = 256, q = 176, v = 4
@@ -180,7 +197,26 @@ struct EngGQ {
     return d0 + ((r + __umul24(3u, d0)) >= kP ? 1u : 0u);
   }
 };
-template <> struct Eng<5> : EngGQ<1> {};
+// GQ58.1 after the collapse: z in [0, p + 184], z = y + 240 (mod p).
+// u = zc + 6 ((p + 205) - zp) < 7 p + 1415 < 2^32 and 8 u = 3 floor(u / 2^26)
+// + 8 (u mod 2^26) (mod p) <= p + 160; the constant p + 205 = p + 41 * 5
+// adds 48 * 205 = 41 * 240 = 41 c
+template <>
+struct Eng<5> : EngGQ<1> {
+  static constexpr uint32_t kC = 240u;
+  __device__ static F to_fast(uint64_t x) {
+    const uint32_t z = (uint32_t)(x >> 29) + kC;
+    return z >= kP ? z - kP : z;
+  }
+  __device__ static uint64_t from_fast(F z) { return ((uint64_t)(z >= kC ? z - kC : z + (kP - kC))) << 29; }
+  __device__ static F step(F zc, F zp) {
+    const uint32_t u = zc + 6u * pin((kP + 205u) - zp);
+    return ((u << 3) & kM) + __umul24(3u, u >> 26);
+  }
+  // y >= (p + 1) / 2 with y = z - 240: z < 240 wraps to a large value and
+  // stands for y = z - 240 + p >= (p + 1) / 2
+  __device__ static bool digit(F z) { return z - kC >= 268435455u; }
+};
 template <> struct Eng<6> : EngGQ<3> {};
 template <> struct Eng<7> : EngGQ<4> {};
 
