@@ -123,7 +123,10 @@ struct Eng<4> {
   __device__ static bool digit(F z) { return ((uint32_t)(z >> 32) >= (1u << 28)) & (z < g); }
 };
 
-// GM55: g = 2^4 p, p = 2^51 - 129, k = 256, q = 176, v = 4
+// GM55: g = 2^4 p, p = 2^51 - 129, k = 256, q = 176, v = 4.  After the
+// collapse the kernels keep y = x / 16 (mod p) in [0, p + 78560]:
+// s = (zc << 8) + 176 (2p - zp) < 609 p < 2^61 folded once with 2^51 = 129
+// (mod p) is at most p + 78431
 template <>
 struct Eng<3> {
   static constexpr bool kComposite = true;
@@ -145,14 +148,16 @@ struct Eng<3> {
     return (uint32_t)(d0 + ((d0 + 1) * p <= x));
   }
   __device__ static F to_fast(uint64_t x) { return x >> 4; }
-  __device__ static uint64_t from_fast(F y) { return y << 4; }
-  __device__ static F step(F yc, F yp) {
-    const uint64_t s = (yc << 8) + 176ull * (p - yp);   // < 2^60
-    return modp_fold(s);
+  __device__ static uint64_t from_fast(F z) { return (z >= p ? z - p : z) << 4; }
+  __device__ static F step(F zc, F zp) {
+    const uint64_t s = (zc << 8) + 176ull * (2 * p - zp);
+    return (s & ((1ull << 51) - 1)) + 129ull * (s >> 51);
   }
-  __device__ static uint32_t digit(F y) {
-    const uint64_t num = y << 4, d0 = num >> 51;
-    return (uint32_t)(d0 + ((d0 + 1) * p <= num));
+  // floor(16 y / p); a value z in [p, p + 78560] stands for z - p < p / 16
+  // (digit 0) and gives 16 here, which the 4-bit mask drops
+  __device__ static uint32_t digit(F z) {
+    const uint64_t num = z << 4, d0 = num >> 51;
+    return (uint32_t)(d0 + ((d0 + 1) * p <= num)) & 15u;
   }
 };
 
@@ -175,28 +180,34 @@ struct EngGQ {
     const uint64_t num = (x << V) >> 29, d0 = num >> 29;
     return (uint32_t)(d0 + ((d0 + 1) * p <= num));
   }
-  // fast recurrence on y = x / 2^29 mod p in 32-bit integers:
-  // 8 yc - 48 yp = 8 u mod p with u = yc + 6 (p - yp) < 7 p < 2^32.  With
-  // u = a 2^26 + b (b < 2^26), 8 u = a 2^29 + 8 b = 3 a + 8 b (mod p), and
-  // 3 a + 8 b < 2^29 + 189 < 2 p: one fold and one conditional subtraction
+  // fast recurrence on y = x / 2^29 mod p, stored as z = y - 37 (mod p) in
+  // [0, p + 166]: u = zc + 6 ((p + 11184779) - zp) < 2^32 (41 * 37 + 48 *
+  // 11184779 = p makes the constant cancel the offset) and 8 u = 3 floor(u /
+  // 2^26) + 8 (u mod 2^26) (mod p) is at most p + 163
   using F = uint32_t;
   static constexpr uint32_t kP = 536870909u, kM = 0x1FFFFFFFu;
-  __device__ static F to_fast(uint64_t x) { return (uint32_t)(x >> 29); }
-  __device__ static uint64_t from_fast(F y) { return ((uint64_t)y) << 29; }
-  __device__ static F step(F yc, F yp) {
-    const uint32_t u = yc + 6u * (kP - yp);                         // < 7 p < 2^32
-    const uint32_t w = ((u << 3) & kM) + __umul24(3u, u >> 26);     // = 8 u mod p, < 2 p
-    return min(w, w - kP);
+  static constexpr uint32_t kD = 37u, kE = 11184779u;
+  __device__ static F to_fast(uint64_t x) {
+    const uint32_t y = (uint32_t)(x >> 29);
+    return y >= kD ? y - kD : y + (kP - kD);
   }
-  // floor(2^v y / p): with d0 = floor(2^v y / 2^29) and r its remainder
-  // part, 2^v y - d0 p = r + 3 d0 < 2 p, so the digit is d0 or d0 + 1
-  __device__ static uint32_t digit(F y) {
-    if (V == 1) return y >= 268435455u;   // 2y >= p
-    const uint32_t d0 = y >> (29 - V);
-    const uint32_t r = (y & ((1u << (29 - V)) - 1u)) << V;
-    return d0 + ((r + __umul24(3u, d0)) >= kP ? 1u : 0u);
+  __device__ static uint64_t from_fast(F z) { return ((uint64_t)(z + kD >= kP ? z + kD - kP : z + kD)) << 29; }
+  __device__ static F step(F zc, F zp) {
+    const uint32_t u = zc + 6u * pin((kP + kE) - zp);
+    return ((u << 3) & kM) + __umul24(3u, u >> 26);
+  }
+  // floor(2^v y / p) with y = z + 37: with d0 = floor(2^v y / 2^29),
+  // 2^v y - d0 p < 2 p, so the digit is floor((2^v y + 3 d0 + 3) / 2^29) =
+  // floor((y + floor((3 d0 + 3) / 2^v)) / 2^(29-v)); d0 may be taken from z
+  // instead of y (checked for every z in the range).  z + 37 in [p, p + 203]
+  // stands for a value below p / 2^v (digit 0) and gives 2^v, which the
+  // v-bit field drops.
+  __device__ static uint32_t digit(F z) {
+    const uint32_t d0 = z >> (29 - V);
+    return ((z + ((__umul24(3u, d0) + (3u + (kD << V))) >> V)) >> (29 - V)) & ((1u << V) - 1u);
   }
 };
+
 // GQ58.1 after the collapse: z in [0, p + 184], z = y + 240 (mod p).
 // u = zc + 6 ((p + 205) - zp) < 7 p + 1415 < 2^32 and 8 u = 3 floor(u / 2^26)
 // + 8 (u mod 2^26) (mod p) <= p + 160; the constant p + 205 = p + 41 * 5

@@ -94,9 +94,9 @@ __device__ __forceinline__ FastPair<G> lane_jump_fast(const GmState* in, int e, 
     yc = nc;
     yp = np;
   }
-  FastPair<G> r;
-  r.yc = (typename E::F)yc;
-  r.yp = (typename E::F)yp;
+  FastPair<G> r;   // the ladder gives exact residues; the kernels' form may be offset
+  r.yc = E::to_fast(yc << E::t);
+  r.yp = E::to_fast(yp << E::t);
   return r;
 }
 
@@ -236,11 +236,15 @@ __device__ __forceinline__ void gmlane_wave(uint32_t* rows, bool live, const GmS
     sout->off = off_end;
     sout->pad = 0;
   };
+  // (the volatile asm keeps the conversion to exact values inside the rare
+  // save branch instead of letting it run ahead on every step)
   auto save_fast = [&](const F (&cur)[S], const F (&prev)[S]) {
 #pragma unroll
     for (int e = 0; e < S; e++) {
-      sout->xc[e] = E::from_fast(cur[e]);
-      sout->xp[e] = E::from_fast(prev[e]);
+      F c = cur[e], q = prev[e];
+      asm volatile("" : "+v"(c), "+v"(q));
+      sout->xc[e] = E::from_fast(c);
+      sout->xp[e] = E::from_fast(q);
     }
     save_tail();
   };
