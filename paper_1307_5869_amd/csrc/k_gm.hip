@@ -18,7 +18,11 @@
 // following the same recurrence mod p and the digit equal to
 // floor(2^v y / p), so the kernels run exact mod-g steps only until every
 // element of the wavefront has collapsed and then switch to the mod-p
-// recurrence.
+// recurrence.  In the steady state an element is held as a redundant
+// residue (congruent to the exact value, possibly shifted by a constant, in
+// a range a little wider than the modulus), so no step needs a final
+// conditional subtraction; digits are read off that form and states are
+// written back exact.
 #include "dev_gm.h"
 #include "dev_gmlane.h"
 
