@@ -6,9 +6,10 @@
 // long tiles early and the short ones fill the end.  Every MRG32K3A/LFSR113
 // and GM/GQ tile gets a slot in the batch's scratch area for its sections'
 // start states.  The launch is captured once in a HIP graph on a private
-// stream: the MT19937 kernel on one branch; the section-start kernel, then
-// the MRG32K3A/LFSR113 kernel and the three GM/GQ kernels on branches of
-// their own; it is replayed on the caller's stream.  The autotuner times a
+// stream: the section-start kernel, then MT19937 together with the v = 1
+// GM/GQ tiles on the main branch and the other GM/GQ shapes and
+// MRG32K3A/LFSR113 on branches of their own; it is replayed on the caller's
+// stream.  The autotuner times a
 // small grid of (wavefronts per workgroup, MRG32K3A/LFSR113 lane section,
 // GM/GQ group section) on the actual task mix.
 #include <hip/hip_runtime.h>
@@ -215,9 +216,12 @@ void free_batch(prand_batch* b) {
   delete b;
 }
 
-// The batch's kernels on stream a, forked onto the side streams and joined
-// back: MT19937 on side[0]; the section starts on a, then GM/GQ v = 1 on a,
-// v = 4 on side[1], GQ58.3 on side[2] and MRG32K3A/LFSR113 on side[3].
+// The batch's kernels on stream a, forked onto side streams 1..3 and joined
+// back: a runs the section starts, then MT19937 with the v = 1 ensembles in
+// one launch (the MT19937 tasks are single wavefronts, some tens of ms long,
+// and overlap the largest family inside that launch whatever hardware queues
+// the branches get); side 1 the v = 4 lane sections, side 2 GQ58.3, side 3
+// MRG32K3A/LFSR113.  side[0] is not used.
 hipError_t enqueue_forked(prand_batch* b, hipStream_t a) {
   const DeviceTables& T = b->ctx->T;
   const uint32_t w = b->cfg.waves_per_block;
@@ -227,17 +231,14 @@ hipError_t enqueue_forked(prand_batch* b, hipStream_t a) {
   const BatchTile* g8 = g32 + n.g32;
   const BatchTile* g3 = g8 + n.g8;
   const BatchTile* mt = g3 + n.g3;
-  hipError_t e = hipEventRecord(b->ev[0], a);
-  if (e == hipSuccess) e = hipStreamWaitEvent(b->side[0], b->ev[0], 0);
-  if (e == hipSuccess) e = launch_batch_mt(mt, n.mt + n.copy, b->d_tasks, w, b->side[0]);
-  if (e == hipSuccess) e = launch_batch_starts(T, reg, n.with_starts(), b->d_tasks, b->d_scratch, w, a);
+  hipError_t e = launch_batch_starts(T, reg, n.with_starts(), b->d_tasks, b->d_scratch, w, a);
   if (e == hipSuccess) e = hipEventRecord(b->ev[1], a);
+  if (e == hipSuccess) e = launch_batch_mt_v1(mt, n.mt + n.copy, g32, n.g32, b->d_tasks, b->d_scratch, w, a);
   for (int i = 1; i < 4 && e == hipSuccess; i++) e = hipStreamWaitEvent(b->side[i], b->ev[1], 0);
-  if (e == hipSuccess) e = launch_batch_gm(2, g3, n.g3, b->d_tasks, b->d_scratch, w, b->side[2]);
   if (e == hipSuccess) e = launch_batch_gm(1, g8, n.g8, b->d_tasks, b->d_scratch, w, b->side[1]);
+  if (e == hipSuccess) e = launch_batch_gm(2, g3, n.g3, b->d_tasks, b->d_scratch, w, b->side[2]);
   if (e == hipSuccess) e = launch_batch_reg(reg, n.reg, b->d_tasks, b->d_scratch, w, b->side[3]);
-  if (e == hipSuccess) e = launch_batch_gm(0, g32, n.g32, b->d_tasks, b->d_scratch, w, a);
-  for (int i = 0; i < 4 && e == hipSuccess; i++) {
+  for (int i = 1; i < 4 && e == hipSuccess; i++) {
     e = hipEventRecord(b->ev[2 + i], b->side[i]);
     if (e == hipSuccess) e = hipStreamWaitEvent(a, b->ev[2 + i], 0);
   }
@@ -323,7 +324,7 @@ int prand_batch_create(prand_ctx* c, const prand_task* h_tasks, uint32_t ntasks,
     e = hipMemcpy(b->d_tiles, plan.tiles.data(), plan.tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
   if (e == hipSuccess && ntasks) e = hipMemcpy(b->d_tasks, h_tasks, ntasks * sizeof(BatchTask), hipMemcpyHostToDevice);
   if (e == hipSuccess && conf.use_graph) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-  for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+  for (int i = 1; i < 4 && e == hipSuccess; i++) e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
   for (int i = 0; i < 6 && e == hipSuccess; i++) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     free_batch(b);

@@ -11,13 +11,17 @@
 //  - batch_starts_kernel jumps every MRG32K3A/LFSR113/GM/GQ section to its
 //    start and writes the state to the batch's scratch area (the jump code
 //    needs many registers, so it runs apart from the generation loops);
-//  - batch_reg_kernel, batch_gm_kernel<shape> (32-lane v = 1 ensembles,
-//    lane-per-section v = 4 ensembles, GQ58.3) and batch_mt_kernel generate, one
-//    wavefront per tile, from those states (or, for MT19937, from the task
-//    state) with the same wavefront routines as the one-generator kernels,
-//    and at their register counts.
+//  - batch_reg_kernel, batch_gm_kernel<shape> (lane-per-section v = 4
+//    ensembles, GQ58.3) and batch_mt_v1_kernel (MT19937 tasks, then the
+//    32-lane v = 1 ensembles) generate, one wavefront per tile, from those
+//    states (or, for MT19937, from the task state) with the same wavefront
+//    routines as the one-generator kernels, and at their register counts.
 // The generation kernels are independent of each other; tiles within each
 // are ordered longest first, so the dispatcher starts the long ones early.
+// MT19937 tasks run whole on one wavefront (the longest take tens of ms), so
+// they share a launch with the largest family, whose tiles fill the chip
+// around them: that overlap does not depend on how concurrent kernels are
+// spread over hardware queues.
 #include "dev_gm.h"
 #include "dev_gmlane.h"
 #include "dev_lfsr.h"
@@ -193,9 +197,9 @@ __device__ __forceinline__ void gen_gm(const BatchTile& tl, const BatchTask& tk,
   else gm::gen32_wave<G, DT, false>(s.live, in, 0, tl.len32, o, sout, nullptr);
 }
 
-// one kernel per ensemble shape, so each runs at its own register count:
-// S = 0: v = 1 (32 lanes per section), 1: v = 4 (a lane per section), 2:
-// GQ58.3 (a lane per section)
+// per ensemble shape, so each kernel runs at its own register count: S = 0:
+// v = 1 (32 lanes per section; batch_mt_v1_kernel), 1: v = 4 (a lane per
+// section), 2: GQ58.3 (a lane per section)
 template <int S, int DT>
 __device__ __forceinline__ void gen_gm_dt(const BatchTile& tl, const BatchTask& tk, const char* scratch,
                                           uint32_t* rows) {
@@ -215,16 +219,11 @@ __device__ __forceinline__ void gen_gm_dt(const BatchTile& tl, const BatchTask& 
   }
 }
 
-// LDS only for the lane-per-section shapes
-template <int S>
-struct GmRows {
-  static constexpr int kWords = (S == 0) ? 1 : gm::kLaneWaveWords;
-};
-
 template <int S>
 __global__ void __launch_bounds__(256) batch_gm_kernel(const BatchTile* __restrict__ tiles, uint32_t ntiles,
                                                        const BatchTask* __restrict__ tasks, const char* scratch) {
-  __shared__ __align__(16) uint32_t lds[4][GmRows<S>::kWords];
+  static_assert(S == 1 || S == 2, "lane-per-section shapes only");
+  __shared__ __align__(16) uint32_t lds[4][gm::kLaneWaveWords];
   const uint32_t t = wave_index();
   if (t >= ntiles) return;
   uint32_t* rows = lds[(threadIdx.x >> 6) & 3];
@@ -238,14 +237,8 @@ __global__ void __launch_bounds__(256) batch_gm_kernel(const BatchTile* __restri
 }
 
 // --------------------------------------------------- MT19937 and n = 0 tasks
-__global__ void __launch_bounds__(256) batch_mt_kernel(const BatchTile* __restrict__ tiles, uint32_t ntiles,
-                                                       const BatchTask* __restrict__ tasks) {
-  __shared__ uint32_t mt[4][624];
-  const uint32_t t = wave_index();
-  if (t >= ntiles) return;
+__device__ __forceinline__ void mt_tile(const BatchTile& tl, const BatchTask& tk, uint32_t* mine) {
   const int lane = threadIdx.x & 63;
-  const BatchTile tl = tiles[t];
-  const BatchTask tk = tasks[tl.task];
   if (tl.kind == kTileCopy) {
     // n = 0: the output state is the input state
     const uint32_t* a = (const uint32_t*)tk.state_in;
@@ -253,13 +246,34 @@ __global__ void __launch_bounds__(256) batch_mt_kernel(const BatchTile* __restri
     for (uint32_t i = lane; i < tl.len32; i += 64) b[i] = a[i];
     return;
   }
-  uint32_t* mine = mt[(threadIdx.x >> 6) & 3];
   const MtState* in = (const MtState*)tk.state_in;
   MtState* out = (MtState*)tk.state_out;
   switch (tk.dtype) {
     case PRAND_U32: mt::gen_wave<PRAND_U32>(mine, in, out, tk.n, tk.out); break;
     case PRAND_F32: mt::gen_wave<PRAND_F32>(mine, in, out, tk.n, tk.out); break;
     default: mt::gen_wave<PRAND_F64>(mine, in, out, tk.n, tk.out); break;
+  }
+}
+
+// wavefronts 0 .. nmt-1 take the MT19937 tiles, the next nv1 the v = 1 GM/GQ
+// tiles (the branch is uniform per wavefront)
+__global__ void __launch_bounds__(256) batch_mt_v1_kernel(const BatchTile* __restrict__ mt_tiles, uint32_t nmt,
+                                                          const BatchTile* __restrict__ v1_tiles, uint32_t nv1,
+                                                          const BatchTask* __restrict__ tasks, const char* scratch) {
+  __shared__ uint32_t mt[4][624];
+  const uint32_t t = wave_index();
+  if (t < nmt) {
+    const BatchTile tl = mt_tiles[t];
+    mt_tile(tl, tasks[tl.task], mt[(threadIdx.x >> 6) & 3]);
+    return;
+  }
+  if (t - nmt >= nv1) return;
+  const BatchTile tl = v1_tiles[t - nmt];
+  const BatchTask tk = tasks[tl.task];
+  switch (tk.dtype) {
+    case PRAND_U32: gen_gm_dt<0, PRAND_U32>(tl, tk, scratch, nullptr); break;
+    case PRAND_F32: gen_gm_dt<0, PRAND_F32>(tl, tk, scratch, nullptr); break;
+    default: gen_gm_dt<0, PRAND_F64>(tl, tk, scratch, nullptr); break;
   }
 }
 
@@ -287,18 +301,16 @@ hipError_t launch_batch_gm(int shape, const BatchTile* tiles, uint32_t ntiles, c
                            const char* scratch, uint32_t waves, hipStream_t st) {
   if (!ntiles) return hipSuccess;
   const dim3 grid(blocks_for(ntiles, waves)), block(64 * waves);
-  switch (shape) {
-    case 0: hipLaunchKernelGGL(batch_gm_kernel<0>, grid, block, 0, st, tiles, ntiles, tasks, scratch); break;
-    case 1: hipLaunchKernelGGL(batch_gm_kernel<1>, grid, block, 0, st, tiles, ntiles, tasks, scratch); break;
-    default: hipLaunchKernelGGL(batch_gm_kernel<2>, grid, block, 0, st, tiles, ntiles, tasks, scratch); break;
-  }
+  if (shape == 1) hipLaunchKernelGGL(batch_gm_kernel<1>, grid, block, 0, st, tiles, ntiles, tasks, scratch);
+  else hipLaunchKernelGGL(batch_gm_kernel<2>, grid, block, 0, st, tiles, ntiles, tasks, scratch);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_mt(const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks, uint32_t waves,
-                           hipStream_t st) {
-  if (!ntiles) return hipSuccess;
-  hipLaunchKernelGGL(batch_mt_kernel, dim3(blocks_for(ntiles, waves)), dim3(64 * waves), 0, st, tiles, ntiles, tasks);
+hipError_t launch_batch_mt_v1(const BatchTile* mt, uint32_t nmt, const BatchTile* v1, uint32_t nv1,
+                              const BatchTask* tasks, const char* scratch, uint32_t waves, hipStream_t st) {
+  if (!nmt && !nv1) return hipSuccess;
+  hipLaunchKernelGGL(batch_mt_v1_kernel, dim3(blocks_for(nmt + nv1, waves)), dim3(64 * waves), 0, st, mt, nmt, v1,
+                     nv1, tasks, scratch);
   return hipGetLastError();
 }
 
@@ -309,11 +321,10 @@ hipError_t launch_batch_serial(const DeviceTables& T, const BatchTile* tiles, co
   const BatchTile* g8 = g32 + n.g32;
   const BatchTile* g3 = g8 + n.g8;
   const BatchTile* mt = g3 + n.g3;
-  hipError_t e = launch_batch_mt(mt, n.mt + n.copy, tasks, waves, st);
-  if (e == hipSuccess) e = launch_batch_starts(T, tiles, n.with_starts(), tasks, scratch, waves, st);
+  hipError_t e = launch_batch_starts(T, tiles, n.with_starts(), tasks, scratch, waves, st);
+  if (e == hipSuccess) e = launch_batch_mt_v1(mt, n.mt + n.copy, g32, n.g32, tasks, scratch, waves, st);
   if (e == hipSuccess) e = launch_batch_gm(2, g3, n.g3, tasks, scratch, waves, st);
   if (e == hipSuccess) e = launch_batch_gm(1, g8, n.g8, tasks, scratch, waves, st);
-  if (e == hipSuccess) e = launch_batch_gm(0, g32, n.g32, tasks, scratch, waves, st);
   if (e == hipSuccess) e = launch_batch_reg(reg, n.reg, tasks, scratch, waves, st);
   return e;
 }

@@ -62,12 +62,14 @@ hipError_t launch_batch_starts(const DeviceTables& T, const BatchTile* tiles, ui
                                char* scratch, uint32_t waves, hipStream_t st);
 hipError_t launch_batch_reg(const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks, const char* scratch,
                             uint32_t waves, hipStream_t st);
-// shape 0: v = 1 ensembles, 1: v = 4 ensembles, 2: GQ58.3
+// lane-section GM/GQ shapes: 1 = v = 4 ensembles, 2 = GQ58.3
 hipError_t launch_batch_gm(int shape, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
                            const char* scratch, uint32_t waves, hipStream_t st);
-hipError_t launch_batch_mt(const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks, uint32_t waves,
-                           hipStream_t st);
-// all of them on one stream: MT19937, section starts, GM/GQ, MRG32K3A/LFSR113
+// MT19937 tiles (and n = 0 copies) followed by the v = 1 GM/GQ tiles, in one
+// launch (after the section starts, which the v = 1 tiles read)
+hipError_t launch_batch_mt_v1(const BatchTile* mt, uint32_t nmt, const BatchTile* v1, uint32_t nv1,
+                              const BatchTask* tasks, const char* scratch, uint32_t waves, hipStream_t st);
+// all of them on one stream: section starts, MT19937 + v = 1, the other GM/GQ, MRG32K3A/LFSR113
 hipError_t launch_batch_serial(const DeviceTables& T, const BatchTile* tiles, const BatchCounts& n,
                                const BatchTask* tasks, char* scratch, uint32_t waves, hipStream_t st);
 
