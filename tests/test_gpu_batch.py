@@ -71,6 +71,29 @@ def test_batch_matches_oracle(ctx, oracle, cfg):
     b.close()
 
 
+# batches holding only some families: the MT19937 tiles and the v = 1 GM/GQ
+# tiles share one kernel, and either part (or both) may be empty
+SUBSETS = {
+    "mt_only": [(P.MT19937, dt, n) for dt in (P.U32, P.F64) for n in (0, 1, 700, 5000)],
+    "v1_only": [(g, dt, n) for g in (P.GM19, P.GM61, P.GQ58X1) for dt in (P.U32, P.F32) for n in (1, 64, 3001)],
+    "mt_and_v1": [(P.MT19937, P.F32, 2500), (P.GM29, P.F32, 2500), (P.GM31, P.U32, 77), (P.MT19937, P.U32, 0)],
+    "no_mt_no_v1": [(g, P.U32, n) for g in (P.MRG32K3A, P.GM55, P.GQ58X3) for n in (5, 4000)],
+    "copies_only": [(g, P.U32, 0) for g in range(11)],
+}
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+@pytest.mark.parametrize("subset", sorted(SUBSETS))
+def test_batch_family_subsets(ctx, oracle, subset, graph):
+    tasks, refs = make_tasks(oracle, SUBSETS[subset], seed0=1300)
+    b = P.Batch(ctx, tasks, P.BatchConfig(4, 2048, 4096, graph))
+    for _ in range(2):
+        b.launch()
+        torch.cuda.synchronize()
+        check(tasks, refs)
+    b.close()
+
+
 def test_batch_graph_replays(ctx, oracle):
     """Replays of the captured graph, with eager work between them, all give
     the same result (the input states are never written)."""
