@@ -29,6 +29,40 @@ __device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
   else ((double*)out)[i] = (double)w * 0x1p-32;
 }
 
+// One phase of a twist: words j = j0 + lane + 64 k (k < K, j < j1) become
+// recur(mt[j], mt[j + 1], mt[j + off]) (word 623's successor is word 0).
+// Every word a phase reads is either untouched by it or renewed by an
+// earlier phase, so all its loads are issued before any of its stores: one
+// LDS latency per phase instead of one per 64 words (a lone wavefront, as in
+// batched and served MT19937 tasks, is bound by that latency).
+template <int DT, int K>
+__device__ __forceinline__ void twist_phase(uint32_t* mt, int j0, int j1, int off, int want, uint64_t pos, void* out) {
+  const int lane = threadIdx.x & 63;
+  uint32_t a[K], b[K], c[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int j = j0 + lane + 64 * k;
+    if (j < j1) {
+      a[k] = mt[j];
+      b[k] = mt[j == 623 ? 0 : j + 1];
+      c[k] = mt[j + off];
+    }
+  }
+  // lane 63's mt[j + 1] is lane 0's word of the next slice: no store may be
+  // scheduled above these loads (one wavefront's LDS operations then run in
+  // issue order)
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int j = j0 + lane + 64 * k;
+    if (j < j1) {
+      const uint32_t v = recur(a[k], b[k], c[k]);
+      mt[j] = v;
+      if (j < want) put<DT>(out, pos + j, temper(v));
+    }
+  }
+}
+
 // One wavefront generates n outputs of one stream: state *in (copied into
 // the LDS block mt[624]), outputs at out, advanced state to *sout (may be
 // the same object as *in).  A twist renews the block in three dependency
@@ -50,23 +84,11 @@ __device__ __forceinline__ void gen_wave(uint32_t* mt, const MtState* in, MtStat
   while (pos < n) {
     const uint64_t left = n - pos;
     const int want = left < 624 ? (int)left : 624;
-    for (int j = lane; j < 227; j += 64) {
-      const uint32_t v = recur(mt[j], mt[j + 1], mt[j + 397]);
-      mt[j] = v;
-      if (j < want) put<DT>(out, pos + j, temper(v));
-    }
+    twist_phase<DT, 4>(mt, 0, 227, 397, want, pos, out);
     wave_lds_sync();
-    for (int j = 227 + lane; j < 454; j += 64) {
-      const uint32_t v = recur(mt[j], mt[j + 1], mt[j - 227]);
-      mt[j] = v;
-      if (j < want) put<DT>(out, pos + j, temper(v));
-    }
+    twist_phase<DT, 4>(mt, 227, 454, -227, want, pos, out);
     wave_lds_sync();
-    for (int j = 454 + lane; j < 624; j += 64) {
-      const uint32_t v = recur(mt[j], mt[j == 623 ? 0 : j + 1], mt[j - 227]);
-      mt[j] = v;
-      if (j < want) put<DT>(out, pos + j, temper(v));
-    }
+    twist_phase<DT, 3>(mt, 454, 624, -227, want, pos, out);
     wave_lds_sync();
     pos += want;
     idx = want;
