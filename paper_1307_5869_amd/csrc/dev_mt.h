@@ -29,12 +29,13 @@ __device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
   else ((double*)out)[i] = (double)w * 0x1p-32;
 }
 
-// One phase of a twist: words j = j0 + lane + 64 k (k < K, j < j1) become
-// recur(mt[j], mt[j + 1], mt[j + off]) (word 623's successor is word 0).
-// Every word a phase reads is either untouched by it or renewed by an
-// earlier phase, so all its loads are issued before any of its stores: one
-// LDS latency per phase instead of one per 64 words (a lone wavefront, as in
-// batched and served MT19937 tasks, is bound by that latency).
+// A piece of a twist phase: words j = j0 + lane + 64 k (k < K, j < j1)
+// become recur(mt[j], mt[j + 1], mt[j + off]) (word 623's successor is word
+// 0).  Every word a phase reads is either untouched by it or renewed by an
+// earlier phase, so a piece issues all its loads before any of its stores:
+// one LDS latency per K slices of 64 words instead of one per slice (a lone
+// wavefront, as in batched and served MT19937 tasks, is bound by that
+// latency).
 template <int DT, int K>
 __device__ __forceinline__ void twist_phase(uint32_t* mt, int j0, int j1, int off, int want, uint64_t pos, void* out) {
   const int lane = threadIdx.x & 63;
@@ -48,9 +49,9 @@ __device__ __forceinline__ void twist_phase(uint32_t* mt, int j0, int j1, int of
       c[k] = mt[j + off];
     }
   }
-  // lane 63's mt[j + 1] is lane 0's word of the next slice: no store may be
-  // scheduled above these loads (one wavefront's LDS operations then run in
-  // issue order)
+  // lane 63's mt[j + 1] is lane 0's word of the next slice (maybe in the
+  // next piece): no store may be scheduled above these loads (one
+  // wavefront's LDS operations then run in issue order)
   asm volatile("" ::: "memory");
 #pragma unroll
   for (int k = 0; k < K; k++) {
@@ -84,11 +85,19 @@ __device__ __forceinline__ void gen_wave(uint32_t* mt, const MtState* in, MtStat
   while (pos < n) {
     const uint64_t left = n - pos;
     const int want = left < 624 ? (int)left : 624;
-    twist_phase<DT, 4>(mt, 0, 227, 397, want, pos, out);
+    // phases in pieces of two 64-word slices: the loads of four slices at
+    // once measured the same for a lone wavefront but took 60 instead of 56
+    // VGPRs in the batch kernel that shares this code with the v = 1 GM/GQ
+    // tiles, which upset the balance of the batch's concurrent kernels
+    // (95.8 -> 102.9 ms per launch)
+    twist_phase<DT, 2>(mt, 0, 128, 397, want, pos, out);
+    twist_phase<DT, 2>(mt, 128, 227, 397, want, pos, out);
     wave_lds_sync();
-    twist_phase<DT, 4>(mt, 227, 454, -227, want, pos, out);
+    twist_phase<DT, 2>(mt, 227, 355, -227, want, pos, out);
+    twist_phase<DT, 2>(mt, 355, 454, -227, want, pos, out);
     wave_lds_sync();
-    twist_phase<DT, 3>(mt, 454, 624, -227, want, pos, out);
+    twist_phase<DT, 2>(mt, 454, 582, -227, want, pos, out);
+    twist_phase<DT, 1>(mt, 582, 624, -227, want, pos, out);
     wave_lds_sync();
     pos += want;
     idx = want;
