@@ -91,8 +91,13 @@ hipError_t ensure_mt(prand_ctx* c) {
   if (c->mt_ready) return hipSuccess;
   std::vector<uint32_t> mt((size_t)kLadder * 624), dlo((size_t)kMtLoDigits * kMtLoSize * 624),
       d8((size_t)2 * 256 * 624);
+  std::vector<uint32_t> blk((size_t)kMtBlkPolys * 624), inv(624);
   if (!mt_build_polys(mt.data(), kLadder, dlo.data(), d8.data(), kMtDigitE)) return hipErrorUnknown;
+  if (!mt_build_block_polys(kMtBlkFirst + kMtBlkPolys + 9, kMtBlkFirst, kMtBlkPolys, blk.data(), inv.data()))
+    return hipErrorUnknown;
   hipError_t e = upload(&c->T.mt, mt.data(), mt.size());
+  if (e == hipSuccess) e = upload(&c->T.mtblk, blk.data(), blk.size());
+  if (e == hipSuccess) e = upload(&c->T.mtinv, inv.data(), inv.size());
   if (e == hipSuccess) e = upload(&c->T.mtdiglo, dlo.data(), dlo.size());
   if (e == hipSuccess) e = upload(&c->T.mtdig8hi, d8.data(), d8.size());
   // the default state jumped t * 2^(432 + 48) for every top-16-bit value t
@@ -267,6 +272,8 @@ int prand_ctx_destroy(prand_ctx* c) {
   (void)hipFree(c->T.mtdiglo);
   (void)hipFree(c->T.mtdig8hi);
   (void)hipFree(c->T.mttop);
+  (void)hipFree(c->T.mtblk);
+  (void)hipFree(c->T.mtinv);
   (void)hipFree(c->T.defaults);
   (void)hipFree(c->scratch);
   delete c;

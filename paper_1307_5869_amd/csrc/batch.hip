@@ -87,7 +87,8 @@ namespace prand {
 
 void batch_fill_defaults(prand_batch_config& c) { fill_defaults(c); }
 
-int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, BatchPlan& plan) {
+int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, BatchPlan& plan,
+               uint64_t mt_section_min) {
   // families in BatchCounts order: MRG32K3A/LFSR113, GM/GQ v = 1, v = 4,
   // GQ58.3, MT19937, copies (n = 0)
   std::vector<std::pair<double, BatchTile>> work[kBatchFamilies];
@@ -109,10 +110,23 @@ int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_confi
     const uint64_t n = t.n, es = t.dtype == PRAND_F64 ? 8 : 4;
     const double c = per_output_cost(t.gen);
     if (t.gen == PRAND_MT19937) {
-      b.first = 0;
-      b.seclen = n;
-      b.nsec = 1;
-      work[4].push_back({c * (double)n, b});
+      // one wavefront per task, or, for a long task, per kMtSection-output
+      // section (each section starts from a jump of the task state)
+      const uint64_t sec = kMtSection;
+      if (n <= std::max(sec, mt_section_min)) {
+        b.first = 0;
+        b.seclen = n;
+        b.nsec = 1;
+        work[4].push_back({c * (double)n, b});
+      } else {
+        b.kind = kTileMtSection;
+        b.seclen = sec;
+        b.nsec = 1;
+        for (uint64_t f = 0; f * sec < n; f++) {
+          b.first = f;
+          work[4].push_back({c * (double)std::min(sec, n - f * sec), b});
+        }
+      }
       continue;
     }
     if (is_reg(t.gen)) {
@@ -173,18 +187,23 @@ int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_confi
   if (total > 0xFFFFFFF0ull) return PRAND_ERANGE;
   plan.tiles.resize(total);
   plan.scratch_bytes = 0;
+  plan.n.mtsec = 0;
   size_t at = 0;
   for (int f = 0; f < kBatchFamilies; f++) {
     std::stable_sort(work[f].begin(), work[f].end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     for (auto& w : work[f]) {
       BatchTile& tl = plan.tiles[at++];
       tl = w.second;
-      if (f <= 3) {
-        // section start states: 64 register states or one GmState per section
+      if (f <= 3 || tl.kind == kTileMtSection) {
+        // section start states: 64 register states, one GmState per
+        // section, or the MT19937 section's state
         const int gen = tasks[tl.task].gen;
-        const uint64_t bytes = f == 0 ? 64 * state_size(gen) : (uint64_t)tl.nsec * sizeof(GmState);
+        const uint64_t bytes = f == 0   ? 64 * state_size(gen)
+                               : f == 4 ? (uint64_t)sizeof(MtState)
+                                        : (uint64_t)tl.nsec * sizeof(GmState);
         tl.starts = plan.scratch_bytes;
         plan.scratch_bytes += round_up(bytes, 64);
+        if (f == 4) plan.n.mtsec++;
       }
     }
   }
@@ -217,8 +236,9 @@ void free_batch(prand_batch* b) {
 }
 
 // The batch's kernels on stream a, forked onto side streams 1..3 and joined
-// back: a runs the section starts, then MT19937 with the v = 1 ensembles in
-// one launch (the MT19937 tasks are single wavefronts, some tens of ms long,
+// back: a runs the section starts (and the MT19937 section starts, when a
+// task is long enough to have sections), then MT19937 with the v = 1
+// ensembles in one launch (the MT19937 tasks are single wavefronts, some tens of ms long,
 // and overlap the largest family inside that launch whatever hardware queues
 // the branches get); side 1 the v = 4 lane sections, side 2 GQ58.3, side 3
 // MRG32K3A/LFSR113.  side[0] is not used.
@@ -233,6 +253,7 @@ hipError_t enqueue_forked(prand_batch* b, hipStream_t a) {
   const BatchTile* mt = g3 + n.g3;
   hipError_t e = launch_batch_starts(T, reg, n.with_starts(), b->d_tasks, b->d_scratch, w, a);
   if (e == hipSuccess) e = hipEventRecord(b->ev[1], a);
+  if (e == hipSuccess && n.mtsec) e = launch_batch_mt_starts(T, mt, n.mt, b->d_tasks, b->d_scratch, a);
   if (e == hipSuccess) e = launch_batch_mt_v1(mt, n.mt + n.copy, g32, n.g32, b->d_tasks, b->d_scratch, w, a);
   for (int i = 1; i < 4 && e == hipSuccess; i++) e = hipStreamWaitEvent(b->side[i], b->ev[1], 0);
   if (e == hipSuccess) e = launch_batch_gm(1, g8, n.g8, b->d_tasks, b->d_scratch, w, b->side[1]);
@@ -309,8 +330,10 @@ int prand_batch_create(prand_ctx* c, const prand_task* h_tasks, uint32_t ntasks,
   if (cfg) conf = *cfg;
   fill_defaults(conf);
   BatchPlan plan;
-  int rc = batch_plan(h_tasks, ntasks, conf, plan);
+  int rc = batch_plan(h_tasks, ntasks, conf, plan, kMtBatchSectionMin);
   if (rc) return rc;
+  // MT19937 sections start from ladder jumps: the context's MT19937 tables
+  if (plan.n.mtsec && (rc = ensure_mt_tables(c)) != PRAND_OK) return rc;
   DeviceGuard g(c->device);
   prand_batch* b = new (std::nothrow) prand_batch;
   if (!b) return PRAND_ENOMEM;

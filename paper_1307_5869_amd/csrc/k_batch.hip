@@ -53,7 +53,11 @@ __device__ __forceinline__ Sect section_of(const BatchTile& tl, const BatchTask&
 
 constexpr int gm_groups(int G) { return (G == 3 || G == 6 || G == 7) ? 64 : 2; }
 
-__device__ __forceinline__ uint32_t wave_index() { return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); }
+// the tile index of this wavefront, known to the compiler as uniform across
+// it, so the tile and task fields it loads live in scalar registers
+__device__ __forceinline__ uint32_t wave_index() {
+  return __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+}
 
 // ---------------------------------------------------------------- starts
 template <class G>
@@ -237,7 +241,11 @@ __global__ void __launch_bounds__(256) batch_gm_kernel(const BatchTile* __restri
 }
 
 // --------------------------------------------------- MT19937 and n = 0 tasks
-__device__ __forceinline__ void mt_tile(const BatchTile& tl, const BatchTask& tk, uint32_t* mine) {
+// A whole MT19937 task, or one kMtSection-output section of a long one: the
+// section starts from its state in the scratch; a section that is not the
+// task's last leaves its end state in that same slot (read by this
+// wavefront only, before it is written).
+__device__ __forceinline__ void mt_tile(const BatchTile& tl, const BatchTask& tk, char* scratch, uint32_t* mine) {
   const int lane = threadIdx.x & 63;
   if (tl.kind == kTileCopy) {
     // n = 0: the output state is the input state
@@ -248,10 +256,18 @@ __device__ __forceinline__ void mt_tile(const BatchTile& tl, const BatchTask& tk
   }
   const MtState* in = (const MtState*)tk.state_in;
   MtState* out = (MtState*)tk.state_out;
+  uint64_t n = tk.n, start = 0;
+  if (tl.kind == kTileMtSection) {
+    MtState* slot = (MtState*)(scratch + tl.starts);
+    start = tl.first * tl.seclen;
+    n = (tk.n - start < tl.seclen) ? tk.n - start : tl.seclen;
+    in = slot;
+    if (start + n < tk.n) out = slot;
+  }
   switch (tk.dtype) {
-    case PRAND_U32: mt::gen_wave<PRAND_U32>(mine, in, out, tk.n, tk.out); break;
-    case PRAND_F32: mt::gen_wave<PRAND_F32>(mine, in, out, tk.n, tk.out); break;
-    default: mt::gen_wave<PRAND_F64>(mine, in, out, tk.n, tk.out); break;
+    case PRAND_U32: mt::gen_wave<PRAND_U32>(mine, in, out, n, (char*)tk.out + start * 4); break;
+    case PRAND_F32: mt::gen_wave<PRAND_F32>(mine, in, out, n, (char*)tk.out + start * 4); break;
+    default: mt::gen_wave<PRAND_F64>(mine, in, out, n, (char*)tk.out + start * 8); break;
   }
 }
 
@@ -259,12 +275,12 @@ __device__ __forceinline__ void mt_tile(const BatchTile& tl, const BatchTask& tk
 // tiles (the branch is uniform per wavefront)
 __global__ void __launch_bounds__(256) batch_mt_v1_kernel(const BatchTile* __restrict__ mt_tiles, uint32_t nmt,
                                                           const BatchTile* __restrict__ v1_tiles, uint32_t nv1,
-                                                          const BatchTask* __restrict__ tasks, const char* scratch) {
+                                                          const BatchTask* __restrict__ tasks, char* scratch) {
   __shared__ uint32_t mt[4][624];
   const uint32_t t = wave_index();
   if (t < nmt) {
     const BatchTile tl = mt_tiles[t];
-    mt_tile(tl, tasks[tl.task], mt[(threadIdx.x >> 6) & 3]);
+    mt_tile(tl, tasks[tl.task], scratch, mt[(threadIdx.x >> 6) & 3]);
     return;
   }
   if (t - nmt >= nv1) return;
@@ -307,7 +323,7 @@ hipError_t launch_batch_gm(int shape, const BatchTile* tiles, uint32_t ntiles, c
 }
 
 hipError_t launch_batch_mt_v1(const BatchTile* mt, uint32_t nmt, const BatchTile* v1, uint32_t nv1,
-                              const BatchTask* tasks, const char* scratch, uint32_t waves, hipStream_t st) {
+                              const BatchTask* tasks, char* scratch, uint32_t waves, hipStream_t st) {
   if (!nmt && !nv1) return hipSuccess;
   hipLaunchKernelGGL(batch_mt_v1_kernel, dim3(blocks_for(nmt + nv1, waves)), dim3(64 * waves), 0, st, mt, nmt, v1,
                      nv1, tasks, scratch);
@@ -322,6 +338,7 @@ hipError_t launch_batch_serial(const DeviceTables& T, const BatchTile* tiles, co
   const BatchTile* g3 = g8 + n.g8;
   const BatchTile* mt = g3 + n.g3;
   hipError_t e = launch_batch_starts(T, tiles, n.with_starts(), tasks, scratch, waves, st);
+  if (e == hipSuccess && n.mtsec) e = launch_batch_mt_starts(T, mt, n.mt, tasks, scratch, st);
   if (e == hipSuccess) e = launch_batch_mt_v1(mt, n.mt + n.copy, g32, n.g32, tasks, scratch, waves, st);
   if (e == hipSuccess) e = launch_batch_gm(2, g3, n.g3, tasks, scratch, waves, st);
   if (e == hipSuccess) e = launch_batch_gm(1, g8, n.g8, tasks, scratch, waves, st);

@@ -25,6 +25,7 @@
 // three-input XORs per two.
 #include "dev_mt.h"
 #include "mt_poly.h"
+#include "prand_batch.h"
 
 namespace prand {
 namespace {
@@ -248,7 +249,57 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
   }
 }
 
+// Start state of an MT19937 section tile of a batch: the task state moved
+// D = first * kMtSection outputs on, a whole number of 624-word blocks, so
+// the state keeps the task's block grid and its place in the block (idx)
+// and equals the state sequential generation would reach.  x^D (one
+// whole-block ladder polynomial per set bit of the section number) moves
+// every word of the array D places along the sequence but leaves only the
+// top bit of the oldest word exact; x^(-1) then steps the window one word
+// back, so that the array's words 1..623 are the exact words 0..622 of the
+// target window, and one step of the recurrence supplies its word 623.
+// Section 0 is a copy.
+__global__ void __launch_bounds__(64) mt_section_start_kernel(const BatchTile* __restrict__ tiles, uint32_t ntiles,
+                                                              const BatchTask* __restrict__ tasks,
+                                                              char* __restrict__ scratch,
+                                                              const uint32_t* __restrict__ blk,
+                                                              const uint32_t* __restrict__ inv) {
+  __shared__ __align__(16) uint32_t ring[kRing + kMirror];
+  const uint32_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  const BatchTile tl = tiles[t];
+  if (tl.kind != kTileMtSection) return;
+  const int lane = threadIdx.x;
+  const MtState* src = (const MtState*)tasks[tl.task].state_in;
+  MtState* dst = (MtState*)(scratch + tl.starts);
+  for (int i = lane; i < 624; i += 64) ring[i] = src->mt[i];
+  const uint32_t idx = src->idx < 624u ? src->idx : 624u;
+  __syncthreads();
+  uint64_t sec = tl.first;
+  if (sec == 0) {
+    for (int i = lane; i < 624; i += 64) dst->mt[i] = ring[i];
+  } else {
+    for (int b = 0; sec; b++, sec >>= 1)
+      if (sec & 1u) apply_poly(ring, blk + (size_t)b * 624, lane);
+    apply_poly(ring, inv, lane);
+    for (int i = lane; i < 623; i += 64) dst->mt[i] = ring[i + 1];
+    if (lane == 0) dst->mt[623] = recur(ring[0], ring[1], ring[397]);
+  }
+  if (lane == 0) {
+    dst->idx = idx;
+    dst->pad[0] = dst->pad[1] = dst->pad[2] = 0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_batch_mt_starts(const DeviceTables& T, const BatchTile* tiles, uint32_t ntiles,
+                                  const BatchTask* tasks, char* scratch, hipStream_t st) {
+  if (!ntiles) return hipSuccess;
+  hipLaunchKernelGGL(mt_section_start_kernel, dim3(ntiles), dim3(64), 0, st, tiles, ntiles, tasks, scratch, T.mtblk,
+                     T.mtinv);
+  return hipGetLastError();
+}
 
 hipError_t launch_mt_generate(MtState* states, uint32_t count, uint64_t n, int dtype, void* out, hipStream_t st) {
   switch (dtype) {

@@ -298,4 +298,28 @@ bool mt_build_polys(uint32_t* ladder, int nladder, uint32_t* dig_lo, uint32_t* d
   return true;
 }
 
+bool mt_build_block_polys(int nladder, int first, int nblk, uint32_t* blk, uint32_t* inv) {
+  if (first + nblk + 9 > nladder) return false;
+  Field F;
+  if (!F.init()) return false;
+  std::vector<uint64_t> lad((size_t)nladder * kW, 0);
+  lad[0] = 2;   // x
+  for (int b = 0; b + 1 < nladder; b++) F.mulmod(&lad[(size_t)b * kW], &lad[(size_t)b * kW], &lad[(size_t)(b + 1) * kW]);
+  // 624 2^k = 2^(k+9) + 2^(k+6) + 2^(k+5) + 2^(k+4)
+  std::vector<uint64_t> g(kW), t(kW);
+  for (int i = 0; i < nblk; i++) {
+    const int k = first + i;
+    F.mulmod(&lad[(size_t)(k + 9) * kW], &lad[(size_t)(k + 6) * kW], g.data());
+    F.mulmod(g.data(), &lad[(size_t)(k + 5) * kW], t.data());
+    F.mulmod(t.data(), &lad[(size_t)(k + 4) * kW], g.data());
+    store(g.data(), blk + (size_t)i * kMtPolyWords);
+  }
+  // (phi - 1) / x: phi's bits 1 .. n moved down one place (degree n - 1)
+  std::vector<uint64_t> q(kW, 0);
+  if (!(F.phi[0] & 1u)) return false;
+  shr(F.phi.data(), kW + 1, 1, q.data(), kW);
+  store(q.data(), inv);
+  return true;
+}
+
 }  // namespace prand

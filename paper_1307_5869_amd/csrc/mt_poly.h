@@ -24,4 +24,10 @@ constexpr int kMtLoSize = 1 << kMtLoBits;
 // false if phi has the wrong degree or the ladder is too short.
 bool mt_build_polys(uint32_t* ladder, int nladder, uint32_t* dig_lo, uint32_t* dig8hi, int digit_e);
 
+// Whole-block jumps: blk (nblk polynomials) gets x^(624 * 2^(first + i))
+// mod phi, i < nblk (needs first + nblk + 9 <= nladder of the 2^b ladder,
+// rebuilt here), and inv gets x^(-1) mod phi = (phi - 1) / x (phi(0) = 1: the
+// transition is invertible).  Returns false as mt_build_polys does.
+bool mt_build_block_polys(int nladder, int first, int nblk, uint32_t* blk, uint32_t* inv);
+
 }  // namespace prand

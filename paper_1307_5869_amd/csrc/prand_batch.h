@@ -21,6 +21,11 @@ static_assert(sizeof(BatchTask) == sizeof(prand_task), "prand_task layout");
 
 constexpr uint32_t kTileGen = 0;    // generate sections first .. first + nsec - 1
 constexpr uint32_t kTileCopy = 1;   // n = 0: copy state_in to state_out
+// section `first` of a long MT19937 task (kMtSection outputs each: whole
+// 624-word blocks), started from the state the section-start kernel leaves
+// in the scratch
+constexpr uint32_t kTileMtSection = 2;
+constexpr uint64_t kMtSection = 624ull << kMtBlkFirst;
 
 // the work of one wavefront
 struct BatchTile {
@@ -40,6 +45,7 @@ struct BatchTile {
 // (MRG32K3A/LFSR113; GM/GQ with v = 1, with v = 4, GQ58.3; MT19937; n = 0)
 struct BatchCounts {
   uint32_t reg = 0, g32 = 0, g8 = 0, g3 = 0, mt = 0, copy = 0;
+  uint32_t mtsec = 0;   // MT19937 section tiles among the mt ones
   uint32_t with_starts() const { return reg + g32 + g8 + g3; }
   uint32_t total() const { return with_starts() + mt + copy; }
 };
@@ -54,8 +60,14 @@ struct BatchPlan {
 // zero fields of a configuration replaced by the defaults
 void batch_fill_defaults(prand_batch_config& c);
 // cut tasks into tiles, family by family, each family longest first
-// (PRAND_OK or an error code)
-int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, BatchPlan& plan);
+// (PRAND_OK or an error code); MT19937 tasks longer than mt_section_min
+// outputs are cut into kMtSection-output sections
+int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, BatchPlan& plan,
+               uint64_t mt_section_min);
+// MT19937 tasks of a batched launch above this many outputs (about 16 ms of
+// one wavefront) run as sections; below it the jumps cost more than the
+// wavefront's run, which the batch's other work covers
+constexpr uint64_t kMtBatchSectionMin = 1ull << 24;
 
 // the kernels of a batch, `waves` wavefronts (tiles) per workgroup
 hipError_t launch_batch_starts(const DeviceTables& T, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
@@ -66,9 +78,14 @@ hipError_t launch_batch_reg(const BatchTile* tiles, uint32_t ntiles, const Batch
 hipError_t launch_batch_gm(int shape, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
                            const char* scratch, uint32_t waves, hipStream_t st);
 // MT19937 tiles (and n = 0 copies) followed by the v = 1 GM/GQ tiles, in one
-// launch (after the section starts, which the v = 1 tiles read)
+// launch (after the section starts, which the v = 1 and MT19937 section
+// tiles read)
 hipError_t launch_batch_mt_v1(const BatchTile* mt, uint32_t nmt, const BatchTile* v1, uint32_t nv1,
-                              const BatchTask* tasks, const char* scratch, uint32_t waves, hipStream_t st);
+                              const BatchTask* tasks, char* scratch, uint32_t waves, hipStream_t st);
+// start states of the MT19937 section tiles among tiles[0 .. ntiles): the
+// task state moved first * kMtSection outputs on (one wavefront each)
+hipError_t launch_batch_mt_starts(const DeviceTables& T, const BatchTile* tiles, uint32_t ntiles,
+                                  const BatchTask* tasks, char* scratch, hipStream_t st);
 // all of them on one stream: section starts, MT19937 + v = 1, the other GM/GQ, MRG32K3A/LFSR113
 hipError_t launch_batch_serial(const DeviceTables& T, const BatchTile* tiles, const BatchCounts& n,
                                const BatchTask* tasks, char* scratch, uint32_t waves, hipStream_t st);

@@ -75,11 +75,17 @@ struct DeviceTables {
   uint32_t* mtdiglo = nullptr;  // [3][65536][624]: x^(d 2^(kMtDigitE + 16k)) mod phi
   uint32_t* mtdig8hi = nullptr; // [2][256][624]: x^(d 2^(kMtDigitE + 48 + 8j)) mod phi
   void* mttop = nullptr;        // [65536] MtState: the default state jumped t 2^(kMtDigitE + 48)
+  uint32_t* mtblk = nullptr;    // [kMtBlkPolys][624]: x^(624 2^(kMtBlkFirst + i)) mod phi
+  uint32_t* mtinv = nullptr;    // [624]: x^(-1) mod phi
   void* defaults = nullptr;   // default state of each generator, 11 x 2560 bytes
 };
 constexpr size_t kDefaultStride = 2560;
 // exponent of the MT19937 digit tables: the block-splitting block 2^432
 constexpr int kMtDigitE = 432;
+// whole-block MT19937 jumps for batched sections of 624 2^kMtBlkFirst outputs
+// (tasks up to 2^40 outputs: section numbers below 2^22)
+constexpr int kMtBlkFirst = 10;
+constexpr int kMtBlkPolys = 22;
 
 // Order a wavefront's LDS writes before its later LDS reads (and reads before
 // later writes) when the LDS block is private to the wavefront: LDS

@@ -451,7 +451,8 @@ int enqueue_iteration(prand_server* s, Lane& L, IterSlot& sl, bool* launched) {
     if (r->issued == r->r.n) sl.finishing.push_back(r);
   }
   BatchPlan& plan = s->plan;
-  int rc = batch_plan(s->tasks.data(), (uint32_t)s->tasks.size(), s->bcfg, plan);
+  // MT19937 requests are sectioned at admission; their chunks stay whole
+  int rc = batch_plan(s->tasks.data(), (uint32_t)s->tasks.size(), s->bcfg, plan, UINT64_MAX);
   if (rc) return rc;
   hipError_t e = grow_slot(s, sl, (uint32_t)s->tasks.size(), (uint32_t)plan.tiles.size(), plan.scratch_bytes);
   if (e != hipSuccess) return hipfail(s->ctx, e);

@@ -82,6 +82,52 @@ SUBSETS = {
 }
 
 
+def mt_state_at(oracle, seed, kind):
+    """A seeded MT19937 state at a chosen place in its 624-word block:
+    block used up (624), 300 or 1 words used, or a renewed block with none
+    used (index 0: the oracle's state after 624 outputs, index reset)."""
+    st = oracle.seed(P.MT19937, seed)
+    if kind == "mid":
+        oracle.generate(P.MT19937, st, 300)
+    elif kind == "one":
+        oracle.generate(P.MT19937, st, 1)
+    elif kind == "zero":
+        oracle.generate(P.MT19937, st, 624)
+        st.view(np.uint32)[624] = 0
+    return st
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_batch_long_mt_sections(ctx, oracle, graph):
+    """MT19937 tasks longer than 2^24 outputs are cut into sections of
+    624 * 2^10 outputs, each started by a whole-block jump of the task state
+    that keeps its place in the block; outputs and final states (bit for bit)
+    equal the oracle's sequential ones, whatever the start index."""
+    L, T = 624 << 10, 1 << 24
+    specs = [("aligned", P.U32, T + 1), ("mid", P.F32, T + 3 * L - 5), ("one", P.U32, T + 2 * L),
+             ("zero", P.F64, T + 2 * L + 1877), ("zero", P.U32, T + 624), ("mid", P.U32, T)]
+    tasks, refs = [], []
+    for k, (kind, dt, n) in enumerate(specs):
+        st = mt_state_at(oracle, 4000 + k, kind)
+        sin = torch.from_numpy(st.copy()).cuda()
+        sout = torch.full_like(sin, 0xA5)
+        out = torch.empty(n, dtype=TDT[dt], device="cuda")
+        ref_state = st.copy()
+        ref = oracle.generate(P.MT19937, ref_state, n, dt)
+        tasks.append((P.MT19937, dt, n, sin, sout, out))
+        refs.append((ref, ref_state, st))
+    b = P.Batch(ctx, tasks, P.BatchConfig(4, 2048, 4096, graph))
+    assert b.tiles() == sum((n + L - 1) // L if n > T else 1 for _, _, n in specs)
+    for _ in range(2):
+        for (_, _, _, _, sout, out) in tasks:
+            out.zero_()
+            sout.fill_(0x5A)
+        b.launch()
+        torch.cuda.synchronize()
+        check(tasks, refs)
+    b.close()
+
+
 @pytest.mark.parametrize("graph", [1, 0])
 @pytest.mark.parametrize("subset", sorted(SUBSETS))
 def test_batch_family_subsets(ctx, oracle, subset, graph):
