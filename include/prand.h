@@ -196,7 +196,10 @@ typedef struct prand_batch prand_batch;
 /* Plan a batch (tasks are read on the host; the device pointers they hold
    must stay valid while the batch is launched).  cfg NULL: defaults.  The
    batch owns a device scratch area for the section start states (about 1.5 KB
-   per tile). */
+   per tile).  MT19937 tasks longer than 2^24 outputs are run as sections of
+   624 * 2^10 outputs, whose start states come from whole-block jumps of the
+   task state; a batch with such a task makes the context build its MT19937
+   jump tables first, if no earlier call has (a few seconds, once). */
 int prand_batch_create(prand_ctx* ctx, const prand_task* h_tasks, uint32_t ntasks, const prand_batch_config* cfg,
                        prand_batch** batch);
 /* Enqueue the batch on `stream` (a hipStream_t, NULL = default stream); the
