@@ -170,9 +170,9 @@ int prand_generate_streams(prand_ctx* ctx, int gen, void* d_states, uint32_t cou
  * dtypes in one launch, replayed from a HIP graph.  Each task is cut into
  * sections that jump to their first output (the sectioning of "Multi-threaded
  * generation"), grouped into per-wavefront tiles; a first kernel computes
- * every section's start state, then one kernel per generator family
- * (MT19937; MRG32K3A/LFSR113; GM/GQ) generates, the families running
- * concurrently.
+ * every section's start state, then the generation kernels (MT19937 together
+ * with the v = 1 GM/GQ ensembles; MRG32K3A/LFSR113; the other GM/GQ shapes)
+ * run concurrently.
  * ------------------------------------------------------------------------ */
 typedef struct prand_task {
   int32_t gen;           /* enum prand_gen */
