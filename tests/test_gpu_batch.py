@@ -105,7 +105,8 @@ def test_batch_long_mt_sections(ctx, oracle, graph):
     equal the oracle's sequential ones, whatever the start index."""
     L, T = 624 << 10, 1 << 24
     specs = [("aligned", P.U32, T + 1), ("mid", P.F32, T + 3 * L - 5), ("one", P.U32, T + 2 * L),
-             ("zero", P.F64, T + 2 * L + 1877), ("zero", P.U32, T + 624), ("mid", P.U32, T)]
+             ("zero", P.F64, T + 2 * L + 1877), ("zero", P.U32, T + 624), ("mid", P.U32, T),
+             ("one", P.U32, 27 * L)]   # a whole number of sections
     tasks, refs = [], []
     for k, (kind, dt, n) in enumerate(specs):
         st = mt_state_at(oracle, 4000 + k, kind)
