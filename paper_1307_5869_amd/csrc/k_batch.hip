@@ -11,17 +11,20 @@
 //  - batch_starts_kernel jumps every MRG32K3A/LFSR113/GM/GQ section to its
 //    start and writes the state to the batch's scratch area (the jump code
 //    needs many registers, so it runs apart from the generation loops);
+//    sections of MT19937 tasks above 2^24 outputs get theirs from
+//    mt_section_start_kernel (k_mt19937.hip);
 //  - batch_reg_kernel, batch_gm_kernel<shape> (lane-per-section v = 4
-//    ensembles, GQ58.3) and batch_mt_v1_kernel (MT19937 tasks, then the
-//    32-lane v = 1 ensembles) generate, one wavefront per tile, from those
-//    states (or, for MT19937, from the task state) with the same wavefront
-//    routines as the one-generator kernels, and at their register counts.
+//    ensembles, GQ58.3) and batch_mt_v1_kernel (MT19937 tasks and sections,
+//    then the 32-lane v = 1 ensembles) generate, one wavefront per tile, from
+//    those states (or, for a whole MT19937 task, from the task state) with
+//    the same wavefront routines as the one-generator kernels, and at their
+//    register counts.
 // The generation kernels are independent of each other; tiles within each
 // are ordered longest first, so the dispatcher starts the long ones early.
-// MT19937 tasks run whole on one wavefront (the longest take tens of ms), so
-// they share a launch with the largest family, whose tiles fill the chip
-// around them: that overlap does not depend on how concurrent kernels are
-// spread over hardware queues.
+// A whole MT19937 task runs on one wavefront (up to 2^24 outputs, some tens
+// of ms), so MT19937 shares a launch with the largest family, whose tiles
+// fill the chip around it: that overlap does not depend on how concurrent
+// kernels are spread over hardware queues.
 #include "dev_gm.h"
 #include "dev_gmlane.h"
 #include "dev_lfsr.h"
