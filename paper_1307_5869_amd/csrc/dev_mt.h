@@ -10,10 +10,15 @@ constexpr uint32_t kUpper = 0x80000000u;
 constexpr uint32_t kLower = 0x7FFFFFFFu;
 constexpr uint32_t kMatA = 0x9908B0DFu;
 
+// y ^ ((y << k) & mask) as one three-input op (gfx950 v_bitop3_b32; truth
+// table 0x78 = src0 ^ (src1 & src2))
+__device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t m) {
+  return __builtin_amdgcn_bitop3_b32(a, b, m, 0x78);
+}
 __device__ __forceinline__ uint32_t temper(uint32_t y) {
   y ^= y >> 11;
-  y ^= (y << 7) & 0x9D2C5680u;
-  y ^= (y << 15) & 0xEFC60000u;
+  y = xor_and(y, y << 7, 0x9D2C5680u);
+  y = xor_and(y, y << 15, 0xEFC60000u);
   return y ^ (y >> 18);
 }
 // x_{j+624} from x_j (upper bit), x_{j+1} (lower bits), x_{j+397}
