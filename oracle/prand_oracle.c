@@ -27,11 +27,15 @@
  *    launch shapes (32, 8 or 12 elements), digit = floor(2^v x / g), digits
  *    packed element 0 first, most significant bit first, into consecutive
  *    32-bit words (GQ58.3: 36 bits per step, 9 words per 8 steps);
- *  - seeds: SplitMix64 expansion where a seed is not used verbatim;
+ *  - seeds: SplitMix64 expansion where a seed is not used verbatim (below);
  *  - block-splitting block lengths L are powers of two no smaller than the
  *    sequence lengths of the paper's stream table.
- * Parity unpinned: the GM/GQ digit packing and the GM/GQ seed expansion (the
- * paper gives neither; only internal consistency can be checked).
+ *  - seed expansion: SplitMix64 draws from a start state that is the first
+ *    SplitMix64 output of seed ^ (increment * (generator + 1)); pinned by its
+ *    tests against an independent implementation of the SplitMix64 output
+ *    function and the closed form of its increment.
+ * Parity unpinned: the GM/GQ digit packing (the paper does not give it; only
+ * internal consistency can be checked).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -124,6 +128,15 @@ static uint64_t splitmix64(uint64_t* s) {
   return z ^ (z >> 31);
 }
 static uint64_t seed_tag(int gen) { return 0x9E3779B97F4A7C15ULL * (uint64_t)(gen + 1); }
+/* start state of a seed's expansion: the first SplitMix64 output from
+   seed ^ tag(gen).  (Starting at seed ^ tag(gen) itself would put the start
+   states of different generators on the Weyl sequence the draws walk along,
+   since the tags are multiples of its increment: for most seeds the draws of
+   one generator would be those of another shifted by a few places.) */
+static uint64_t seed_start(uint64_t seed, int gen) {
+  uint64_t t = seed ^ seed_tag(gen);
+  return splitmix64(&t);
+}
 /* uniform in [0, bound), bound >= 2: top bits of a draw, rejected when >= bound */
 static uint64_t draw_below(uint64_t* s, uint64_t bound) {
   int nb = 64 - __builtin_clzll(bound - 1);
@@ -220,7 +233,7 @@ static void mrg_seed(or_mrg* s, uint64_t seed) {
     for (int i = 0; i < 3; i++) { s->x[i] = (uint32_t)seed; s->y[i] = (uint32_t)seed; }
     return;
   }
-  uint64_t sm = seed ^ seed_tag(OR_MRG32K3A);
+  uint64_t sm = seed_start(seed, OR_MRG32K3A);
   do { for (int i = 0; i < 3; i++) s->x[i] = (uint32_t)draw_below(&sm, MRG_M1); }
   while (!s->x[0] && !s->x[1] && !s->x[2]);
   do { for (int i = 0; i < 3; i++) s->y[i] = (uint32_t)draw_below(&sm, MRG_M2); }
@@ -287,7 +300,7 @@ static void lfsr_seed(or_lfsr* st, uint64_t seed) {
     for (int c = 0; c < 4; c++) st->z[c] = (uint32_t)seed;
     return;
   }
-  uint64_t sm = seed ^ seed_tag(OR_LFSR113);
+  uint64_t sm = seed_start(seed, OR_LFSR113);
   for (int c = 0; c < 4; c++) {
     uint32_t topmask = 0xFFFFFFFFu << (32 - LF_P[c]);
     do st->z[c] = (uint32_t)(splitmix64(&sm) >> 32); while (!(st->z[c] & topmask));
@@ -613,7 +626,7 @@ static void gm_skip(int gen, or_gm* st, const big* Nwords) {
 static void gm_seed(int gen, or_gm* st, uint64_t seed) {
   const gm_par* P = gm_par_of(gen);
   memset(st, 0, sizeof *st);
-  uint64_t sm = seed ^ seed_tag(gen);
+  uint64_t sm = seed_start(seed, gen);
   for (int i = 0; i < P->s; i++) {
     do {
       st->xp[i] = draw_below(&sm, P->g);

@@ -3,8 +3,11 @@
 //            two 32-bit halves (Matsumoto-Nishimura reference seeding).
 //   MRG32K3A: all six words = seed when 1 <= seed < m2; LFSR113: all four
 //            words = seed when 128 <= seed < 2^32.
-//   Otherwise, and for every GM/GQ element, SplitMix64 draws from
-//   seed ^ (0x9E3779B97F4A7C15 * (gen + 1)): the top bits of a draw, rejected
+//   Otherwise, and for every GM/GQ element, SplitMix64 draws from a start
+//   state that is the first SplitMix64 output from
+//   seed ^ (0x9E3779B97F4A7C15 * (gen + 1)) (the tags are multiples of the
+//   Weyl increment, so starting at seed ^ tag itself would make the draws of
+//   one generator those of another shifted by a few): the top bits of a draw, rejected
 //   until below the bound; an MRG triple or a GM element pair that is zero
 //   (mod p) is drawn again; an LFSR word is redrawn until its top p bits are
 //   not all zero.
@@ -18,6 +21,10 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t& s) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t seed_start(uint64_t seed, int gen) {
+  uint64_t t = seed ^ (0x9E3779B97F4A7C15ull * (uint64_t)(gen + 1));
+  return splitmix64(t);
 }
 __device__ __forceinline__ uint64_t draw_below(uint64_t& s, uint64_t bound) {
   const int nb = 64 - __clzll((long long)(bound - 1));
@@ -61,7 +68,7 @@ __device__ void seed_mrg(MrgState* st, uint64_t seed) {
     for (int i = 0; i < 3; i++) { st->x[i] = (uint32_t)seed; st->y[i] = (uint32_t)seed; }
     return;
   }
-  uint64_t sm = seed ^ (0x9E3779B97F4A7C15ull * (PRAND_MRG32K3A + 1));
+  uint64_t sm = seed_start(seed, PRAND_MRG32K3A);
   uint32_t x[3], y[3];
   do { for (int i = 0; i < 3; i++) x[i] = (uint32_t)draw_below(sm, kMrgM1); } while (!(x[0] | x[1] | x[2]));
   do { for (int i = 0; i < 3; i++) y[i] = (uint32_t)draw_below(sm, kMrgM2); } while (!(y[0] | y[1] | y[2]));
@@ -74,7 +81,7 @@ __device__ void seed_lfsr(LfsrState* st, uint64_t seed) {
     return;
   }
   const int p[4] = {31, 29, 28, 25};
-  uint64_t sm = seed ^ (0x9E3779B97F4A7C15ull * (PRAND_LFSR113 + 1));
+  uint64_t sm = seed_start(seed, PRAND_LFSR113);
   for (int c = 0; c < 4; c++) {
     const uint32_t top = 0xFFFFFFFFu << (32 - p[c]);
     uint32_t z;
@@ -86,7 +93,7 @@ __device__ void seed_lfsr(LfsrState* st, uint64_t seed) {
 __device__ void seed_gm(int gen, GmState* st, uint64_t seed) {
   const GmParams& P = kGmParams[gen - PRAND_GM19];
   const uint64_t g = P.p << P.t;
-  uint64_t sm = seed ^ (0x9E3779B97F4A7C15ull * (uint64_t)(gen + 1));
+  uint64_t sm = seed_start(seed, gen);
   for (int i = 0; i < 32; i++) {
     uint64_t a = 0, b = 0;
     if (i < P.s) {

@@ -4,8 +4,9 @@ of (k_n, q_n)) and rec3 of the section on jumping ahead for GM/GQ generators,
 brute force, periods of Table 2, tiny-modulus variants by brute force, and the
 2-adic collapse of the composite moduli.
 
-Parity unpinned: the digit packing and the seed expansion (the paper gives
-neither); the tests below only check them for internal consistency."""
+Parity unpinned: the digit packing (the paper does not give it); the tests
+below only check it for internal consistency.  The seed expansion is pinned in
+test_oracle_seed.py."""
 import os
 
 import numpy as np
