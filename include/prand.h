@@ -103,7 +103,10 @@ int prand_ctx_create(prand_ctx** ctx, int hip_device);
 /* Free the context's device tables (rng_free_device_consts_).  NULL is OK. */
 int prand_ctx_destroy(prand_ctx* ctx);
 
-/* Size in bytes of the state blob of `gen`; 0 for an invalid generator. */
+/* Size in bytes of the state blob of `gen` (the paper's rng_state, section
+   "Function call interface": one structure per generator holding all of its
+   internal state, copied between host and device memory as is); 0 for an
+   invalid generator. */
 size_t prand_state_bytes(int gen);
 
 /* Block-splitting block length: stream `id` starts id * L outputs into the
@@ -124,10 +127,14 @@ int prand_init_default(prand_ctx* ctx, int gen, void* h_state);
    init_by_array over the two 32-bit halves.  MRG32K3A: all six words = seed
    when 1 <= seed < m2.  LFSR113: all four words = seed when
    128 <= seed < 2^32.  Otherwise (and for GM/GQ, per element) SplitMix64
-   draws reduced by rejection.  Blocks. */
+   draws reduced by rejection, from a start state that is the first SplitMix64
+   output of seed ^ (0x9E3779B97F4A7C15 * (gen + 1)).  Blocks. */
 int prand_seed(prand_ctx* ctx, int gen, uint64_t seed, void* h_state);
 
-/* count states from count seeds, on the device. */
+/* count states from count seeds, on the device: the seeded form of
+   rng_init_, which the paper provides in device code too (section
+   "Function call interface", "Initialization").  d_seeds: count uint64;
+   d_states: count state blobs, written.  Asynchronous on `stream`. */
 int prand_seed_dev(prand_ctx* ctx, int gen, const uint64_t* d_seeds, uint32_t count,
                    void* d_states, void* stream);
 
@@ -136,9 +143,12 @@ int prand_seed_dev(prand_ctx* ctx, int gen, const uint64_t* d_seeds, uint32_t co
    <= 8.  Runs on the device; blocks. */
 int prand_skipahead(prand_ctx* ctx, int gen, void* h_state, const uint64_t* h_dist, int nlimbs);
 
-/* Jump count device states ahead.  d_dist holds nlimbs limbs per stream
-   (count * nlimbs uint64, stream-major) when per_stream != 0, else one
-   distance of nlimbs limbs shared by all streams. */
+/* Jump count device states ahead (rng_skipahead_ in device code, section
+   "Function call interface", "Jumping ahead"; the jump methods of section
+   "Parallel streams of pseudorandom numbers").  d_dist holds nlimbs limbs per
+   stream (count * nlimbs uint64, stream-major) when per_stream != 0, else one
+   distance of nlimbs limbs shared by all streams; 0 <= nlimbs <= 8.  States
+   are updated in place.  Asynchronous on `stream`. */
 int prand_skipahead_dev(prand_ctx* ctx, int gen, void* d_states, uint32_t count,
                         const uint64_t* d_dist, int nlimbs, int per_stream, void* stream);
 
@@ -160,8 +170,13 @@ int prand_init_streams_dev(prand_ctx* ctx, int gen, int variant, const void* d_b
 int prand_generate(prand_ctx* ctx, int gen, void* h_state, int dtype, void* d_out, uint64_t n,
                    void* stream);
 
-/* Many independent streams: d_out[s * n_per_stream + i] = output i of
-   stream s, for s < count; each d_states[s] is advanced by n_per_stream. */
+/* Many independent streams (section "Multi-threaded generation of
+   pseudorandom numbers with GPGPU" applied to one state per stream, as in
+   the paper's use of block splitting to give every thread block its own
+   stream): d_out[s * n_per_stream + i] = output i of stream s, for s < count;
+   each d_states[s] is advanced by n_per_stream in place.  PRAND_ERANGE when
+   n_per_stream > 2^40 or the output exceeds 2^50 bytes.  Asynchronous on
+   `stream`. */
 int prand_generate_streams(prand_ctx* ctx, int gen, void* d_states, uint32_t count,
                            uint64_t n_per_stream, int dtype, void* d_out, void* stream);
 
@@ -203,7 +218,7 @@ typedef struct prand_batch prand_batch;
 int prand_batch_create(prand_ctx* ctx, const prand_task* h_tasks, uint32_t ntasks, const prand_batch_config* cfg,
                        prand_batch** batch);
 /* Enqueue the batch on `stream` (a hipStream_t, NULL = default stream); the
-   work forks onto two private streams and joins back into `stream`.
+   work forks onto three private streams and joins back into `stream`.
    Launches of the same batch must not overlap each other. */
 int prand_batch_launch(prand_batch* batch, void* stream);
 /* Number of tiles (wavefront work items) the plan holds. */

@@ -85,6 +85,10 @@ bool is_reg(int g) { return g == PRAND_MRG32K3A || g == PRAND_LFSR113; }
 
 namespace prand {
 
+// tasks of up to 2^40 outputs (checked below) never need a whole-block ladder
+// entry beyond the table
+static_assert(((1ull << 40) - 1) / kMtSection < (1ull << kMtBlkPolys), "MT19937 block ladder too short");
+
 void batch_fill_defaults(prand_batch_config& c) { fill_defaults(c); }
 
 int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_config& cfg, BatchPlan& plan,
@@ -119,6 +123,9 @@ int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_confi
         b.nsec = 1;
         work[4].push_back({c * (double)n, b});
       } else {
+        // a section's start applies the whole-block ladder entry of every set
+        // bit of its number: the numbers must stay below 2^kMtBlkPolys
+        if ((n - 1) / sec >= (1ull << kMtBlkPolys)) return PRAND_ERANGE;
         b.kind = kTileMtSection;
         b.seclen = sec;
         b.nsec = 1;

@@ -323,3 +323,15 @@ bool mt_build_block_polys(int nladder, int first, int nblk, uint32_t* blk, uint3
 }
 
 }  // namespace prand
+
+// Host check of the whole-block jump table (not part of the public ABI; the
+// test suite compares it with the oracle's x^N mod phi on the CPU): writes
+// entry i of the table built for sections of 624 * 2^first outputs, i.e.
+// x^(624 * 2^(first + i)) mod phi, and x^(-1) mod phi.  Returns 0, or -1.
+extern "C" int prand_internal_mt_block_poly(int first, int i, uint32_t* out624, uint32_t* inv624) {
+  if (first < 0 || i < 0 || first + i > 480 || !out624 || !inv624) return -1;
+  std::vector<uint32_t> blk((size_t)(i + 1) * prand::kMtPolyWords);
+  if (!prand::mt_build_block_polys(first + i + 10, first, i + 1, blk.data(), inv624)) return -1;
+  for (int w = 0; w < prand::kMtPolyWords; w++) out624[w] = blk[(size_t)i * prand::kMtPolyWords + w];
+  return 0;
+}

@@ -92,3 +92,20 @@ def test_context_needs_gfx950(lib):
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert lib.load().prand_ctx_create(ctypes.byref(h), 0) == lib.ENODEV
+
+
+def test_mt_block_ladder_top_entry_matches_oracle(lib, oracle):
+    """The whole-block jump table of batched MT19937 sections (sections of
+    624 * 2^10 outputs, 22 entries): its last entry, used by sections whose
+    number has bit 21 set, equals the oracle's x^(624 * 2^31) mod phi, and
+    the table's x^(-1) times x is 1 mod phi.  Host code only."""
+    so = ctypes.CDLL(lib.LIB_PATH)
+    f = so.prand_internal_mt_block_poly
+    f.restype = ctypes.c_int
+    out, inv = (ctypes.c_uint32 * 624)(), (ctypes.c_uint32 * 624)()
+    assert f(10, 21, out, inv) == 0
+    as_int = lambda a: sum(int(a[w]) << (32 * w) for w in range(624))
+    assert as_int(out) == oracle.mt_jump_poly(624 << 31)
+    assert oracle.mt_reduce(as_int(inv) << 1, bitwise=False) == 1
+    assert f(10, 3, out, inv) == 0
+    assert as_int(out) == oracle.mt_jump_poly(624 << 13)
