@@ -65,6 +65,8 @@ class Oracle:
             "or_mt_reduce_bitwise": (i32, [p64]),
             "or_mt_reduce_words": (i32, [p64]),
             "or_mt_frobenius": (i32, [i32, p64]),
+            "or_mt_poly_mulmod": (i32, [p64, p64, p64]),
+            "or_mt_apply_poly": (i32, [vp, p64]),
             "or_mat3_pow": (i32, [p64, u64, p64, i32, p64]),
             "or_gm_generic_step": (i32, [u64, u64, u64, p64, p64]),
             "or_gm_generic_jump": (i32, [u64, u64, u64, p64, i32, p64, p64]),
@@ -153,6 +155,20 @@ class Oracle:
         buf = (ctypes.c_uint64 * self.PW)()
         self._check(self.lib.or_mt_frobenius(n, buf), "mt_frobenius")
         return sum(int(buf[i]) << (64 * i) for i in range(self.PW))
+
+    def _poly_words(self, poly):
+        return (ctypes.c_uint64 * self.PW)(*[(poly >> (64 * i)) & 0xFFFFFFFFFFFFFFFF for i in range(self.PW)])
+
+    def mt_poly_mulmod(self, a, b):
+        """a * b mod phi for reduced polynomials given as ints."""
+        out = (ctypes.c_uint64 * self.PW)()
+        self._check(self.lib.or_mt_poly_mulmod(self._poly_words(a), self._poly_words(b), out), "mt_poly_mulmod")
+        return sum(int(out[i]) << (64 * i) for i in range(self.PW))
+
+    def mt_apply_poly(self, st, g):
+        """g(A) applied in place to an MT19937 state at a block boundary."""
+        self._check(self.lib.or_mt_apply_poly(self._ptr(st), self._poly_words(g)), "mt_apply_poly")
+        return st
 
     def mt_reduce(self, poly, bitwise):
         nw = 2 * self.PW + 2

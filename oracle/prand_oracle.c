@@ -477,6 +477,42 @@ static int mt_jump_poly(const big* N, uint64_t* g) {
   }
   return OR_OK;
 }
+/* g(A) applied to a state at a block boundary (index 624): with seq the raw
+   words continued from its window, g(A) Y = sum over the set coefficients i
+   of the window starting i words later (equation g_v); the oldest word keeps
+   only its top bit (no later output depends on the others). */
+static int mt_apply_window(or_mt* st, const uint64_t* g) {
+  const int len = MT_DEG - 1 + MT_N;
+  uint32_t* seq = (uint32_t*)malloc((size_t)len * 4);
+  if (!seq) return OR_ENOMEM;
+  for (int j = 0; j < MT_N; j++) seq[j] = st->mt[j];
+  for (int j = MT_N; j < len; j++) seq[j] = mt_recur(seq[j - MT_N], seq[j - MT_N + 1], seq[j - MT_N + MT_M]);
+  uint32_t res[MT_N];
+  memset(res, 0, sizeof res);
+  for (int i = 0; i < MT_DEG; i++)
+    if (pbit(g, i))
+      for (int t = 0; t < MT_N; t++) res[t] ^= seq[i + t];
+  memcpy(st->mt, res, sizeof res);
+  st->mt[0] &= 0x80000000u;
+  st->mti = MT_N;
+  free(seq);
+  return OR_OK;
+}
+/* r = a * b mod phi: the carry-less schoolbook product, then reduction */
+static void poly_mulmod(uint64_t* r, const uint64_t* a, const uint64_t* b) {
+  uint64_t t[2 * PW + 2];
+  memset(t, 0, sizeof t);
+  for (int i = 0; i < MT_DEG; i++) {
+    if (!pbit(a, i)) continue;
+    int q = i >> 6, sh = i & 63;
+    for (int w = 0; w < PW; w++) {
+      t[w + q] ^= b[w] << sh;
+      if (sh) t[w + q + 1] ^= b[w] >> (64 - sh);
+    }
+  }
+  poly_reduce_fast(t);
+  memcpy(r, t, PW * 8);
+}
 /* A^N applied to the state; states in the middle of a block first consume
    the rest of the block, so that the polynomial acts on a window of 624
    consecutive raw words whose next output is the tempered successor word.
@@ -491,23 +527,11 @@ static int mt_skip(or_mt* st, const big* Nin) {
   big_sub_small(&N, rest);
   st->mti = MT_N;
   uint64_t* g = (uint64_t*)malloc(PW * 8);
-  const int len = MT_DEG - 1 + MT_N;
-  uint32_t* seq = (uint32_t*)malloc((size_t)len * 4);
-  if (!g || !seq) { free(g); free(seq); return OR_ENOMEM; }
+  if (!g) return OR_ENOMEM;
   int rc = mt_jump_poly(&N, g);
-  if (rc) { free(g); free(seq); return rc; }
-  for (int j = 0; j < MT_N; j++) seq[j] = st->mt[j];
-  for (int j = MT_N; j < len; j++) seq[j] = mt_recur(seq[j - MT_N], seq[j - MT_N + 1], seq[j - MT_N + MT_M]);
-  uint32_t res[MT_N];
-  memset(res, 0, sizeof res);
-  for (int i = 0; i < MT_DEG; i++)
-    if (pbit(g, i))
-      for (int t = 0; t < MT_N; t++) res[t] ^= seq[i + t];
-  memcpy(st->mt, res, sizeof res);
-  st->mt[0] &= 0x80000000u;
-  st->mti = MT_N;
-  free(g); free(seq);
-  return OR_OK;
+  if (!rc) rc = mt_apply_window(st, g);
+  free(g);
+  return rc;
 }
 
 /* ======================================================================== */
@@ -839,6 +863,19 @@ uint32_t or_lfsr_comp_jump(uint32_t z, int p, int q, int s, const uint64_t* limb
   big N;
   if (big_load(&N, limbs, nlimbs)) return 0;
   return lfsr_comp_jump(z, p, q, s, &N);
+}
+/* a * b mod phi (reduced inputs: degree < 19937) */
+int or_mt_poly_mulmod(const uint64_t* a, const uint64_t* b, uint64_t* out /* PW words each */) {
+  int rc = mt_need_phi();
+  if (rc) return rc;
+  poly_mulmod(out, a, b);
+  return OR_OK;
+}
+/* g(A) applied to an MT19937 state at a block boundary (index 624) */
+int or_mt_apply_poly(void* st, const uint64_t* g /* PW words, reduced */) {
+  or_mt* m = (or_mt*)st;
+  if (m->mti != MT_N) return OR_EINVAL;
+  return mt_apply_window(m, g);
 }
 /* x^(2^n) mod phi by n squarings (for an irreducibility pin) */
 int or_mt_frobenius(int n, uint64_t* out /* PW words */) {

@@ -1,6 +1,7 @@
 """Parity at the workloads' full sizes, in the launch configurations the
-benchmark times, on sampled outputs that the oracle computes directly (head
-and tail windows of long streams through the oracle's own skip-ahead)."""
+benchmark times, on sampled outputs that the oracle computes directly (whole
+rows of sampled streams; head and tail windows of long streams through the
+oracle's own skip-ahead).  Oracle references are computed on host threads."""
 import time
 
 import numpy as np
@@ -9,6 +10,7 @@ import torch
 
 from paper_1307_5869_amd import prand as P
 from paper_1307_5869_amd import workloads as W
+from refpool import MtLadder, StreamStarts, pmap
 
 pytestmark = pytest.mark.gpu
 
@@ -28,39 +30,71 @@ def ids_tensor(ids):
     return torch.from_numpy(np.ascontiguousarray(ids, dtype=np.uint64).view(np.int64)).cuda()
 
 
+def c2_sample(S, gen):
+    """First and last 64 streams and a random 1 % of the others."""
+    rng = np.random.default_rng(1000 + gen)
+    mid = np.sort(rng.choice(np.arange(64, S - 64), size=S // 100, replace=False))
+    return np.concatenate([np.arange(64), mid, np.arange(S - 64, S)])
+
+
 @pytest.mark.parametrize("gen", range(11))
 def test_many_streams_full_size(ctx, oracle, gen):
-    """65536 block-split streams (ids uniform in [0, 1e19)) x 16384 u32
-    words, one init and one generation launch: sampled rows and states."""
+    """65536 block-split streams (ids uniform in [0, 1e19)) x 16384 words,
+    one init and one generation launch per dtype, as the benchmark times
+    them: the first and last 64 streams and a random 1 % of the rest, whole
+    rows in u32, f32 and f64, start and final states."""
     S, N = 65536, 16384
     sb = P.state_bytes(gen)
     ids = W.stream_ids(S, gen)
+    sample = c2_sample(S, gen)
+    starts = StreamStarts(oracle, gen)
+
+    def ref(s):
+        st0 = starts(ids[s])
+        rows = {}
+        for dt in (P.U32, P.F32, P.F64):
+            o = st0.copy()
+            rows[dt] = oracle.generate(gen, o, N, dt)
+        return st0, rows, o
+
+    refs = pmap(ref, sample)
     states = torch.empty(S * sb, dtype=torch.uint8, device="cuda")
     ctx.init_streams_dev(gen, P.SEQ_DEFAULT, None, ids_tensor(ids), S, states)
     init = states.clone()
-    out = torch.empty(S * N, dtype=torch.int32, device="cuda")
-    ctx.generate_streams(gen, states, S, N, P.U32, out)
-    torch.cuda.synchronize()
-    sample = [0, 1, 4097, S - 1] + list(np.random.default_rng(gen).integers(0, S, size=2))
-    rows = out.view(S, N)[torch.tensor(sample, device="cuda")].cpu().numpy().view(np.uint32)
-    st_all = states.view(S, sb)[torch.tensor(sample, device="cuda")].cpu().numpy()
-    in_all = init.view(S, sb)[torch.tensor(sample, device="cuda")].cpu().numpy()
+    idx = torch.from_numpy(sample).cuda()
+    got_init = init.view(S, sb)[idx].cpu().numpy()
     for j, s in enumerate(sample):
-        ost = oracle.init_stream(gen, 0, int(ids[s]))
-        assert np.array_equal(in_all[j], ost), f"{P.NAMES[gen]} init stream {s}"
-        ref = oracle.generate(gen, ost, N, P.U32)
-        np.testing.assert_array_equal(rows[j], ref, err_msg=f"{P.NAMES[gen]} stream {s}")
-        assert np.array_equal(st_all[j], ost), f"{P.NAMES[gen]} final state {s}"
-    del out, states, init
+        assert np.array_equal(got_init[j], refs[j][0]), f"{P.NAMES[gen]} init stream {s}"
+    big = torch.empty(S * N * 2, dtype=torch.int32, device="cuda")
+    for dt in (P.U32, P.F32, P.F64):
+        states.copy_(init)
+        out = big if dt == P.F64 else big[:S * N]
+        ctx.generate_streams(gen, states, S, N, dt, out)
+        torch.cuda.synchronize()
+        es = 8 if dt == P.F64 else 4
+        rows = out.view(torch.uint8).view(S, N * es)[idx].cpu().numpy().view(NPDT[dt])
+        st_all = states.view(S, sb)[idx].cpu().numpy()
+        for j, s in enumerate(sample):
+            np.testing.assert_array_equal(rows[j], refs[j][1][dt], err_msg=f"{P.NAMES[gen]} dtype {dt} stream {s}")
+            assert np.array_equal(st_all[j], refs[j][2]), f"{P.NAMES[gen]} final state {s}"
+    del big, states, init
     torch.cuda.empty_cache()
+
+
+def c3_sample(S, gen):
+    rng = np.random.default_rng(2000 + gen)
+    mid = np.sort(rng.choice(np.arange(64, S - 64), size=S // 100, replace=False))
+    return np.concatenate([np.arange(64), mid, np.arange(S - 64, S)])
 
 
 @pytest.mark.parametrize("gen", range(11))
 def test_jump_2pow_k_full_size(ctx, oracle, gen):
     """2^20 streams per generator jumped by 2^k, k uniform in the generator's
-    range: sampled states against the oracle; on a 1024-stream subset with
-    distances n <= 2^16, the jumped stream's next outputs equal generating
-    past n outputs of the original."""
+    range: the first and last 64 states and a random 1 % of the others
+    against the oracle's jump; then 1024 streams with distances n <= 2^16:
+    every jumped stream's next 16 outputs equal outputs n .. n + 15 of the
+    original, and (except MT19937, whose jumped window is a canonical form)
+    every jumped state equals the oracle's."""
     S = 1 << 20
     sb = P.state_bytes(gen)
     base = oracle.seed(gen, 4242 + gen)
@@ -69,25 +103,35 @@ def test_jump_2pow_k_full_size(ctx, oracle, gen):
     limbs = np.zeros((S, 8), dtype=np.uint64)
     limbs[np.arange(S), ks // 64] = np.left_shift(np.uint64(1), (ks % 64).astype(np.uint64))
     ctx.skipahead_dev(gen, states, S, torch.from_numpy(limbs.reshape(-1).view(np.int64)).cuda(), 8, True)
+    sample = c3_sample(S, gen)
+    kset = sorted(set(int(ks[s]) for s in sample))
+    if gen == P.MT19937:
+        lad = MtLadder(oracle, 0, max(kset) + 1)
+        jumped = dict(zip(kset, pmap(lambda k: oracle.mt_apply_poly(base.copy(), lad.lad[k]), kset)))
+        assert np.array_equal(jumped[kset[0]], oracle.skipahead(gen, base.copy(), 1 << kset[0]))
+    else:
+        jumped = dict(zip(kset, pmap(lambda k: oracle.skipahead(gen, base.copy(), 1 << k), kset)))
     torch.cuda.synchronize()
-    sample = [0, S - 1] + [int(x) for x in np.random.default_rng(100 + gen).integers(0, S, size=4)]
-    got = states.view(S, sb)[torch.tensor(sample, device="cuda")].cpu().numpy()
+    got = states.view(S, sb)[torch.from_numpy(sample).cuda()].cpu().numpy()
     for j, s in enumerate(sample):
-        ref = oracle.skipahead(gen, base.copy(), 1 << int(ks[s]))
-        assert np.array_equal(got[j], ref), f"{P.NAMES[gen]} stream {s} k {int(ks[s])}"
+        assert np.array_equal(got[j], jumped[int(ks[s])]), f"{P.NAMES[gen]} stream {s} k {int(ks[s])}"
     del states
-    # small distances: jump == generation, compared through the next outputs
+    # small distances: jump == generation
     n = W.small_jumps(1024, gen)
     sub = torch.from_numpy(base.copy()).cuda().repeat(1024)
     ctx.skipahead_dev(gen, sub, 1024, torch.from_numpy(n.astype(np.uint64).view(np.int64)).cuda(), 1, True)
     nxt = torch.empty(1024 * 16, dtype=torch.int32, device="cuda")
+    sub_states = sub.view(1024, sb).cpu().numpy()
     ctx.generate_streams(gen, sub, 1024, 16, P.U32, nxt)
     torch.cuda.synchronize()
     nxt = nxt.cpu().numpy().view(np.uint32).reshape(1024, 16)
-    for s in range(0, 1024, 97):
-        o = base.copy()
-        oracle.generate(gen, o, int(n[s]))
-        np.testing.assert_array_equal(nxt[s], oracle.generate(gen, o, 16), err_msg=f"{P.NAMES[gen]} n {int(n[s])}")
+    seq = oracle.generate(gen, base.copy(), int(n.max()) + 16)
+    for s in range(1024):
+        np.testing.assert_array_equal(nxt[s], seq[int(n[s]):int(n[s]) + 16], err_msg=f"{P.NAMES[gen]} n {int(n[s])}")
+    if gen != P.MT19937:
+        refs = pmap(lambda d: oracle.skipahead(gen, base.copy(), int(d)), n)
+        for s in range(1024):
+            assert np.array_equal(sub_states[s], refs[s]), f"{P.NAMES[gen]} state n {int(n[s])}"
     torch.cuda.empty_cache()
 
 

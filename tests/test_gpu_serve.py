@@ -81,7 +81,7 @@ def test_serve_alone_equals_mix(ctx):
     # small iterations: most requests span several loop iterations
     cfg = P.ServerConfig(hbm_budget=1 << 30, iter_numbers=1 << 20, min_chunk=1 << 12, mt_chunk=1 << 13)
     srv = P.Server(ctx, cfg)
-    reqs = mixed_requests(300, seed=21)
+    reqs = mixed_requests(500, seed=21)
     tickets = {}
     for k, (g, sid, n, dt) in enumerate(reqs):
         tickets[srv.submit(g, sid, n, dt, tag=k)] = k
