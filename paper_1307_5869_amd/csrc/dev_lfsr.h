@@ -14,8 +14,13 @@ namespace prand {
 namespace lfsr {
 
 
+// The two halves occupy disjoint bits (the masked part from bit 32 - k + s
+// up, the feedback below it), so they join with an OR, and the mask is
+// applied after the shift: one three-input op (v_bitop3_b32, truth table
+// 0xEA = (src0 & src1) | src2) joins them, five VALU operations per
+// component (the compiler's own form of the masked shift takes six).
 __device__ __forceinline__ uint32_t comp(uint32_t z, uint32_t mask, int q, int sh1, int s) {
-  return ((z & mask) << s) ^ (((z << q) ^ z) >> sh1);
+  return __builtin_amdgcn_bitop3_b32(z << s, mask << s, ((z << q) ^ z) >> sh1, 0xEA);
 }
 
 struct LfsrRegs {
@@ -27,7 +32,7 @@ __device__ __forceinline__ uint32_t step(LfsrRegs& r) {
   r.z1 = comp(r.z1, 0xFFFFFFF8u, 2, 27, 2);
   r.z2 = comp(r.z2, 0xFFFFFFF0u, 13, 21, 7);
   r.z3 = comp(r.z3, 0xFFFFFF80u, 3, 12, 13);
-  return r.z0 ^ r.z1 ^ r.z2 ^ r.z3;
+  return __builtin_amdgcn_bitop3_b32(r.z0, r.z1, r.z2, 0x96) ^ r.z3;   // 0x96: three-input XOR
 }
 
 __device__ __forceinline__ uint32_t f2_apply(const uint32_t* __restrict__ cols, uint32_t v) {
