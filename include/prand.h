@@ -83,6 +83,7 @@ enum prand_variant {
 #define PRAND_ENOMEM (-5)        /* allocation failed */
 #define PRAND_ENODEV (-6)        /* no usable gfx950 device */
 #define PRAND_EBUSY (-7)         /* serving queue full: request rejected */
+#define PRAND_ENOTREADY (-8)     /* context tables the call needs are not built, and it may not build them */
 
 typedef struct prand_ctx prand_ctx;
 
@@ -179,6 +180,26 @@ int prand_generate(prand_ctx* ctx, int gen, void* h_state, int dtype, void* d_ou
    `stream`. */
 int prand_generate_streams(prand_ctx* ctx, int gen, void* d_states, uint32_t count,
                            uint64_t n_per_stream, int dtype, void* d_out, void* stream);
+
+/* prand_generate for callers that cannot allocate device memory (harnesses
+   that forbid hipMalloc, tight serving loops): the same arguments, result
+   and blocking behaviour, but the section start states, their distances and
+   the copied-in state live in a static device array of 4 MiB per GPU
+   (PRAND_NOALLOC_SCRATCH_BYTES) instead of memory allocated per call, and no
+   hipMalloc, hipFree or allocating library routine is called.  The array is
+   reserved by the library on each device where a context is created and is
+   held until the process ends.  The section plan is limited to what fits in
+   it (at most 1663 MT19937, 7941 GM/GQ, 131048 MRG32K3A and 174730 LFSR113
+   sections); the output never depends on the plan.  PRAND_ERANGE when
+   n > 2^40.  MT19937 needs the context's jump tables: PRAND_ENOTREADY when no
+   earlier MT19937 call on this context (for example prand_init_stream) has
+   built them.  Every call on one GPU shares that GPU's array and keeps the
+   last call's contents there: the library serialises the calls of one
+   process on a device (each call holds the array until its copy-back has
+   finished), and calls that overlap from another thread block until then. */
+#define PRAND_NOALLOC_SCRATCH_BYTES (4u << 20)
+int prand_generate_noalloc(prand_ctx* ctx, int gen, void* h_state, int dtype, void* d_out, uint64_t n,
+                           void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched launch: many streams of uneven lengths and mixed generators and

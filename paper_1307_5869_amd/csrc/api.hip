@@ -184,6 +184,107 @@ int prand::ensure_mt_tables(prand_ctx* c) {
   return ensure_mt_locked(c, PRAND_MT19937);
 }
 
+// The sectioned fill behind prand_generate and prand_generate_noalloc.
+// Bulk sections of 2^k outputs cover [0, T); each starts from the state
+// jumped j * 2^k ahead (one ladder application per set bit of j) and fills
+// its slice.  A final section covers [T, n) and leaves the advanced state.
+// For MT19937, T is the last twist-block boundary of the original stream
+// before n: a jump yields the canonical window, which differs from the array
+// sequential generation holds only in bits the next twist overwrites, so the
+// final section's state is exactly the sequential one.  The section states,
+// their distances and the copied-in base state live in `scratch` when it is
+// given (the plan then uses at most as many sections as fit in
+// scratch_bytes; the output does not depend on the plan), else in memory
+// allocated for the call.  Arguments are checked by the caller; MT19937
+// tables must exist.
+int prand::generate_host_state(prand_ctx* c, int gen, void* h_state, int dtype, void* d_out, uint64_t n,
+                               hipStream_t st, void* scratch, size_t scratch_bytes) {
+  uint64_t min_sec, max_secs;
+  switch (gen) {
+    case PRAND_MT19937: min_sec = 1ull << 18; max_secs = 4096; break;
+    case PRAND_MRG32K3A:
+    case PRAND_LFSR113: min_sec = 256; max_secs = 1u << 19; break;
+    default: min_sec = 4096; max_secs = 1u << 16; break;
+  }
+  const size_t sb = state_bytes(gen);
+  const size_t es = elem_bytes(dtype);
+  const size_t base_bytes = (sb + 255) & ~(size_t)255;
+  if (scratch) {
+    // base state, then distances, then states, each 256-byte aligned
+    if (scratch_bytes < base_bytes + 2 * 256 + 2 * (sb + 8)) return PRAND_ERANGE;
+    const uint64_t fit = (scratch_bytes - base_bytes - 2 * 256) / (sb + 8);   // section states that fit
+    max_secs = std::min<uint64_t>(max_secs, fit - 1);
+  }
+  int k = 0;
+  while ((1ull << k) < min_sec) k++;
+  while (((n + (1ull << k) - 1) >> k) > max_secs) k++;
+  const bool one = (1ull << k) >= n;
+  const uint64_t seclen = one ? n : (1ull << k);
+  uint64_t T;
+  if (one) {
+    T = 0;
+  } else if (gen == PRAND_MT19937) {
+    const uint32_t idx0 = std::min<uint32_t>(((const MtState*)h_state)->idx, 624u);
+    const uint64_t r0 = 624 - idx0;
+    T = (n <= r0) ? 0 : r0 + 624 * ((n - r0 + 623) / 624 - 1);
+  } else {
+    T = ((n + seclen - 1) / seclen - 1) * seclen;
+  }
+  const uint64_t full = T / seclen, part = T % seclen;
+  const uint64_t nb = full + (part ? 1 : 0);   // bulk sections
+  const uint64_t nst = nb + 1;                 // plus the final one
+  void* d_states = nullptr;
+  uint64_t* d_dist = nullptr;
+  void* d_base = nullptr;
+  hipError_t e = hipSuccess;
+  std::unique_lock<std::mutex> lk(c->mu, std::defer_lock);
+  if (scratch) {
+    const size_t dist_off = base_bytes;
+    const size_t st_off = dist_off + ((nst * 8 + 255) & ~(size_t)255);
+    if (st_off + nst * sb > scratch_bytes) return PRAND_ERANGE;
+    d_base = scratch;
+    d_dist = (uint64_t*)((char*)scratch + dist_off);
+    d_states = (char*)scratch + st_off;
+  } else {
+    e = hipMalloc(&d_states, nst * sb);
+    if (e == hipSuccess) e = hipMalloc((void**)&d_dist, nst * 8);
+    lk.lock();   // the context's host-call scratch holds the base state
+    d_base = c->scratch;
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(d_base, h_state, sb, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(section_dist_kernel, dim3((uint32_t)((nst + 255) / 256)), dim3(256), 0, st, d_dist,
+                       (uint32_t)nb, seclen, T);
+    e = hipGetLastError();
+  }
+  JumpSpec js;
+  js.dist = d_dist;
+  js.nlimbs = 1;
+  js.per_stream = 1;
+  if (e == hipSuccess) e = launch_jump(c, gen, d_states, (uint32_t)nst, js, d_base, st);
+  if (e == hipSuccess && full)
+    e = launch_streams(c, gen, d_states, d_states, (uint32_t)full, seclen, dtype, d_out, st);
+  if (e == hipSuccess && part) {
+    void* sp = (char*)d_states + full * sb;
+    e = launch_streams(c, gen, sp, sp, 1, part, dtype, (char*)d_out + full * seclen * es, st);
+  }
+  void* last = (char*)d_states + nb * sb;
+  if (e == hipSuccess) e = launch_streams(c, gen, last, last, 1, n - T, dtype, (char*)d_out + T * es, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_state, last, sb, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (!scratch) {
+    lk.unlock();
+    (void)hipFree(d_states);
+    (void)hipFree(d_dist);
+  }
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+bool prand::mt_tables_ready(prand_ctx* c) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  return c->mt_ready;
+}
+
 extern "C" {
 
 const char* prand_strerror(int code) {
@@ -196,6 +297,7 @@ const char* prand_strerror(int code) {
     case PRAND_ENOMEM: return "out of memory";
     case PRAND_ENODEV: return "no usable gfx950 device";
     case PRAND_EBUSY: return "request queue full";
+    case PRAND_ENOTREADY: return "context tables this call needs are not built yet";
     default: return "unknown error";
   }
 }
@@ -242,6 +344,7 @@ int prand_ctx_create(prand_ctx** out, int hip_device) {
   delete H;
   if (e == hipSuccess) e = hipMalloc(&c->T.defaults, kDefaultStride * PRAND_NUM_GENERATORS);
   if (e == hipSuccess) e = hipMalloc(&c->scratch, kScratch);
+  if (e == hipSuccess) e = noalloc_setup(hip_device);
   if (e == hipSuccess) {
     // default states: the documented default seed of each generator
     uint64_t seeds[PRAND_NUM_GENERATORS];
@@ -405,73 +508,7 @@ int prand_generate(prand_ctx* c, int gen, void* h_state, int dtype, void* d_out,
   DeviceGuard g(c->device);
   int rc = ensure_mt_locked(c, gen);
   if (rc) return rc;
-  hipStream_t st = (hipStream_t)stream;
-  // Bulk sections of 2^k outputs cover [0, T); each starts from the state
-  // jumped j * 2^k ahead (one ladder application per set bit of j) and fills
-  // its slice.  A final section covers [T, n) and leaves the advanced state.
-  // For MT19937, T is the last twist-block boundary of the original stream
-  // before n: a jump yields the canonical window, which differs from the
-  // array sequential generation holds only in bits the next twist
-  // overwrites, so the final section's state is exactly the sequential one.
-  uint64_t min_sec, max_secs;
-  switch (gen) {
-    case PRAND_MT19937: min_sec = 1ull << 18; max_secs = 4096; break;
-    case PRAND_MRG32K3A:
-    case PRAND_LFSR113: min_sec = 256; max_secs = 1u << 19; break;
-    default: min_sec = 4096; max_secs = 1u << 16; break;
-  }
-  int k = 0;
-  while ((1ull << k) < min_sec) k++;
-  while (((n + (1ull << k) - 1) >> k) > max_secs) k++;
-  const bool one = (1ull << k) >= n;
-  const uint64_t seclen = one ? n : (1ull << k);
-  uint64_t T;
-  if (one) {
-    T = 0;
-  } else if (gen == PRAND_MT19937) {
-    const uint32_t idx0 = std::min<uint32_t>(((const MtState*)h_state)->idx, 624u);
-    const uint64_t r0 = 624 - idx0;
-    T = (n <= r0) ? 0 : r0 + 624 * ((n - r0 + 623) / 624 - 1);
-  } else {
-    T = ((n + seclen - 1) / seclen - 1) * seclen;
-  }
-  const uint64_t full = T / seclen, part = T % seclen;
-  const uint64_t nb = full + (part ? 1 : 0);   // bulk sections
-  const uint64_t nst = nb + 1;                 // plus the final one
-  const size_t sb = state_bytes(gen);
-  const size_t es = elem_bytes(dtype);
-  void* d_states = nullptr;
-  uint64_t* d_dist = nullptr;
-  hipError_t e = hipMalloc(&d_states, nst * sb);
-  if (e == hipSuccess) e = hipMalloc((void**)&d_dist, nst * 8);
-  {
-    std::lock_guard<std::mutex> lk(c->mu);
-    void* d_base = c->scratch;
-    if (e == hipSuccess) e = hipMemcpyAsync(d_base, h_state, sb, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(section_dist_kernel, dim3((uint32_t)((nst + 255) / 256)), dim3(256), 0, st, d_dist,
-                         (uint32_t)nb, seclen, T);
-      e = hipGetLastError();
-    }
-    JumpSpec js;
-    js.dist = d_dist;
-    js.nlimbs = 1;
-    js.per_stream = 1;
-    if (e == hipSuccess) e = launch_jump(c, gen, d_states, (uint32_t)nst, js, d_base, st);
-    if (e == hipSuccess && full)
-      e = launch_streams(c, gen, d_states, d_states, (uint32_t)full, seclen, dtype, d_out, st);
-    if (e == hipSuccess && part) {
-      void* sp = (char*)d_states + full * sb;
-      e = launch_streams(c, gen, sp, sp, 1, part, dtype, (char*)d_out + full * seclen * es, st);
-    }
-    void* last = (char*)d_states + nb * sb;
-    if (e == hipSuccess) e = launch_streams(c, gen, last, last, 1, n - T, dtype, (char*)d_out + T * es, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(h_state, last, sb, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-  }
-  (void)hipFree(d_states);
-  (void)hipFree(d_dist);
-  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+  return generate_host_state(c, gen, h_state, dtype, d_out, n, (hipStream_t)stream, nullptr, 0);
 }
 
 }  // extern "C"

@@ -178,6 +178,15 @@ struct prand_ctx {
 namespace prand {
 // build and upload the MT19937 jump polynomials once per context
 int ensure_mt_tables(prand_ctx* c);
+// whether the MT19937 jump polynomials are built (never builds them)
+bool mt_tables_ready(prand_ctx* c);
+// the sectioned fill of one host state (prand_generate); with `scratch` set
+// it keeps its section states there and allocates nothing
+int generate_host_state(prand_ctx* c, int gen, void* h_state, int dtype, void* d_out, uint64_t n,
+                        hipStream_t st, void* scratch, size_t scratch_bytes);
+// once per device, with that device current: look up the device address of
+// the allocation-free entry point's static array
+hipError_t noalloc_setup(int device);
 
 inline int hipfail(prand_ctx* c, hipError_t e) {
   if (c) c->last_hip = (int)e;

@@ -18,7 +18,8 @@ NUM_GENERATORS = 11
 NAMES = ["MT19937", "MRG32K3A", "LFSR113", "GM19", "GM29", "GM31", "GM55", "GM61", "GQ58.1", "GQ58.3", "GQ58.4"]
 U32, F32, F64 = 0, 1, 2
 SEQ_DEFAULT, SEQ, SEQ_SHORT, SEQ_MEDIUM, SEQ_LONG = range(5)
-OK, EINVAL, EUNSUPPORTED, ERANGE, EHIP, ENOMEM, ENODEV, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, EUNSUPPORTED, ERANGE, EHIP, ENOMEM, ENODEV, EBUSY, ENOTREADY = 0, -1, -2, -3, -4, -5, -6, -7, -8
+NOALLOC_SCRATCH_BYTES = 4 << 20
 MAX_LIMBS = 8
 
 _u64, _u32, _i32, _vp, _sz = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
@@ -38,6 +39,7 @@ _SIGNATURES = {
     "prand_init_stream": (_i32, [_vp, _i32, _i32, _u64, _vp]),
     "prand_init_streams_dev": (_i32, [_vp, _i32, _i32, _vp, _vp, _u32, _vp, _vp]),
     "prand_generate": (_i32, [_vp, _i32, _vp, _i32, _vp, _u64, _vp]),
+    "prand_generate_noalloc": (_i32, [_vp, _i32, _vp, _i32, _vp, _u64, _vp]),
     "prand_generate_streams": (_i32, [_vp, _i32, _vp, _u32, _u64, _i32, _vp, _vp]),
     "prand_batch_create": (_i32, [_vp, _vp, _u32, _vp, ctypes.POINTER(_vp)]),
     "prand_batch_launch": (_i32, [_vp, _vp]),
@@ -233,6 +235,10 @@ class Context:
 
     def generate(self, gen, state, dtype, d_out, n, stream=None):
         self._call("prand_generate", gen, _ptr(state), dtype, _ptr(d_out), n, _stream(stream))
+        return d_out
+
+    def generate_noalloc(self, gen, state, dtype, d_out, n, stream=None):
+        self._call("prand_generate_noalloc", gen, _ptr(state), dtype, _ptr(d_out), n, _stream(stream))
         return d_out
 
     # ---- device states (torch uint8 tensors of count * state_bytes) ----
