@@ -72,6 +72,31 @@ def build(verbose=False):
     return LIB
 
 
+# test-side user kernels built on include/prand_device.h (not part of the
+# library): tests/devapi/*.hip -> tests/devapi/lib<name>.so
+TEST_KERNELS = os.path.join(ROOT, "tests", "devapi")
+
+
+def build_test_kernels(verbose=False):
+    built = []
+    for f in sorted(os.listdir(TEST_KERNELS)):
+        if not f.endswith(".hip"):
+            continue
+        src = os.path.join(TEST_KERNELS, f)
+        lib = os.path.join(TEST_KERNELS, "lib" + f[:-4] + ".so")
+        tmp = lib + ".tmp"
+        cmd = [HIPCC] + FLAGS + ["-shared", "-x", "hip", src, "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, lib)
+        built.append(lib)
+        if verbose:
+            print("built", lib)
+    return built
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    build_test_kernels(verbose=True)
     sys.exit(0)
