@@ -40,8 +40,9 @@ __device__ __forceinline__ void put(void* out, uint64_t i, uint32_t w) {
 // earlier phase, so a piece issues all its loads before any of its stores:
 // one LDS latency per K slices of 64 words instead of one per slice (a lone
 // wavefront, as in batched and served MT19937 tasks, is bound by that
-// latency).
-template <int DT, int K>
+// latency).  kOut: renewed words below `want` are also tempered and stored
+// at out[pos + j] straight from registers.
+template <int DT, int K, bool kOut = true>
 __device__ __forceinline__ void twist_phase(uint32_t* mt, int j0, int j1, int off, int want, uint64_t pos, void* out) {
   const int lane = threadIdx.x & 63;
   uint32_t a[K], b[K], c[K];
@@ -64,20 +65,59 @@ __device__ __forceinline__ void twist_phase(uint32_t* mt, int j0, int j1, int of
     if (j < j1) {
       const uint32_t v = recur(a[k], b[k], c[k]);
       mt[j] = v;
-      if (j < want) put<DT>(out, pos + j, temper(v));
+      if (kOut && j < want) put<DT>(out, pos + j, temper(v));
+    }
+  }
+}
+
+// A whole renewed block written out as 16-byte pieces: lane l tempers the
+// words 4q .. 4q + 3 for q = l, l + 64, l + 128 (q < 156) and stores them at
+// out + 16 q (u32/f32) or out + 32 q (f64, two pieces).  `out` is 16-byte
+// aligned; mt is 16-byte aligned LDS.
+template <int DT>
+__device__ __forceinline__ void write_block(const uint32_t* mt, char* out) {
+  const int lane = threadIdx.x & 63;
+  uint4 w[3];
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    const int q = lane + 64 * r;
+    if (q < 156) w[r] = *(const uint4*)(mt + 4 * q);
+  }
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    const int q = lane + 64 * r;
+    if (q >= 156) continue;
+    const uint32_t t0 = temper(w[r].x), t1 = temper(w[r].y), t2 = temper(w[r].z), t3 = temper(w[r].w);
+    if (DT == PRAND_U32) {
+      *(uint4*)(out + 16 * q) = make_uint4(t0, t1, t2, t3);
+    } else if (DT == PRAND_F32) {
+      *(uint4*)(out + 16 * q) = make_uint4(__float_as_uint((float)(t0 >> 8) * 0x1p-24f),
+                                           __float_as_uint((float)(t1 >> 8) * 0x1p-24f),
+                                           __float_as_uint((float)(t2 >> 8) * 0x1p-24f),
+                                           __float_as_uint((float)(t3 >> 8) * 0x1p-24f));
+    } else {
+      const double d0 = (double)t0 * 0x1p-32, d1 = (double)t1 * 0x1p-32;
+      const double d2 = (double)t2 * 0x1p-32, d3 = (double)t3 * 0x1p-32;
+      *(double2*)(out + 32 * q) = make_double2(d0, d1);
+      *(double2*)(out + 32 * q + 16) = make_double2(d2, d3);
     }
   }
 }
 
 // One wavefront generates n outputs of one stream: state *in (copied into
-// the LDS block mt[624]), outputs at out, advanced state to *sout (may be
-// the same object as *in).  A twist renews the block in three dependency
-// phases (words 0..226 read old words 397..623; 227..453 read words renewed
-// in phase one; 454..623 read phase two and word 0), each parallel across the
-// lanes; renewed words are tempered and stored straight from registers.  The
-// LDS block is private to the wavefront (wavefront-level ordering only).
+// the LDS block mt[624], 16-byte aligned), outputs at out, advanced state to
+// *sout (may be the same object as *in).  A twist renews the block in three
+// dependency phases (words 0..226 read old words 397..623; 227..453 read
+// words renewed in phase one; 454..623 read phase two and word 0), each
+// parallel across the lanes.  A whole block whose outputs start 16-byte
+// aligned is twisted first (one piece per phase) and then tempered and
+// written out from LDS as 16-byte pieces (one vector store per four words
+// instead of four); a partial block tempers and stores renewed words
+// straight from registers.  The LDS block is private to the wavefront
+// (wavefront-level ordering only).
 template <int DT>
 __device__ __forceinline__ void gen_wave(uint32_t* mt, const MtState* in, MtState* sout, uint64_t n, void* out) {
+  constexpr int es = (DT == PRAND_F64) ? 8 : 4;
   const int lane = threadIdx.x & 63;
   for (int i = lane; i < 624; i += 64) mt[i] = in->mt[i];
   uint32_t idx = in->idx < 624u ? in->idx : 624u;   // an index past the block means "block used up"
@@ -87,22 +127,33 @@ __device__ __forceinline__ void gen_wave(uint32_t* mt, const MtState* in, MtStat
   for (uint32_t i = lane; i < first; i += 64) put<DT>(out, i, temper(mt[idx + i]));
   uint64_t pos = first;
   idx += (uint32_t)first;
+  // every later block starts 624 * es bytes (a multiple of 16) further on
+  const bool vec = (((uintptr_t)out + pos * es) & 15) == 0;
   while (pos < n) {
     const uint64_t left = n - pos;
     const int want = left < 624 ? (int)left : 624;
-    // phases in pieces of two 64-word slices: the loads of four slices at
-    // once measured the same for a lone wavefront but took 60 instead of 56
-    // VGPRs in the batch kernel that shares this code with the v = 1 GM/GQ
-    // tiles, which upset the balance of the batch's concurrent kernels
-    // (95.8 -> 102.9 ms per launch)
-    twist_phase<DT, 2>(mt, 0, 128, 397, want, pos, out);
-    twist_phase<DT, 2>(mt, 128, 227, 397, want, pos, out);
-    wave_lds_sync();
-    twist_phase<DT, 2>(mt, 227, 355, -227, want, pos, out);
-    twist_phase<DT, 2>(mt, 355, 454, -227, want, pos, out);
-    wave_lds_sync();
-    twist_phase<DT, 2>(mt, 454, 582, -227, want, pos, out);
-    twist_phase<DT, 1>(mt, 582, 624, -227, want, pos, out);
+    if (vec && want == 624) {
+      twist_phase<DT, 4, false>(mt, 0, 227, 397, 0, 0, nullptr);
+      wave_lds_sync();
+      twist_phase<DT, 4, false>(mt, 227, 454, -227, 0, 0, nullptr);
+      wave_lds_sync();
+      twist_phase<DT, 3, false>(mt, 454, 624, -227, 0, 0, nullptr);
+      wave_lds_sync();
+      write_block<DT>(mt, (char*)out + pos * es);
+    } else {
+      // phases in pieces of two 64-word slices: the loads of four slices at
+      // once measured the same for a lone wavefront but took 60 instead of 56
+      // VGPRs in the batch kernel that shares this code with the v = 1 GM/GQ
+      // tiles, which upset the balance of the batch's concurrent kernels
+      twist_phase<DT, 2>(mt, 0, 128, 397, want, pos, out);
+      twist_phase<DT, 2>(mt, 128, 227, 397, want, pos, out);
+      wave_lds_sync();
+      twist_phase<DT, 2>(mt, 227, 355, -227, want, pos, out);
+      twist_phase<DT, 2>(mt, 355, 454, -227, want, pos, out);
+      wave_lds_sync();
+      twist_phase<DT, 2>(mt, 454, 582, -227, want, pos, out);
+      twist_phase<DT, 1>(mt, 582, 624, -227, want, pos, out);
+    }
     wave_lds_sync();
     pos += want;
     idx = want;

@@ -36,7 +36,7 @@ using namespace mt;
 template <int DT>
 __global__ void __launch_bounds__(64) mt_generate_kernel(MtState* states, uint32_t count, uint64_t n,
                                                          void* __restrict__ out) {
-  __shared__ uint32_t mt[624];
+  __shared__ __align__(16) uint32_t mt[624];
   const uint32_t s = blockIdx.x;
   if (s >= count) return;
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
