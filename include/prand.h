@@ -206,9 +206,11 @@ int prand_generate_noalloc(prand_ctx* ctx, int gen, void* h_state, int dtype, vo
  * dtypes in one launch, replayed from a HIP graph.  Each task is cut into
  * sections that jump to their first output (the sectioning of "Multi-threaded
  * generation"), grouped into per-wavefront tiles; a first kernel computes
- * every section's start state, then the generation kernels (MT19937 together
- * with the v = 1 GM/GQ ensembles; MRG32K3A/LFSR113; the other GM/GQ shapes)
- * run concurrently.
+ * every section's start state, then two persistent kernels (one per register
+ * class: the lane-per-section GM55/GQ58.3/GQ58.4 tiles, then all others),
+ * each as many wavefronts as the chip holds, work through their tile lists
+ * longest first, every wavefront taking the next tile from a device
+ * counter.
  * ------------------------------------------------------------------------ */
 typedef struct prand_task {
   int32_t gen;           /* enum prand_gen */
@@ -221,10 +223,12 @@ typedef struct prand_task {
 } prand_task;
 
 typedef struct prand_batch_config {
-  uint32_t waves_per_block; /* tiles (wavefronts) per workgroup: 1, 2 or 4 (0: 4) */
+  uint32_t waves_per_block; /* wavefronts per workgroup: 1, 2 or 4 (0: 4) */
   uint32_t reg_section;    /* MRG32K3A/LFSR113 outputs per lane section, multiple of 32 (0: 2048) */
   uint32_t gm_section;     /* GM/GQ outputs per element-group section (0: 4096) */
   uint32_t use_graph;      /* 1: capture the launch in a HIP graph and replay it */
+  uint32_t lds_chunk_words; /* LDS staging of MRG32K3A/LFSR113 lanes, 16 or 32 words (0: 32):
+                               5 or 9 KB per wavefront of the light kernel */
 } prand_batch_config;
 
 typedef struct prand_batch prand_batch;
@@ -238,9 +242,10 @@ typedef struct prand_batch prand_batch;
    jump tables first, if no earlier call has (a few seconds, once). */
 int prand_batch_create(prand_ctx* ctx, const prand_task* h_tasks, uint32_t ntasks, const prand_batch_config* cfg,
                        prand_batch** batch);
-/* Enqueue the batch on `stream` (a hipStream_t, NULL = default stream); the
-   work forks onto three private streams and joins back into `stream`.
-   Launches of the same batch must not overlap each other. */
+/* Enqueue the batch on `stream` (a hipStream_t, NULL = default stream), as
+   one graph launch when use_graph is set, else as its kernels.  Launches of
+   the same batch must not overlap each other (they share the batch's tile
+   counters and scratch). */
 int prand_batch_launch(prand_batch* batch, void* stream);
 /* Number of tiles (wavefront work items) the plan holds. */
 int prand_batch_tiles(const prand_batch* batch, uint32_t* ntiles);

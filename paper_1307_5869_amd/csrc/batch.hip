@@ -2,16 +2,16 @@
 //
 // The planner cuts each task into sections that jump to their first output
 // and groups them into per-wavefront tiles (see k_batch.hip), family by
-// family, each family sorted longest first so that the dispatcher starts the
-// long tiles early and the short ones fill the end.  Every MRG32K3A/LFSR113
-// and GM/GQ tile gets a slot in the batch's scratch area for its sections'
-// start states.  The launch is captured once in a HIP graph on a private
-// stream: the section-start kernel, then MT19937 together with the v = 1
-// GM/GQ tiles on the main branch and the other GM/GQ shapes and
-// MRG32K3A/LFSR113 on branches of their own; it is replayed on the caller's
-// stream.  The autotuner times a
-// small grid of (wavefronts per workgroup, MRG32K3A/LFSR113 lane section,
-// GM/GQ group section) on the actual task mix.
+// family.  Every MRG32K3A/LFSR113 and GM/GQ tile gets a slot in the batch's
+// scratch area for its sections' start states.  The tiles of each register
+// class (light: MRG32K3A/LFSR113, v = 1 GM/GQ, MT19937, copies; heavy: the
+// lane-per-section GM/GQ shapes) form one list, longest first by estimated
+// wavefront time, which the class's persistent kernel works through.  The
+// launch -- counter reset, section starts, heavy list, light list, all on
+// one stream -- is captured once in a HIP graph on a private stream and
+// replayed on the caller's stream.  The autotuner times a small grid of
+// (MRG32K3A/LFSR113 lane section, GM/GQ group section, LDS chunk width of
+// the light kernel) on the actual task mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,8 +35,11 @@ struct prand_batch {
   BatchCounts n;
   BatchTask* d_tasks = nullptr;
   char* d_scratch = nullptr;
-  hipStream_t cap = nullptr, side[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  uint32_t* d_order = nullptr;      // light list, then heavy list
+  uint32_t* d_counters = nullptr;   // kBatchCounters tile counters
+  uint32_t n_light = 0, n_heavy = 0;
+  uint32_t blocks_light = 0, blocks_heavy = 0;
+  hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -74,6 +77,7 @@ void fill_defaults(prand_batch_config& c) {
   if (!c.waves_per_block) c.waves_per_block = 4;
   if (!c.reg_section) c.reg_section = 2048;
   if (!c.gm_section) c.gm_section = 4096;
+  c.lds_chunk_words = c.lds_chunk_words == 16 ? 16 : 32;
   c.waves_per_block = c.waves_per_block >= 4 ? 4 : (c.waves_per_block >= 2 ? 2 : 1);
   c.reg_section = (uint32_t)std::max<uint64_t>(32, round_up(c.reg_section, 32));
   c.gm_section = std::max<uint32_t>(32, c.gm_section);
@@ -191,14 +195,16 @@ int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_confi
   }
   size_t total = 0;
   for (auto& w : work) total += w.size();
-  if (total > 0xFFFFFFF0ull) return PRAND_ERANGE;
+  if (total > (1ull << 31)) return PRAND_ERANGE;   // tile counters stay far from wrapping
   plan.tiles.resize(total);
   plan.scratch_bytes = 0;
   plan.n.mtsec = 0;
+  std::vector<std::pair<double, uint32_t>> light, heavy;
   size_t at = 0;
   for (int f = 0; f < kBatchFamilies; f++) {
     std::stable_sort(work[f].begin(), work[f].end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     for (auto& w : work[f]) {
+      (f == 2 || f == 3 ? heavy : light).push_back({w.first, (uint32_t)at});
       BatchTile& tl = plan.tiles[at++];
       tl = w.second;
       if (f <= 3 || tl.kind == kTileMtSection) {
@@ -214,6 +220,13 @@ int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_confi
       }
     }
   }
+  // each class's list longest first (ties: family order, then placement)
+  for (auto* v : {&light, &heavy})
+    std::stable_sort(v->begin(), v->end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  plan.order_light.resize(light.size());
+  plan.order_heavy.resize(heavy.size());
+  for (size_t i = 0; i < light.size(); i++) plan.order_light[i] = light[i].second;
+  for (size_t i = 0; i < heavy.size(); i++) plan.order_heavy[i] = heavy[i].second;
   plan.n.reg = (uint32_t)work[0].size();
   plan.n.g32 = (uint32_t)work[1].size();
   plan.n.g8 = (uint32_t)work[2].size();
@@ -231,45 +244,33 @@ void free_batch(prand_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (hipEvent_t e : b->ev)
-    if (e) (void)hipEventDestroy(e);
-  for (hipStream_t s : b->side)
-    if (s) (void)hipStreamDestroy(s);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   (void)hipFree(b->d_tiles);
   (void)hipFree(b->d_tasks);
   (void)hipFree(b->d_scratch);
+  (void)hipFree(b->d_order);
+  (void)hipFree(b->d_counters);
   delete b;
 }
 
-// The batch's kernels on stream a, forked onto side streams 1..3 and joined
-// back: a runs the section starts (and the MT19937 section starts, when a
-// task is long enough to have sections), then MT19937 with the v = 1
-// ensembles in one launch (the MT19937 tasks are single wavefronts, some tens of ms long,
-// and overlap the largest family inside that launch whatever hardware queues
-// the branches get); side 1 the v = 4 lane sections, side 2 GQ58.3, side 3
-// MRG32K3A/LFSR113.  side[0] is not used.
-hipError_t enqueue_forked(prand_batch* b, hipStream_t a) {
+// The batch's kernels on stream a: tile counters cleared, section starts
+// (and the MT19937 section starts, when a task is long enough to have
+// sections), then the heavy and the light persistent kernels.
+hipError_t enqueue_persistent(prand_batch* b, hipStream_t a) {
   const DeviceTables& T = b->ctx->T;
   const uint32_t w = b->cfg.waves_per_block;
+  const int cw = (int)b->cfg.lds_chunk_words;
   const BatchCounts& n = b->n;
-  const BatchTile* reg = b->d_tiles;
-  const BatchTile* g32 = reg + n.reg;
-  const BatchTile* g8 = g32 + n.g32;
-  const BatchTile* g3 = g8 + n.g8;
-  const BatchTile* mt = g3 + n.g3;
-  hipError_t e = launch_batch_starts(T, reg, n.with_starts(), b->d_tasks, b->d_scratch, w, a);
-  if (e == hipSuccess) e = hipEventRecord(b->ev[1], a);
+  const BatchTile* mt = b->d_tiles + n.reg + n.g32 + n.g8 + n.g3;
+  hipError_t e = launch_batch_reset(b->d_counters, a);
+  if (e == hipSuccess) e = launch_batch_starts(T, b->d_tiles, n.with_starts(), b->d_tasks, b->d_scratch, w, a);
   if (e == hipSuccess && n.mtsec) e = launch_batch_mt_starts(T, mt, n.mt, b->d_tasks, b->d_scratch, a);
-  if (e == hipSuccess) e = launch_batch_mt_v1(mt, n.mt + n.copy, g32, n.g32, b->d_tasks, b->d_scratch, w, a);
-  for (int i = 1; i < 4 && e == hipSuccess; i++) e = hipStreamWaitEvent(b->side[i], b->ev[1], 0);
-  if (e == hipSuccess) e = launch_batch_gm(1, g8, n.g8, b->d_tasks, b->d_scratch, w, b->side[1]);
-  if (e == hipSuccess) e = launch_batch_gm(2, g3, n.g3, b->d_tasks, b->d_scratch, w, b->side[2]);
-  if (e == hipSuccess) e = launch_batch_reg(reg, n.reg, b->d_tasks, b->d_scratch, w, b->side[3]);
-  for (int i = 1; i < 4 && e == hipSuccess; i++) {
-    e = hipEventRecord(b->ev[2 + i], b->side[i]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(a, b->ev[2 + i], 0);
-  }
+  if (e == hipSuccess)
+    e = launch_batch_persistent(1, cw, b->d_tiles, b->d_order + b->n_light, b->n_heavy, b->d_tasks, b->d_scratch,
+                                b->d_counters + 1, w, b->blocks_heavy, a);
+  if (e == hipSuccess)
+    e = launch_batch_persistent(0, cw, b->d_tiles, b->d_order, b->n_light, b->d_tasks, b->d_scratch, b->d_counters,
+                                w, b->blocks_light, a);
   return e;
 }
 
@@ -302,12 +303,13 @@ bool cache_lookup(const std::string& key, prand_batch_config* cfg) {
     char* tab = std::strchr(line, '\t');
     if (!tab) continue;
     *tab = 0;
-    unsigned w, r, g;
-    if (key == line && std::sscanf(tab + 1, "%u %u %u", &w, &r, &g) == 3) {
+    unsigned w, r, g, cw;
+    if (key == line && std::sscanf(tab + 1, "%u %u %u %u", &w, &r, &g, &cw) == 4) {
       cfg->waves_per_block = w;
       cfg->reg_section = r;
       cfg->gm_section = g;
       cfg->use_graph = 1;
+      cfg->lds_chunk_words = cw;
       found = true;   // the last entry for a key wins
     }
   }
@@ -320,7 +322,8 @@ void cache_store(const std::string& key, const prand_batch_config& cfg) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s\t%u %u %u\n", key.c_str(), cfg.waves_per_block, cfg.reg_section, cfg.gm_section);
+  std::fprintf(f, "%s\t%u %u %u %u\n", key.c_str(), cfg.waves_per_block, cfg.reg_section, cfg.gm_section,
+               cfg.lds_chunk_words);
   std::fclose(f);
 }
 
@@ -353,9 +356,17 @@ int prand_batch_create(prand_ctx* c, const prand_task* h_tasks, uint32_t ntasks,
   if (e == hipSuccess && !plan.tiles.empty())
     e = hipMemcpy(b->d_tiles, plan.tiles.data(), plan.tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
   if (e == hipSuccess && ntasks) e = hipMemcpy(b->d_tasks, h_tasks, ntasks * sizeof(BatchTask), hipMemcpyHostToDevice);
+  b->n_light = (uint32_t)plan.order_light.size();
+  b->n_heavy = (uint32_t)plan.order_heavy.size();
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_order, std::max<size_t>(1, b->n_light + b->n_heavy) * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, 256);
+  if (e == hipSuccess && b->n_light)
+    e = hipMemcpy(b->d_order, plan.order_light.data(), b->n_light * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && b->n_heavy)
+    e = hipMemcpy(b->d_order + b->n_light, plan.order_heavy.data(), b->n_heavy * 4, hipMemcpyHostToDevice);
+  b->blocks_light = batch_persistent_blocks(0, (int)conf.lds_chunk_words, conf.waves_per_block, c->num_cus);
+  b->blocks_heavy = batch_persistent_blocks(1, (int)conf.lds_chunk_words, conf.waves_per_block, c->num_cus);
   if (e == hipSuccess && conf.use_graph) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-  for (int i = 1; i < 4 && e == hipSuccess; i++) e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
-  for (int i = 0; i < 6 && e == hipSuccess; i++) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     free_batch(b);
     if (e == hipErrorOutOfMemory) {
@@ -380,13 +391,13 @@ int prand_batch_launch(prand_batch* b, void* stream) {
   DeviceGuard g(b->ctx->device);
   hipStream_t st = (hipStream_t)stream;
   if (!b->cfg.use_graph) {
-    hipError_t e = enqueue_forked(b, st);
+    hipError_t e = enqueue_persistent(b, st);
     return e == hipSuccess ? PRAND_OK : hipfail(b->ctx, e);
   }
   if (!b->exec) {
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = enqueue_forked(b, b->cap);
+      hipError_t le = enqueue_persistent(b, b->cap);
       e = hipStreamEndCapture(b->cap, &b->graph);
       if (e == hipSuccess) e = le;
     }
@@ -427,14 +438,17 @@ int prand_batch_autotune(prand_ctx* c, const prand_task* h_tasks, uint32_t ntask
   prand_batch_config pick{};
   fill_defaults(pick);
   pick.use_graph = 1;
-  const uint32_t waves[] = {2, 4};
+  // tile sizes of the two section kinds, and the LDS footprint of the light
+  // kernel (staging chunk of 16 or 32 words per MRG32K3A/LFSR113 lane: 5 or
+  // 9 KB per wavefront, which sets how many light wavefronts a CU holds)
+  const uint32_t cws[] = {16, 32};
   const uint32_t regs[] = {512, 2048, 8192};
   const uint32_t gms[] = {1024, 4096, 16384};
-  for (uint32_t w : waves)
+  for (uint32_t cw : cws)
     for (uint32_t r : regs)
       for (uint32_t gsec : gms) {
         if (e != hipSuccess) break;
-        prand_batch_config cand{w, r, gsec, 1};
+        prand_batch_config cand{4, r, gsec, 1, cw};
         prand_batch* b = nullptr;
         int rc = prand_batch_create(c, h_tasks, ntasks, &cand, &b);
         if (rc) {

@@ -7,24 +7,30 @@
 // section), or a whole MT19937 task (one wavefront per stream).  Sections are independent:
 // each starts from the task's state jumped to its first output.
 //
-// The launch is a small graph of kernels:
+// A batched launch (prand_batch_launch) is a chain of kernels on one stream:
+//  - batch_reset_kernel clears the tile counters;
 //  - batch_starts_kernel jumps every MRG32K3A/LFSR113/GM/GQ section to its
 //    start and writes the state to the batch's scratch area (the jump code
 //    needs many registers, so it runs apart from the generation loops);
 //    sections of MT19937 tasks above 2^24 outputs get theirs from
 //    mt_section_start_kernel (k_mt19937.hip);
-//  - batch_reg_kernel, batch_gm_kernel<shape> (lane-per-section v = 4
-//    ensembles, GQ58.3) and batch_mt_v1_kernel (MT19937 tasks and sections,
-//    then the 32-lane v = 1 ensembles) generate, one wavefront per tile, from
-//    those states (or, for a whole MT19937 task, from the task state) with
-//    the same wavefront routines as the one-generator kernels, and at their
-//    register counts.
-// The generation kernels are independent of each other; tiles within each
-// are ordered longest first, so the dispatcher starts the long ones early.
-// A whole MT19937 task runs on one wavefront (up to 2^24 outputs, some tens
-// of ms), so MT19937 shares a launch with the largest family, whose tiles
-// fill the chip around it: that overlap does not depend on how concurrent
-// kernels are spread over hardware queues.
+//  - two persistent kernels, one per register class, each launched with as
+//    many wavefronts as the chip holds at once: every wavefront takes the
+//    next tile of its class's list from a device counter until the list is
+//    used up.  The lists are ordered longest first by the host (estimated
+//    wavefront time), so the long tiles start at once and the short ones
+//    fill the end.  batch_heavy_kernel runs the lane-per-section ensembles
+//    (GM55, GQ58.3, GQ58.4: about 90 VGPRs); batch_light_kernel the rest
+//    (MT19937 tasks and sections, v = 1 GM/GQ, MRG32K3A/LFSR113, n = 0
+//    copies: under 64 VGPRs), its LDS sized by the chunk width of the
+//    MRG32K3A/LFSR113 staging (the footprint the autotuner chooses).
+// Each tile runs the same wavefront routines as the one-generator kernels.
+//
+// The serving loop keeps one grid kernel per family (batch_reg_kernel,
+// batch_gm_kernel<shape>, batch_mt_v1_kernel) on its iteration stream: its
+// iterations are small, and their length is set by the longest chunk.
+#include <algorithm>
+
 #include "dev_gm.h"
 #include "dev_gmlane.h"
 #include "dev_lfsr.h"
@@ -36,7 +42,7 @@
 namespace prand {
 namespace {
 
-constexpr int kBatchCW = 32;
+constexpr int kBatchCW = 32;   // MRG32K3A/LFSR113 staging chunk of the grid kernels
 
 // section geometry of a tile: group gi of the wavefront takes section first + gi
 struct Sect {
@@ -150,14 +156,14 @@ __global__ void __launch_bounds__(256) batch_starts_kernel(const BatchTile* __re
 }
 
 // ------------------------------------------------------- MRG32K3A/LFSR113
-template <class G, int DT>
+template <class G, int DT, int CW = kBatchCW>
 __device__ __forceinline__ void gen_reg(const BatchTile& tl, const BatchTask& tk, uint32_t* lds,
                                         const char* scratch) {
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
   const Sect s = section_of(tl, tk, 64);
   void* o = (char*)tk.out + (s.live ? s.start : 0) * es;
   const typename G::State* in = (const typename G::State*)(scratch + tl.starts) + (threadIdx.x & 63);
-  regstream_wave<G, DT, kBatchCW, false>(lds, s.live, in, 0, s.len, o,
+  regstream_wave<G, DT, CW, false>(lds, s.live, in, 0, s.len, o,
                                          s.last ? (typename G::State*)tk.state_out : nullptr, tl.coalesce != 0,
                                          nullptr);
 }
@@ -279,7 +285,7 @@ __device__ __forceinline__ void mt_tile(const BatchTile& tl, const BatchTask& tk
 __global__ void __launch_bounds__(256) batch_mt_v1_kernel(const BatchTile* __restrict__ mt_tiles, uint32_t nmt,
                                                           const BatchTile* __restrict__ v1_tiles, uint32_t nv1,
                                                           const BatchTask* __restrict__ tasks, char* scratch) {
-  __shared__ uint32_t mt[4][624];
+  __shared__ __align__(16) uint32_t mt[4][624];
   const uint32_t t = wave_index();
   if (t < nmt) {
     const BatchTile tl = mt_tiles[t];
@@ -296,9 +302,132 @@ __global__ void __launch_bounds__(256) batch_mt_v1_kernel(const BatchTile* __res
   }
 }
 
+// ---------------------------------------------------------- persistent
+__global__ void batch_reset_kernel(uint32_t* counters) {
+  if (threadIdx.x < kBatchCounters) counters[threadIdx.x] = 0;
+}
+
+// the next entry of a tile list for this wavefront (uniform across it)
+__device__ __forceinline__ uint32_t next_tile(uint32_t* counter) {
+  uint32_t k = 0;
+  if ((threadIdx.x & 63) == 0) k = atomicAdd(counter, 1u);
+  return __builtin_amdgcn_readfirstlane(__shfl(k, 0));
+}
+
+template <int CW>
+struct LightLds {
+  static constexpr int kWords = RegStage<CW>::kWaveWords > 624 ? RegStage<CW>::kWaveWords : 624;
+};
+
+template <int CW>
+__global__ void __launch_bounds__(256) batch_light_kernel(const BatchTile* __restrict__ tiles,
+                                                          const uint32_t* __restrict__ order, uint32_t n,
+                                                          const BatchTask* __restrict__ tasks, char* scratch,
+                                                          uint32_t* counter) {
+  __shared__ __align__(16) uint32_t lds[4][LightLds<CW>::kWords];
+  uint32_t* mine = lds[(threadIdx.x >> 6) & 3];
+  for (;;) {
+    const uint32_t k = next_tile(counter);
+    if (k >= n) break;
+    const BatchTile tl = tiles[order[k]];
+    const BatchTask tk = tasks[tl.task];
+    if (tk.gen == PRAND_MT19937 || tl.kind == kTileCopy) {
+      mt_tile(tl, tk, scratch, mine);
+    } else if (tk.gen == PRAND_MRG32K3A || tk.gen == PRAND_LFSR113) {
+      const bool mrg = tk.gen == PRAND_MRG32K3A;
+      switch (tk.dtype) {
+        case PRAND_U32:
+          if (mrg) gen_reg<mrg::MrgGen, PRAND_U32, CW>(tl, tk, mine, scratch);
+          else gen_reg<lfsr::LfsrGen, PRAND_U32, CW>(tl, tk, mine, scratch);
+          break;
+        case PRAND_F32:
+          if (mrg) gen_reg<mrg::MrgGen, PRAND_F32, CW>(tl, tk, mine, scratch);
+          else gen_reg<lfsr::LfsrGen, PRAND_F32, CW>(tl, tk, mine, scratch);
+          break;
+        default:
+          if (mrg) gen_reg<mrg::MrgGen, PRAND_F64, CW>(tl, tk, mine, scratch);
+          else gen_reg<lfsr::LfsrGen, PRAND_F64, CW>(tl, tk, mine, scratch);
+          break;
+      }
+    } else {
+      switch (tk.dtype) {
+        case PRAND_U32: gen_gm_dt<0, PRAND_U32>(tl, tk, scratch, nullptr); break;
+        case PRAND_F32: gen_gm_dt<0, PRAND_F32>(tl, tk, scratch, nullptr); break;
+        default: gen_gm_dt<0, PRAND_F64>(tl, tk, scratch, nullptr); break;
+      }
+    }
+    wave_lds_sync();   // the next tile reuses this wavefront's LDS
+  }
+}
+
+__global__ void __launch_bounds__(256) batch_heavy_kernel(const BatchTile* __restrict__ tiles,
+                                                          const uint32_t* __restrict__ order, uint32_t n,
+                                                          const BatchTask* __restrict__ tasks, char* scratch,
+                                                          uint32_t* counter) {
+  __shared__ __align__(16) uint32_t lds[4][gm::kLaneWaveWords];
+  uint32_t* rows = lds[(threadIdx.x >> 6) & 3];
+  for (;;) {
+    const uint32_t k = next_tile(counter);
+    if (k >= n) break;
+    const BatchTile tl = tiles[order[k]];
+    const BatchTask tk = tasks[tl.task];
+    if (tk.gen == PRAND_GQ58X3) {
+      switch (tk.dtype) {
+        case PRAND_U32: gen_gm_dt<2, PRAND_U32>(tl, tk, scratch, rows); break;
+        case PRAND_F32: gen_gm_dt<2, PRAND_F32>(tl, tk, scratch, rows); break;
+        default: gen_gm_dt<2, PRAND_F64>(tl, tk, scratch, rows); break;
+      }
+    } else {
+      switch (tk.dtype) {
+        case PRAND_U32: gen_gm_dt<1, PRAND_U32>(tl, tk, scratch, rows); break;
+        case PRAND_F32: gen_gm_dt<1, PRAND_F32>(tl, tk, scratch, rows); break;
+        default: gen_gm_dt<1, PRAND_F64>(tl, tk, scratch, rows); break;
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
 uint32_t blocks_for(uint32_t ntiles, uint32_t waves) { return (ntiles + waves - 1) / waves; }
 
+// resident workgroups of `waves` wavefronts on the whole chip
+template <class K>
+uint32_t resident_blocks(K kernel, uint32_t waves, int num_cus) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)(64 * waves), 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return (uint32_t)per_cu * (uint32_t)(num_cus > 0 ? num_cus : 1);
+}
+
 }  // namespace
+
+hipError_t launch_batch_reset(uint32_t* counters, hipStream_t st) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, counters);
+  return hipGetLastError();
+}
+
+uint32_t batch_persistent_blocks(int heavy, int cw, uint32_t waves, int num_cus) {
+  if (heavy) return resident_blocks(batch_heavy_kernel, waves, num_cus);
+  return cw == 16 ? resident_blocks(batch_light_kernel<16>, waves, num_cus)
+                  : resident_blocks(batch_light_kernel<32>, waves, num_cus);
+}
+
+hipError_t launch_batch_persistent(int heavy, int cw, const BatchTile* tiles, const uint32_t* order, uint32_t n,
+                                   const BatchTask* tasks, char* scratch, uint32_t* counter, uint32_t waves,
+                                   uint32_t blocks, hipStream_t st) {
+  if (!n) return hipSuccess;
+  // no more workgroups than tiles need
+  blocks = std::min<uint32_t>(blocks, blocks_for(n, waves));
+  const dim3 grid(blocks), block(64 * waves);
+  if (heavy)
+    hipLaunchKernelGGL(batch_heavy_kernel, grid, block, 0, st, tiles, order, n, tasks, scratch, counter);
+  else if (cw == 16)
+    hipLaunchKernelGGL(batch_light_kernel<16>, grid, block, 0, st, tiles, order, n, tasks, scratch, counter);
+  else
+    hipLaunchKernelGGL(batch_light_kernel<32>, grid, block, 0, st, tiles, order, n, tasks, scratch, counter);
+  return hipGetLastError();
+}
 
 hipError_t launch_batch_starts(const DeviceTables& T, const BatchTile* tiles, uint32_t ntiles, const BatchTask* tasks,
                                char* scratch, uint32_t waves, hipStream_t st) {

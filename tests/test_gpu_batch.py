@@ -59,7 +59,8 @@ def mixed_specs():
     return specs
 
 
-@pytest.mark.parametrize("cfg", [None, (2, 512, 1024, 1), (4, 8192, 16384, 0), (1, 32, 32, 1)])
+@pytest.mark.parametrize("cfg", [None, (2, 512, 1024, 1, 16), (4, 8192, 16384, 0, 32), (1, 32, 32, 1, 16),
+                                 (4, 2048, 4096, 1, 16)])
 def test_batch_matches_oracle(ctx, oracle, cfg):
     tasks, refs = make_tasks(oracle, mixed_specs())
     conf = P.BatchConfig(*cfg) if cfg else None
@@ -71,8 +72,9 @@ def test_batch_matches_oracle(ctx, oracle, cfg):
     b.close()
 
 
-# batches holding only some families: the MT19937 tiles and the v = 1 GM/GQ
-# tiles share one kernel, and either part (or both) may be empty
+# batches holding only some families: either register class (or both) may
+# be empty, and within the light class any of MT19937, v = 1 GM/GQ and
+# MRG32K3A/LFSR113
 SUBSETS = {
     "mt_only": [(P.MT19937, dt, n) for dt in (P.U32, P.F64) for n in (0, 1, 700, 5000)],
     "v1_only": [(g, dt, n) for g in (P.GM19, P.GM61, P.GQ58X1) for dt in (P.U32, P.F32) for n in (1, 64, 3001)],
