@@ -171,6 +171,16 @@ int prand_init_streams_dev(prand_ctx* ctx, int gen, int variant, const void* d_b
 int prand_generate(prand_ctx* ctx, int gen, void* h_state, int dtype, void* d_out, uint64_t n,
                    void* stream);
 
+/* Fill the host array h_out with the next n outputs of one host state
+   (rng_generate_array_, section "Multi-threaded generation of pseudorandom
+   numbers with GPGPU"): the values are generated on the device exactly as
+   by prand_generate, in chunks of up to 2^26 values through one device
+   buffer allocated for the call, and copied to the host; h_state is
+   advanced by n.  Any n is accepted (the paper's version pads n to a
+   multiple of its section count on the device; here the sections need no
+   padding).  PRAND_ERANGE when n > 2^40.  Blocks. */
+int prand_generate_array(prand_ctx* ctx, int gen, void* h_state, int dtype, void* h_out, uint64_t n);
+
 /* Many independent streams (section "Multi-threaded generation of
    pseudorandom numbers with GPGPU" applied to one state per stream, as in
    the paper's use of block splitting to give every thread block its own

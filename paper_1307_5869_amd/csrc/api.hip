@@ -488,6 +488,36 @@ int prand_init_stream(prand_ctx* c, int gen, int variant, uint64_t id, void* h_s
   return e == hipSuccess ? PRAND_OK : hipfail(c, e);
 }
 
+int prand_generate_array(prand_ctx* c, int gen, void* h_state, int dtype, void* h_out, uint64_t n) {
+  if (!c || !valid_gen(gen) || !valid_dtype(dtype) || !h_state) return PRAND_EINVAL;
+  if (n == 0) return PRAND_OK;
+  if (!h_out) return PRAND_EINVAL;
+  if (n > (1ull << 40)) return PRAND_ERANGE;
+  DeviceGuard g(c->device);
+  int rc = ensure_mt_locked(c, gen);
+  if (rc) return rc;
+  // chunks of at most 2^26 values: each is filled on the device by the
+  // sectioned fill (which continues the host state) and copied to the host
+  const size_t es = elem_bytes(dtype);
+  const uint64_t chunk = std::min<uint64_t>(n, 1ull << 26);
+  void* d_buf = nullptr;
+  hipError_t e = hipMalloc(&d_buf, chunk * es);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? PRAND_ENOMEM : hipfail(c, e);
+  }
+  for (uint64_t done = 0; done < n && rc == PRAND_OK; done += chunk) {
+    const uint64_t m = std::min(chunk, n - done);
+    rc = generate_host_state(c, gen, h_state, dtype, d_buf, m, nullptr, nullptr, 0);
+    if (rc == PRAND_OK) {
+      e = hipMemcpy((char*)h_out + done * es, d_buf, m * es, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) rc = hipfail(c, e);
+    }
+  }
+  (void)hipFree(d_buf);
+  return rc;
+}
+
 int prand_generate_streams(prand_ctx* c, int gen, void* d_states, uint32_t count, uint64_t n, int dtype,
                            void* d_out, void* stream) {
   if (!c || !valid_gen(gen) || !valid_dtype(dtype)) return PRAND_EINVAL;

@@ -40,6 +40,7 @@ _SIGNATURES = {
     "prand_init_streams_dev": (_i32, [_vp, _i32, _i32, _vp, _vp, _u32, _vp, _vp]),
     "prand_generate": (_i32, [_vp, _i32, _vp, _i32, _vp, _u64, _vp]),
     "prand_generate_noalloc": (_i32, [_vp, _i32, _vp, _i32, _vp, _u64, _vp]),
+    "prand_generate_array": (_i32, [_vp, _i32, _vp, _i32, _vp, _u64]),
     "prand_generate_streams": (_i32, [_vp, _i32, _vp, _u32, _u64, _i32, _vp, _vp]),
     "prand_batch_create": (_i32, [_vp, _vp, _u32, _vp, ctypes.POINTER(_vp)]),
     "prand_batch_launch": (_i32, [_vp, _vp]),
@@ -237,6 +238,12 @@ class Context:
     def generate(self, gen, state, dtype, d_out, n, stream=None):
         self._call("prand_generate", gen, _ptr(state), dtype, _ptr(d_out), n, _stream(stream))
         return d_out
+
+    def generate_array(self, gen, state, dtype, n):
+        """n values from a host state into a new host (numpy) array."""
+        out = np.empty(n, dtype={U32: np.uint32, F32: np.float32, F64: np.float64}[dtype])
+        self._call("prand_generate_array", gen, _ptr(state), dtype, _ptr(out), n)
+        return out
 
     def generate_noalloc(self, gen, state, dtype, d_out, n, stream=None):
         self._call("prand_generate_noalloc", gen, _ptr(state), dtype, _ptr(d_out), n, _stream(stream))
