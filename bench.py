@@ -24,10 +24,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E
-# 32-bit integer VALU lane-ops/s: the fp32 vector peak (157.3 TFLOP/s, an FMA
-# counted as two) is 78.6 T lane-ops/s = 256 CUs x 128 lanes x 2.4 GHz, and
-# 32-bit integer XOR/ADD/shift/compare issue at that rate
-VALU_PEAK_TOPS = 157.3 / 2
+# VALU issue on gfx950 (256 CUs x 4 SIMDs, 2.4 GHz) comes in two rates: the
+# simple 32-bit operations (add/sub, and/or/xor, three-input bitop3, right
+# shifts, FP32 add/mul/fma) complete a wave64 instruction every two cycles,
+# 32 lanes per SIMD per clock = 78.6 T lane-instructions/s -- the published
+# fp32 vector peak, 157.3 TFLOP/s, counts this FMA rate as two flops; the
+# others (left shifts, bit-field ops, 24-bit and 32-bit multiplies, min/max,
+# conversions, every FP64 operation) every four cycles, 39.3 T -- the fp64
+# vector peak, 78.6 TFLOP/s.  A probe of independent dependency chains
+# measured 66-74 T and 35-39 T for the two groups.
+VALU_FAST_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+VALU_SLOW_TOPS = VALU_FAST_TOPS / 2
+# Word-XORs: one three-input XOR (v_bitop3_b32, truth table 0x96, a fast
+# operation) adds two 32-bit words to a third, so the XOR-sum of the MT19937
+# jump peaks at two word-XORs per lane-instruction at the fast rate.
+XOR_PEAK_TOPS = 2 * VALU_FAST_TOPS
+# VALU lane-instructions per 32-bit output word of the GM/GQ generation
+# kernels (SQ_INSTS_VALU x 64 / words, counted at 65536 streams x 16384
+# words); a mix of fast and slow operations, reported against the fast peak
+GM_OPS_PER_WORD = {3: 266.1, 4: 330.1, 5: 330.1, 6: 153.6, 7: 428.1, 8: 338.1, 9: 150.6, 10: 105.5}
 
 
 def log(msg):
@@ -46,6 +61,7 @@ def parse():
     ap.add_argument("--no-dtype-sweep", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-jump", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the steps, one 1 GiB device-to-device copy (a plain copy kernel of known size, "
                          "the scale for hardware byte counters)")
@@ -128,9 +144,9 @@ def main():
             roof = {"kernel": f"{P.NAMES[g]} generate", "bound": "hbm", "achieved": traffic / t / 1e9,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s"}
         else:
-            ops = S * N * 32 * 6                 # element-steps x 6 ops (2 mul, sub, 2 reduce, cmp)
+            ops = S * N * GM_OPS_PER_WORD[g]     # VALU lane-instructions
             roof = {"kernel": f"{P.NAMES[g]} generate", "bound": "alu", "achieved": ops / t / 1e12,
-                    "peak": VALU_PEAK_TOPS, "unit": "Tops/s"}
+                    "peak": VALU_FAST_TOPS, "unit": "T lane-instructions/s"}
     else:
         if g == P.MT19937:
             # XOR-sum: per stream one table polynomial per nonzero 16-bit digit
@@ -140,8 +156,8 @@ def main():
             idv = W.stream_ids(S, g)
             apps = int(sum(sum(1 for k in range(3) if (int(x) >> (16 * k)) & 0xFFFF) for x in idv))
             ops = apps * (19937 // 2) * 624
-            roof = {"kernel": "MT19937 jump", "bound": "alu", "achieved": ops / t / 1e12, "peak": VALU_PEAK_TOPS,
-                    "unit": "Tops/s"}
+            roof = {"kernel": "MT19937 jump", "bound": "alu", "achieved": ops / t / 1e12, "peak": XOR_PEAK_TOPS,
+                    "unit": "T word-XOR/s"}
         else:
             sb = P.state_bytes(g)
             roof = {"kernel": f"{P.NAMES[g]} jump", "bound": "hbm", "achieved": 2 * S * sb / t / 1e9,
@@ -190,8 +206,13 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    log("C2 step done; batched workload")
-    batched = None if args.no_batched else batched_vs_plain(ctx, args.batched_tasks, stream)
+    log("C2 step done; 4096-stream MRG32K3A workload")
+    c1 = mrg_4096_streams(ctx, stream) if P.MRG32K3A in gens else None
+    log("2^20-stream jump workload")
+    c3 = None if args.no_jump else jump_2pow_k(ctx, stream, gens)
+    log("batched workload")
+    rates = {g: extra[P.NAMES[g]]["f32"]["numbers_per_s"] for g in gens} if extra and len(gens) == 11 else None
+    batched = None if args.no_batched else batched_vs_plain(ctx, args.batched_tasks, stream, rates)
     log("batched done; serving loop")
     serving = None if args.no_serve else serve_trace(ctx, args.serve_rate, args.serve_seconds)
     log("serving done; CPU baseline")
@@ -218,6 +239,8 @@ def main():
         "roofline": roof,
         "per_generator": per_gen,
         "dtype_sweep": extra,
+        "mrg32k3a_4096_streams": c1,
+        "jump_2pow_k": c3,
         "fill_probe": write_probe,
         "batched": batched,
         "serving": serving,
@@ -253,7 +276,86 @@ def recorded_traffic(kernel):
     return None
 
 
-def batched_vs_plain(ctx, ntasks, stream):
+def mrg_4096_streams(ctx, stream, reps=20):
+    """4096 MRG32K3A streams from the all-12345 state, stream k skipped
+    k * 2^76 ahead, then 4096 u32 outputs per stream and their float64
+    conversion (16.7M numbers each): skip-ahead + both generation launches
+    per repetition, states reset from the base outside the events."""
+    import torch
+
+    from paper_1307_5869_amd import prand as P
+
+    dev = torch.device("cuda:0")
+    gen, count, n = P.MRG32K3A, 4096, 4096
+    base = ctx.seed(gen, 12345)
+    d0 = torch.from_numpy(np.concatenate([base] * count)).to(dev)
+    limbs = torch.from_numpy(np.stack([P.limbs(k * 2**76) for k in range(count)]).view(np.int64)).to(dev)
+    d, d2 = torch.empty_like(d0), torch.empty_like(d0)
+    u = torch.empty(count * n, dtype=torch.int32, device=dev)
+    f = torch.empty(count * n, dtype=torch.float64, device=dev)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps + 2)]
+    for r in range(reps + 2):
+        d.copy_(d0)
+        e = ev[r]
+        e[0].record(stream)
+        ctx.skipahead_dev(gen, d, count, limbs, 8, True, stream)
+        d2.copy_(d)
+        e[1].record(stream)
+        ctx.generate_streams(gen, d, count, n, P.U32, u, stream)
+        e[2].record(stream)
+        ctx.generate_streams(gen, d2, count, n, P.F64, f, stream)
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    jump = float(np.mean([e[0].elapsed_time(e[1]) for e in ev[2:]]))
+    gu = float(np.mean([e[1].elapsed_time(e[2]) for e in ev[2:]]))
+    gf = float(np.mean([e[2].elapsed_time(e[3]) for e in ev[2:]]))
+    total = jump + gu + gf
+    written = count * n * (4 + 8)
+    return {"workload": "MRG32K3A, 4096 streams from the all-12345 state, stream k skipped k*2^76, "
+                        "4096 u32 + 4096 f64 per stream",
+            "skipahead_ms": round(jump, 4), "gen_u32_ms": round(gu, 4), "gen_f64_ms": round(gf, 4),
+            "total_ms": round(total, 4), "numbers_per_s": 2 * count * n / (total * 1e-3),
+            "gen_write_GBs": written / ((gu + gf) * 1e-3) / 1e9,
+            "gen_hbm_frac": written / ((gu + gf) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "note": "16.7M outputs per launch take tens of microseconds, so launch latency is a large share"}
+
+
+def jump_2pow_k(ctx, stream, gens):
+    """2^20 streams per generator, each jumped 2^k ahead (k uniform in the
+    generator's table range) by one per-stream skip-ahead launch: streams
+    initialised per second."""
+    import torch
+
+    from paper_1307_5869_amd import prand as P
+    from paper_1307_5869_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    S = 1 << 20
+    res = {}
+    for g in gens:
+        base = ctx.seed(g, 4242 + g)
+        states = torch.from_numpy(base.copy()).to(dev).repeat(S)
+        ks = W.jump_exponents(S, g)
+        limbs = np.zeros((S, 8), dtype=np.uint64)
+        limbs[np.arange(S), ks // 64] = np.left_shift(np.uint64(1), (ks % 64).astype(np.uint64))
+        t_limbs = torch.from_numpy(limbs.reshape(-1).view(np.int64)).to(dev)
+        ctx.skipahead_dev(g, states, S, t_limbs, 8, True, stream)   # warm-up (and MT19937 tables)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.skipahead_dev(g, states, S, t_limbs, 8, True, stream)
+        b.record(stream)
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        lo, hi = W.JUMP_EXP_RANGE[g]
+        res[P.NAMES[g]] = {"ms": round(ms, 3), "streams_per_s": S / (ms * 1e-3), "k_range": [lo, hi],
+                           "state_bytes": P.state_bytes(g)}
+        del states, t_limbs
+    torch.cuda.empty_cache()
+    return {"workload": "2^20 streams per generator, stream s jumped 2^k_s ahead, k_s uniform in the range",
+            "per_generator": res}
+
+
+def batched_vs_plain(ctx, ntasks, stream, plain_rates=None):
     """Many streams of mixed generators and uneven lengths (log-uniform in
     [1e3, 1e7]) in f32: one autotuned batched launch replayed from a HIP
     graph, against plain per-stream launches timed on a sample of the tasks."""
@@ -303,6 +405,32 @@ def batched_vs_plain(ctx, ntasks, stream):
     ms = a.elapsed_time(z) / reps
     tiles = b.tiles()
     b.close()
+    # plain per-generator launches on the same work: per generator, tasks
+    # bucketed by length (lengths within a factor of two), one many-stream
+    # launch per bucket generating the bucket's longest length for every
+    # stream in it (padding outputs go to a scratch buffer)
+    buckets = []
+    for g, (sel, st) in sin.items():
+        lg = lens[sel]
+        key = np.floor(np.log2(lg)).astype(int)
+        for kb in np.unique(key):
+            idx = np.nonzero(key == kb)[0]
+            gather = torch.from_numpy(np.concatenate([np.arange(j * sb[g], (j + 1) * sb[g]) for j in idx])).to(dev)
+            buckets.append((g, len(idx), int(lg[idx].max()), int(lg[idx].sum()), st[gather].contiguous()))
+    pad_out = torch.empty(max(c * nmax for _, c, nmax, _, _ in buckets), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for g, c, nmax, _, bst in buckets:
+        ctx.generate_streams(g, bst, c, nmax, P.F32, pad_out, stream)
+    z.record(stream)
+    z.synchronize()
+    bucket_ms = a.elapsed_time(z)
+    bucket_padded = sum(c * nmax for _, c, nmax, _, _ in buckets)
+    del buckets, pad_out
+    # the same work at each generator's full-size many-stream f32 rate
+    ideal_ms = None
+    if plain_rates:
+        ideal_ms = 1e3 * sum(int(lens[sel].sum()) / plain_rates[g] for g, (sel, _) in sin.items())
     # plain: one generate launch per stream (prand_generate_streams, count 1),
     # over a random order of the tasks until about 10 s of GPU time have been
     # spent; the output states are copies of the input states, advanced in place
@@ -345,17 +473,24 @@ def batched_vs_plain(ctx, ntasks, stream):
     del out
     torch.cuda.empty_cache()
     return {"tasks": ntasks, "numbers": total, "dtype": "f32", "tiles": tiles,
+            "plain_per_generator_ms": round(bucket_ms, 3), "plain_per_generator_padded_numbers": bucket_padded,
+            "speedup_vs_plain_per_generator": bucket_ms / ms,
+            "ideal_plain_ms": round(ideal_ms, 3) if ideal_ms else None,
+            "batched_over_ideal_plain": ms / ideal_ms if ideal_ms else None,
             "plain_sectioned_tasks": sec_done, "plain_sectioned_numbers": sec_numbers,
             "plain_sectioned_s": round(sec_s, 3),
             "plain_sectioned_numbers_per_s": sec_numbers / sec_s,
             "speedup_vs_sectioned": (total / (ms * 1e-3)) / (sec_numbers / sec_s),
             "config": {"waves_per_block": best.waves_per_block, "reg_section": best.reg_section,
-                       "gm_section": best.gm_section, "graph": bool(best.use_graph)},
+                       "gm_section": best.gm_section, "lds_chunk_words": best.lds_chunk_words,
+                       "overlap": best.overlap,
+                       "graph": bool(best.use_graph)},
             "autotune_s": round(tune_s, 2), "batched_ms": round(ms, 3),
             "batched_numbers_per_s": total / (ms * 1e-3),
-            "plain_sample_tasks": done, "plain_sample_numbers": plain_numbers,
-            "plain_ms": round(plain_ms, 3), "plain_numbers_per_s": plain_numbers / (plain_ms * 1e-3),
-            "speedup": (total / (ms * 1e-3)) / (plain_numbers / (plain_ms * 1e-3))}
+            "one_launch_per_stream_sample_tasks": done, "one_launch_per_stream_sample_numbers": plain_numbers,
+            "one_launch_per_stream_ms": round(plain_ms, 3),
+            "one_launch_per_stream_numbers_per_s": plain_numbers / (plain_ms * 1e-3),
+            "speedup_vs_one_launch_per_stream": (total / (ms * 1e-3)) / (plain_numbers / (plain_ms * 1e-3))}
 
 
 def serve_trace(ctx, rate, seconds):
@@ -417,41 +552,71 @@ def serve_trace(ctx, rate, seconds):
             "workload": "Poisson arrivals, gen and dtype uniform, ids uniform in [0,1e19), n log-uniform [1e3,1e8]"}
 
 
-def cpu_baseline(gens, S, N):
-    """The oracle (single-threaded C, untuned) on host threads over streams:
-    per generator a sample of streams is initialised by block splitting and
-    generates N words; the full workload's CPU time is scaled from it."""
+def host_cpu():
+    """(logical CPUs of the host, CPUs this process may run on, model name)"""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return os.cpu_count() or 1, usable, model
+
+
+def cpu_baseline(gens, S, N, share=16):
+    """The oracle (plain single-threaded C, untuned) on host threads over
+    streams, per generator: block-splitting initialisation of a sample of the
+    workload's streams, then generation of N words from those states (cycled
+    over a larger sample).  The threads are the CPUs this process may use, at
+    most `share` (a GPU's share of the host).  The whole workload's CPU time
+    is estimated from the two rates."""
     from oracle import Oracle
+    from paper_1307_5869_amd import prand as P
     from paper_1307_5869_amd import workloads as W
 
     O = Oracle()
     O.mt_charpoly()   # one-time polynomial set-up, not part of the timing
-    cores = min(16, os.cpu_count() or 1)
-    total_cpu_s = 0.0
-    sample_desc = []
-    for g in gens:
-        ns = 2 * cores if g == 0 else 8 * cores
-        sid = W.stream_ids(S, g)[:ns]
-        bufs = [np.empty(N, dtype=np.uint32) for _ in range(ns)]
+    nproc, usable, model = host_cpu()
+    cores = max(1, min(share, usable))
 
-        def work(k0):
-            for k in range(k0, ns, cores):
-                st = O.init_stream(g, 0, int(sid[k]))
-                O.generate_into(g, st, 0, bufs[k])
-
-        th = [threading.Thread(target=work, args=(c,)) for c in range(cores)]
+    def run(fn, count):
+        th = [threading.Thread(target=lambda c=c: [fn(k) for k in range(c, count, cores)]) for c in range(cores)]
         t0 = time.perf_counter()
         for t in th:
             t.start()
         for t in th:
             t.join()
-        dt = time.perf_counter() - t0
-        total_cpu_s += dt * S / ns
-        sample_desc.append(f"{ns}")
-    value = len(gens) * S * N / total_cpu_s
+        return time.perf_counter() - t0
+
+    per_gen, total_s = {}, 0.0
+    for g in gens:
+        n_init = cores if g == P.MT19937 else (64 * cores if g == P.LFSR113 else 256 * cores)
+        # about a second of generation per generator
+        n_gen = cores * (1024 if g <= P.LFSR113 else (256 if g in (P.GM55, P.GQ58X3, P.GQ58X4) else 128))
+        sid = W.stream_ids(n_init, g)
+        sts = [None] * n_init
+        t_init = run(lambda k: sts.__setitem__(k, O.init_stream(g, 0, int(sid[k]))), n_init)
+        bufs = [np.empty(N, dtype=np.uint32) for _ in range(cores)]
+        t_gen = run(lambda k: O.generate_into(g, sts[k % n_init], 0, bufs[k % cores]), n_gen)
+        init_ps, gen_ps = n_init / t_init, n_gen * N / t_gen
+        est = S / init_ps + S * N / gen_ps
+        total_s += est
+        per_gen[P.NAMES[g]] = {"init_streams_per_s": init_ps, "gen_u32_numbers_per_s": gen_ps,
+                               "sample": f"init {n_init} streams, generate {n_gen} x {N} words",
+                               "workload_s_est": round(est, 1)}
+    value = len(gens) * S * N / total_s
     return {"value": value, "unit": "numbers/s", "cores": cores, "kind": "oracle",
-            "sample": f"per generator the first k streams of the workload (k = {','.join(sample_desc)}), "
-                      f"init + {N} words each, {cores} threads over streams; scaled to {S} streams"}
+            "host": {"nproc": nproc, "usable_cpus": usable, "model": model},
+            "sample": f"per generator: block-splitting init of a sample of the workload's stream ids, then "
+                      f"{N} u32 words from those states, on {cores} threads over streams; the whole "
+                      f"{len(gens)} x {S}-stream workload's CPU time is estimated from the two rates",
+            "per_generator": per_gen}
 
 
 if __name__ == "__main__":

@@ -216,11 +216,13 @@ int prand_generate_noalloc(prand_ctx* ctx, int gen, void* h_state, int dtype, vo
  * dtypes in one launch, replayed from a HIP graph.  Each task is cut into
  * sections that jump to their first output (the sectioning of "Multi-threaded
  * generation"), grouped into per-wavefront tiles; a first kernel computes
- * every section's start state, then two persistent kernels (one per register
- * class: the lane-per-section GM55/GQ58.3/GQ58.4 tiles, then all others),
- * each as many wavefronts as the chip holds, work through their tile lists
- * longest first, every wavefront taking the next tile from a device
- * counter.
+ * every section's start state, then three persistent kernels, one per
+ * register class (the lane-per-section GM55/GQ58.3/GQ58.4 tiles;
+ * MRG32K3A/LFSR113; MT19937 with the v = 1 GM/GQ ensembles), work through
+ * their tile lists longest first, every wavefront taking the next tile from
+ * its class's device counter -- one after another, each with as many
+ * wavefronts as the chip holds, or side by side, each with a share of the
+ * chip sized by its work (prand_batch_config.overlap).
  * ------------------------------------------------------------------------ */
 typedef struct prand_task {
   int32_t gen;           /* enum prand_gen */
@@ -238,7 +240,9 @@ typedef struct prand_batch_config {
   uint32_t gm_section;     /* GM/GQ outputs per element-group section (0: 4096) */
   uint32_t use_graph;      /* 1: capture the launch in a HIP graph and replay it */
   uint32_t lds_chunk_words; /* LDS staging of MRG32K3A/LFSR113 lanes, 16 or 32 words (0: 32):
-                               5 or 9 KB per wavefront of the light kernel */
+                               5 or 9 KB per wavefront of their kernel */
+  uint32_t overlap;        /* 1: the three class kernels run side by side, each class's share of
+                              the chip sized by its work; 0: one after another */
 } prand_batch_config;
 
 typedef struct prand_batch prand_batch;

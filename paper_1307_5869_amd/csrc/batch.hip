@@ -4,12 +4,12 @@
 // and groups them into per-wavefront tiles (see k_batch.hip), family by
 // family.  Every MRG32K3A/LFSR113 and GM/GQ tile gets a slot in the batch's
 // scratch area for its sections' start states.  The tiles of each register
-// class (light: MRG32K3A/LFSR113, v = 1 GM/GQ, MT19937, copies; heavy: the
-// lane-per-section GM/GQ shapes) form one list, longest first by estimated
-// wavefront time, which the class's persistent kernel works through.  The
-// launch -- counter reset, section starts, heavy list, light list, all on
-// one stream -- is captured once in a HIP graph on a private stream and
-// replayed on the caller's stream.  The autotuner times a small grid of
+// class (light: v = 1 GM/GQ, MT19937, copies; reg: MRG32K3A/LFSR113; heavy:
+// the lane-per-section GM/GQ shapes) form one list, longest first by
+// estimated wavefront time, which the class's persistent kernel works
+// through.  The launch -- counter reset and section starts, then the three
+// persistent kernels side by side on forked streams -- is captured once in a
+// HIP graph on a private stream and replayed on the caller's stream.  The autotuner times a small grid of
 // (MRG32K3A/LFSR113 lane section, GM/GQ group section, LDS chunk width of
 // the light kernel) on the actual task mix.
 #include <hip/hip_runtime.h>
@@ -35,11 +35,14 @@ struct prand_batch {
   BatchCounts n;
   BatchTask* d_tasks = nullptr;
   char* d_scratch = nullptr;
-  uint32_t* d_order = nullptr;      // light list, then heavy list
+  uint32_t* d_order = nullptr;      // the class lists, one after the other
   uint32_t* d_counters = nullptr;   // kBatchCounters tile counters
-  uint32_t n_light = 0, n_heavy = 0;
-  uint32_t blocks_light = 0, blocks_heavy = 0;
+  uint32_t n_cls[kBatchCounters] = {0, 0, 0};
+  uint32_t off_cls[kBatchCounters] = {0, 0, 0};
+  uint32_t blocks_cls[kBatchCounters] = {0, 0, 0};
   hipStream_t cap = nullptr;
+  hipStream_t side[2] = {nullptr, nullptr};    // heavy and reg branches
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // fork, joins
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -71,6 +74,16 @@ double per_output_cost(int gen) {
   }
 }
 
+// whole-chip time per output of the plain many-stream kernels (ms per 2^30
+// outputs, 65536 streams, MI355X; u32 and f32 alike, then f64): the work a
+// class of tiles holds, from which the side-by-side launch sizes its share
+double chip_cost(int gen, int dtype) {
+  static const double t[PRAND_NUM_GENERATORS][2] = {
+      {0.95, 1.80}, {0.97, 1.66}, {1.03, 1.70}, {6.46, 6.53}, {7.33, 7.40}, {7.31, 7.37},
+      {4.16, 6.43}, {10.67, 10.61}, {7.28, 7.42}, {4.08, 5.70}, {3.47, 5.86}};
+  return t[gen][dtype == PRAND_F64 ? 1 : 0];
+}
+
 uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
 
 void fill_defaults(prand_batch_config& c) {
@@ -78,6 +91,7 @@ void fill_defaults(prand_batch_config& c) {
   if (!c.reg_section) c.reg_section = 2048;
   if (!c.gm_section) c.gm_section = 4096;
   c.lds_chunk_words = c.lds_chunk_words == 16 ? 16 : 32;
+  c.overlap = c.overlap ? 1 : 0;
   c.waves_per_block = c.waves_per_block >= 4 ? 4 : (c.waves_per_block >= 2 ? 2 : 1);
   c.reg_section = (uint32_t)std::max<uint64_t>(32, round_up(c.reg_section, 32));
   c.gm_section = std::max<uint32_t>(32, c.gm_section);
@@ -100,6 +114,7 @@ int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_confi
   // families in BatchCounts order: MRG32K3A/LFSR113, GM/GQ v = 1, v = 4,
   // GQ58.3, MT19937, copies (n = 0)
   std::vector<std::pair<double, BatchTile>> work[kBatchFamilies];
+  plan.cost[0] = plan.cost[1] = plan.cost[2] = 0;
   for (uint32_t k = 0; k < ntasks; k++) {
     const prand_task& t = tasks[k];
     if (t.gen < 0 || t.gen >= PRAND_NUM_GENERATORS || t.dtype < PRAND_U32 || t.dtype > PRAND_F64)
@@ -117,6 +132,12 @@ int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_confi
     b.kind = kTileGen;
     const uint64_t n = t.n, es = t.dtype == PRAND_F64 ? 8 : 4;
     const double c = per_output_cost(t.gen);
+    {
+      const bool v1 = t.gen == PRAND_GM19 || t.gen == PRAND_GM29 || t.gen == PRAND_GM31 || t.gen == PRAND_GM61 ||
+                      t.gen == PRAND_GQ58X1;
+      const int cls = (is_reg(t.gen)) ? kClassReg : (t.gen == PRAND_MT19937 || v1) ? kClassLight : kClassHeavy;
+      plan.cost[cls] += (double)n * chip_cost(t.gen, t.dtype);
+    }
     if (t.gen == PRAND_MT19937) {
       // one wavefront per task, or, for a long task, per kMtSection-output
       // section (each section starts from a jump of the task state)
@@ -199,12 +220,12 @@ int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_confi
   plan.tiles.resize(total);
   plan.scratch_bytes = 0;
   plan.n.mtsec = 0;
-  std::vector<std::pair<double, uint32_t>> light, heavy;
+  std::vector<std::pair<double, uint32_t>> light, reg, heavy;
   size_t at = 0;
   for (int f = 0; f < kBatchFamilies; f++) {
     std::stable_sort(work[f].begin(), work[f].end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     for (auto& w : work[f]) {
-      (f == 2 || f == 3 ? heavy : light).push_back({w.first, (uint32_t)at});
+      (f == 0 ? reg : (f == 2 || f == 3) ? heavy : light).push_back({w.first, (uint32_t)at});
       BatchTile& tl = plan.tiles[at++];
       tl = w.second;
       if (f <= 3 || tl.kind == kTileMtSection) {
@@ -221,12 +242,13 @@ int batch_plan(const prand_task* tasks, uint32_t ntasks, const prand_batch_confi
     }
   }
   // each class's list longest first (ties: family order, then placement)
-  for (auto* v : {&light, &heavy})
-    std::stable_sort(v->begin(), v->end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-  plan.order_light.resize(light.size());
-  plan.order_heavy.resize(heavy.size());
-  for (size_t i = 0; i < light.size(); i++) plan.order_light[i] = light[i].second;
-  for (size_t i = 0; i < heavy.size(); i++) plan.order_heavy[i] = heavy[i].second;
+  const std::pair<std::vector<std::pair<double, uint32_t>>*, std::vector<uint32_t>*> lists[] = {
+      {&light, &plan.order_light}, {&reg, &plan.order_reg}, {&heavy, &plan.order_heavy}};
+  for (auto& l : lists) {
+    std::stable_sort(l.first->begin(), l.first->end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    l.second->resize(l.first->size());
+    for (size_t i = 0; i < l.first->size(); i++) (*l.second)[i] = (*l.first)[i].second;
+  }
   plan.n.reg = (uint32_t)work[0].size();
   plan.n.g32 = (uint32_t)work[1].size();
   plan.n.g8 = (uint32_t)work[2].size();
@@ -244,6 +266,10 @@ void free_batch(prand_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t s : b->side)
+    if (s) (void)hipStreamDestroy(s);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   (void)hipFree(b->d_tiles);
   (void)hipFree(b->d_tasks);
@@ -253,9 +279,14 @@ void free_batch(prand_batch* b) {
   delete b;
 }
 
-// The batch's kernels on stream a: tile counters cleared, section starts
-// (and the MT19937 section starts, when a task is long enough to have
-// sections), then the heavy and the light persistent kernels.
+// The batch's kernels: on stream a the tile counters are cleared and every
+// section jumped to its start (and the MT19937 section starts, when a task
+// is long enough to have sections); then the three persistent kernels run,
+// either one after another on stream a, each with the whole chip's worth of
+// workgroups, or side by side -- heavy and reg on two forked streams, each
+// with the share of the chip its work takes, light on stream a with the
+// whole chip's worth (those that do not fit at first are dispatched as the
+// other two classes' wavefronts finish) -- and the forks join back into a.
 hipError_t enqueue_persistent(prand_batch* b, hipStream_t a) {
   const DeviceTables& T = b->ctx->T;
   const uint32_t w = b->cfg.waves_per_block;
@@ -265,12 +296,28 @@ hipError_t enqueue_persistent(prand_batch* b, hipStream_t a) {
   hipError_t e = launch_batch_reset(b->d_counters, a);
   if (e == hipSuccess) e = launch_batch_starts(T, b->d_tiles, n.with_starts(), b->d_tasks, b->d_scratch, w, a);
   if (e == hipSuccess && n.mtsec) e = launch_batch_mt_starts(T, mt, n.mt, b->d_tasks, b->d_scratch, a);
+  if (!b->cfg.overlap) {
+    for (int cls : {kClassHeavy, kClassReg, kClassLight})
+      if (e == hipSuccess)
+        e = launch_batch_persistent(cls, cw, b->d_tiles, b->d_order + b->off_cls[cls], b->n_cls[cls], b->d_tasks,
+                                    b->d_scratch, b->d_counters + cls, w, b->blocks_cls[cls], a);
+    return e;
+  }
+  if (e == hipSuccess) e = hipEventRecord(b->ev[0], a);
+  const int side_cls[2] = {kClassHeavy, kClassReg};
+  for (int i = 0; i < 2 && e == hipSuccess; i++) {
+    const int cls = side_cls[i];
+    e = hipStreamWaitEvent(b->side[i], b->ev[0], 0);
+    if (e == hipSuccess)
+      e = launch_batch_persistent(cls, cw, b->d_tiles, b->d_order + b->off_cls[cls], b->n_cls[cls], b->d_tasks,
+                                  b->d_scratch, b->d_counters + cls, w, b->blocks_cls[cls], b->side[i]);
+    if (e == hipSuccess) e = hipEventRecord(b->ev[1 + i], b->side[i]);
+  }
   if (e == hipSuccess)
-    e = launch_batch_persistent(1, cw, b->d_tiles, b->d_order + b->n_light, b->n_heavy, b->d_tasks, b->d_scratch,
-                                b->d_counters + 1, w, b->blocks_heavy, a);
-  if (e == hipSuccess)
-    e = launch_batch_persistent(0, cw, b->d_tiles, b->d_order, b->n_light, b->d_tasks, b->d_scratch, b->d_counters,
-                                w, b->blocks_light, a);
+    e = launch_batch_persistent(kClassLight, cw, b->d_tiles, b->d_order + b->off_cls[kClassLight],
+                                b->n_cls[kClassLight], b->d_tasks, b->d_scratch, b->d_counters + kClassLight, w,
+                                b->blocks_cls[kClassLight], a);
+  for (int i = 0; i < 2 && e == hipSuccess; i++) e = hipStreamWaitEvent(a, b->ev[1 + i], 0);
   return e;
 }
 
@@ -303,13 +350,14 @@ bool cache_lookup(const std::string& key, prand_batch_config* cfg) {
     char* tab = std::strchr(line, '\t');
     if (!tab) continue;
     *tab = 0;
-    unsigned w, r, g, cw;
-    if (key == line && std::sscanf(tab + 1, "%u %u %u %u", &w, &r, &g, &cw) == 4) {
+    unsigned w, r, g, cw, ov;
+    if (key == line && std::sscanf(tab + 1, "%u %u %u %u %u", &w, &r, &g, &cw, &ov) == 5) {
       cfg->waves_per_block = w;
       cfg->reg_section = r;
       cfg->gm_section = g;
       cfg->use_graph = 1;
       cfg->lds_chunk_words = cw;
+      cfg->overlap = ov;
       found = true;   // the last entry for a key wins
     }
   }
@@ -322,8 +370,8 @@ void cache_store(const std::string& key, const prand_batch_config& cfg) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s\t%u %u %u %u\n", key.c_str(), cfg.waves_per_block, cfg.reg_section, cfg.gm_section,
-               cfg.lds_chunk_words);
+  std::fprintf(f, "%s\t%u %u %u %u %u\n", key.c_str(), cfg.waves_per_block, cfg.reg_section, cfg.gm_section,
+               cfg.lds_chunk_words, cfg.overlap);
   std::fclose(f);
 }
 
@@ -356,17 +404,30 @@ int prand_batch_create(prand_ctx* c, const prand_task* h_tasks, uint32_t ntasks,
   if (e == hipSuccess && !plan.tiles.empty())
     e = hipMemcpy(b->d_tiles, plan.tiles.data(), plan.tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
   if (e == hipSuccess && ntasks) e = hipMemcpy(b->d_tasks, h_tasks, ntasks * sizeof(BatchTask), hipMemcpyHostToDevice);
-  b->n_light = (uint32_t)plan.order_light.size();
-  b->n_heavy = (uint32_t)plan.order_heavy.size();
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_order, std::max<size_t>(1, b->n_light + b->n_heavy) * 4);
+  const std::vector<uint32_t>* ord[kBatchCounters] = {&plan.order_light, &plan.order_reg, &plan.order_heavy};
+  uint32_t total_order = 0;
+  const double all = plan.cost[0] + plan.cost[1] + plan.cost[2];
+  for (int cls = 0; cls < kBatchCounters; cls++) {
+    b->n_cls[cls] = (uint32_t)ord[cls]->size();
+    b->off_cls[cls] = total_order;
+    total_order += b->n_cls[cls];
+    const uint32_t full = batch_persistent_blocks(cls, (int)conf.lds_chunk_words, conf.waves_per_block, c->num_cus);
+    // one after another, every class gets the whole chip; side by side, the
+    // light class gets the whole chip's worth and the forked classes the
+    // share their work takes of the batch's (a tenth more, so that they
+    // rather finish before the light class than after it)
+    const double share =
+        (!conf.overlap || cls == kClassLight || all <= 0) ? 1.0 : std::min(1.0, 1.1 * plan.cost[cls] / all);
+    b->blocks_cls[cls] = std::max<uint32_t>(1, (uint32_t)std::ceil(share * full));
+  }
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_order, std::max<size_t>(1, total_order) * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, 256);
-  if (e == hipSuccess && b->n_light)
-    e = hipMemcpy(b->d_order, plan.order_light.data(), b->n_light * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess && b->n_heavy)
-    e = hipMemcpy(b->d_order + b->n_light, plan.order_heavy.data(), b->n_heavy * 4, hipMemcpyHostToDevice);
-  b->blocks_light = batch_persistent_blocks(0, (int)conf.lds_chunk_words, conf.waves_per_block, c->num_cus);
-  b->blocks_heavy = batch_persistent_blocks(1, (int)conf.lds_chunk_words, conf.waves_per_block, c->num_cus);
+  for (int cls = 0; cls < kBatchCounters && e == hipSuccess; cls++)
+    if (b->n_cls[cls])
+      e = hipMemcpy(b->d_order + b->off_cls[cls], ord[cls]->data(), b->n_cls[cls] * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && conf.use_graph) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  for (int i = 0; i < 2 && e == hipSuccess; i++) e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+  for (int i = 0; i < 3 && e == hipSuccess; i++) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     free_batch(b);
     if (e == hipErrorOutOfMemory) {
@@ -442,13 +503,15 @@ int prand_batch_autotune(prand_ctx* c, const prand_task* h_tasks, uint32_t ntask
   // kernel (staging chunk of 16 or 32 words per MRG32K3A/LFSR113 lane: 5 or
   // 9 KB per wavefront, which sets how many light wavefronts a CU holds)
   const uint32_t cws[] = {16, 32};
-  const uint32_t regs[] = {512, 2048, 8192};
-  const uint32_t gms[] = {1024, 4096, 16384};
-  for (uint32_t cw : cws)
+  const uint32_t regs[] = {2048, 8192};
+  const uint32_t gms[] = {4096, 16384};
+  const uint32_t ovs[] = {0, 1};
+  for (uint32_t ov : ovs)
+   for (uint32_t cw : cws)
     for (uint32_t r : regs)
       for (uint32_t gsec : gms) {
         if (e != hipSuccess) break;
-        prand_batch_config cand{4, r, gsec, 1, cw};
+        prand_batch_config cand{4, r, gsec, 1, cw, ov};
         prand_batch* b = nullptr;
         int rc = prand_batch_create(c, h_tasks, ntasks, &cand, &b);
         if (rc) {

@@ -14,16 +14,18 @@
 //    needs many registers, so it runs apart from the generation loops);
 //    sections of MT19937 tasks above 2^24 outputs get theirs from
 //    mt_section_start_kernel (k_mt19937.hip);
-//  - two persistent kernels, one per register class, each launched with as
-//    many wavefronts as the chip holds at once: every wavefront takes the
+//  - three persistent kernels, one per register class, each launched with
+//    as many wavefronts as the chip holds at once: every wavefront takes the
 //    next tile of its class's list from a device counter until the list is
 //    used up.  The lists are ordered longest first by the host (estimated
 //    wavefront time), so the long tiles start at once and the short ones
 //    fill the end.  batch_heavy_kernel runs the lane-per-section ensembles
-//    (GM55, GQ58.3, GQ58.4: about 90 VGPRs); batch_light_kernel the rest
-//    (MT19937 tasks and sections, v = 1 GM/GQ, MRG32K3A/LFSR113, n = 0
-//    copies: under 64 VGPRs), its LDS sized by the chunk width of the
-//    MRG32K3A/LFSR113 staging (the footprint the autotuner chooses).
+//    (GM55, GQ58.3, GQ58.4), batch_reg_persistent_kernel MRG32K3A/LFSR113
+//    (its LDS sized by the chunk width of the staging, the footprint the
+//    autotuner chooses), batch_light_kernel MT19937 tasks and sections, the
+//    v = 1 GM/GQ tiles and n = 0 copies.  Kept apart, each runs at its own
+//    register count: one loop over every family holds the union of their
+//    live values (over 100 VGPRs) and halves the resident wavefronts.
 // Each tile runs the same wavefront routines as the one-generator kernels.
 //
 // The serving loop keeps one grid kernel per family (batch_reg_kernel,
@@ -315,17 +317,17 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* counter) {
 }
 
 template <int CW>
-struct LightLds {
-  static constexpr int kWords = RegStage<CW>::kWaveWords > 624 ? RegStage<CW>::kWaveWords : 624;
+struct RegLds {
+  static constexpr int kWords = RegStage<CW>::kWaveWords;
 };
 
-template <int CW>
+// MT19937 tasks and sections, v = 1 GM/GQ tiles and n = 0 copies
 __global__ void __launch_bounds__(256) batch_light_kernel(const BatchTile* __restrict__ tiles,
                                                           const uint32_t* __restrict__ order, uint32_t n,
                                                           const BatchTask* __restrict__ tasks, char* scratch,
                                                           uint32_t* counter) {
-  __shared__ __align__(16) uint32_t lds[4][LightLds<CW>::kWords];
-  uint32_t* mine = lds[(threadIdx.x >> 6) & 3];
+  __shared__ __align__(16) uint32_t mt[4][624];
+  uint32_t* mine = mt[(threadIdx.x >> 6) & 3];
   for (;;) {
     const uint32_t k = next_tile(counter);
     if (k >= n) break;
@@ -333,22 +335,6 @@ __global__ void __launch_bounds__(256) batch_light_kernel(const BatchTile* __res
     const BatchTask tk = tasks[tl.task];
     if (tk.gen == PRAND_MT19937 || tl.kind == kTileCopy) {
       mt_tile(tl, tk, scratch, mine);
-    } else if (tk.gen == PRAND_MRG32K3A || tk.gen == PRAND_LFSR113) {
-      const bool mrg = tk.gen == PRAND_MRG32K3A;
-      switch (tk.dtype) {
-        case PRAND_U32:
-          if (mrg) gen_reg<mrg::MrgGen, PRAND_U32, CW>(tl, tk, mine, scratch);
-          else gen_reg<lfsr::LfsrGen, PRAND_U32, CW>(tl, tk, mine, scratch);
-          break;
-        case PRAND_F32:
-          if (mrg) gen_reg<mrg::MrgGen, PRAND_F32, CW>(tl, tk, mine, scratch);
-          else gen_reg<lfsr::LfsrGen, PRAND_F32, CW>(tl, tk, mine, scratch);
-          break;
-        default:
-          if (mrg) gen_reg<mrg::MrgGen, PRAND_F64, CW>(tl, tk, mine, scratch);
-          else gen_reg<lfsr::LfsrGen, PRAND_F64, CW>(tl, tk, mine, scratch);
-          break;
-      }
     } else {
       switch (tk.dtype) {
         case PRAND_U32: gen_gm_dt<0, PRAND_U32>(tl, tk, scratch, nullptr); break;
@@ -357,6 +343,38 @@ __global__ void __launch_bounds__(256) batch_light_kernel(const BatchTile* __res
       }
     }
     wave_lds_sync();   // the next tile reuses this wavefront's LDS
+  }
+}
+
+// MRG32K3A/LFSR113 tiles, LDS staging chunks of CW words
+template <int CW>
+__global__ void __launch_bounds__(256) batch_reg_persistent_kernel(const BatchTile* __restrict__ tiles,
+                                                                   const uint32_t* __restrict__ order, uint32_t n,
+                                                                   const BatchTask* __restrict__ tasks,
+                                                                   char* scratch, uint32_t* counter) {
+  __shared__ __align__(16) uint32_t lds[4][RegLds<CW>::kWords];
+  uint32_t* mine = lds[(threadIdx.x >> 6) & 3];
+  for (;;) {
+    const uint32_t k = next_tile(counter);
+    if (k >= n) break;
+    const BatchTile tl = tiles[order[k]];
+    const BatchTask tk = tasks[tl.task];
+    const bool mrg = tk.gen == PRAND_MRG32K3A;
+    switch (tk.dtype) {
+      case PRAND_U32:
+        if (mrg) gen_reg<mrg::MrgGen, PRAND_U32, CW>(tl, tk, mine, scratch);
+        else gen_reg<lfsr::LfsrGen, PRAND_U32, CW>(tl, tk, mine, scratch);
+        break;
+      case PRAND_F32:
+        if (mrg) gen_reg<mrg::MrgGen, PRAND_F32, CW>(tl, tk, mine, scratch);
+        else gen_reg<lfsr::LfsrGen, PRAND_F32, CW>(tl, tk, mine, scratch);
+        break;
+      default:
+        if (mrg) gen_reg<mrg::MrgGen, PRAND_F64, CW>(tl, tk, mine, scratch);
+        else gen_reg<lfsr::LfsrGen, PRAND_F64, CW>(tl, tk, mine, scratch);
+        break;
+    }
+    wave_lds_sync();
   }
 }
 
@@ -407,25 +425,30 @@ hipError_t launch_batch_reset(uint32_t* counters, hipStream_t st) {
   return hipGetLastError();
 }
 
-uint32_t batch_persistent_blocks(int heavy, int cw, uint32_t waves, int num_cus) {
-  if (heavy) return resident_blocks(batch_heavy_kernel, waves, num_cus);
-  return cw == 16 ? resident_blocks(batch_light_kernel<16>, waves, num_cus)
-                  : resident_blocks(batch_light_kernel<32>, waves, num_cus);
+uint32_t batch_persistent_blocks(int cls, int cw, uint32_t waves, int num_cus) {
+  if (cls == kClassHeavy) return resident_blocks(batch_heavy_kernel, waves, num_cus);
+  if (cls == kClassLight) return resident_blocks(batch_light_kernel, waves, num_cus);
+  return cw == 16 ? resident_blocks(batch_reg_persistent_kernel<16>, waves, num_cus)
+                  : resident_blocks(batch_reg_persistent_kernel<32>, waves, num_cus);
 }
 
-hipError_t launch_batch_persistent(int heavy, int cw, const BatchTile* tiles, const uint32_t* order, uint32_t n,
+hipError_t launch_batch_persistent(int cls, int cw, const BatchTile* tiles, const uint32_t* order, uint32_t n,
                                    const BatchTask* tasks, char* scratch, uint32_t* counter, uint32_t waves,
                                    uint32_t blocks, hipStream_t st) {
   if (!n) return hipSuccess;
   // no more workgroups than tiles need
   blocks = std::min<uint32_t>(blocks, blocks_for(n, waves));
   const dim3 grid(blocks), block(64 * waves);
-  if (heavy)
+  if (cls == kClassHeavy)
     hipLaunchKernelGGL(batch_heavy_kernel, grid, block, 0, st, tiles, order, n, tasks, scratch, counter);
+  else if (cls == kClassLight)
+    hipLaunchKernelGGL(batch_light_kernel, grid, block, 0, st, tiles, order, n, tasks, scratch, counter);
   else if (cw == 16)
-    hipLaunchKernelGGL(batch_light_kernel<16>, grid, block, 0, st, tiles, order, n, tasks, scratch, counter);
+    hipLaunchKernelGGL(batch_reg_persistent_kernel<16>, grid, block, 0, st, tiles, order, n, tasks, scratch,
+                       counter);
   else
-    hipLaunchKernelGGL(batch_light_kernel<32>, grid, block, 0, st, tiles, order, n, tasks, scratch, counter);
+    hipLaunchKernelGGL(batch_reg_persistent_kernel<32>, grid, block, 0, st, tiles, order, n, tasks, scratch,
+                       counter);
   return hipGetLastError();
 }
 

@@ -55,10 +55,13 @@ struct BatchPlan {
   std::vector<BatchTile> tiles;
   BatchCounts n;
   uint64_t scratch_bytes = 0;
-  // tile indices of the two register classes of the persistent launch,
-  // longest (estimated wavefront time) first: light = MRG32K3A/LFSR113,
-  // v = 1 GM/GQ, MT19937, copies; heavy = v = 4 GM/GQ, GQ58.3
-  std::vector<uint32_t> order_light, order_heavy;
+  // tile indices of the register classes of the persistent launch, longest
+  // (estimated wavefront time) first: light = v = 1 GM/GQ, MT19937, copies;
+  // reg = MRG32K3A/LFSR113; heavy = v = 4 GM/GQ, GQ58.3
+  std::vector<uint32_t> order_light, order_reg, order_heavy;
+  // estimated wavefront time of each class's tiles, summed (the planner's
+  // relative cost units), indexed by kClass*
+  double cost[3] = {0, 0, 0};
 };
 
 // zero fields of a configuration replaced by the defaults
@@ -90,14 +93,15 @@ hipError_t launch_batch_mt_v1(const BatchTile* mt, uint32_t nmt, const BatchTile
 // task state moved first * kMtSection outputs on (one wavefront each)
 hipError_t launch_batch_mt_starts(const DeviceTables& T, const BatchTile* tiles, uint32_t ntiles,
                                   const BatchTask* tasks, char* scratch, hipStream_t st);
-// persistent launch: tile counters (light, heavy) cleared by a small kernel
+// persistent launch: one tile counter per class, cleared by a small kernel
 // (no memset node in a captured graph)
-constexpr int kBatchCounters = 2;
+constexpr int kClassLight = 0, kClassReg = 1, kClassHeavy = 2;
+constexpr int kBatchCounters = 3;
 hipError_t launch_batch_reset(uint32_t* counters, hipStream_t st);
-// workgroups of `waves` wavefronts of the light (heavy = 0; LDS chunk
-// width cw = 16 or 32) or heavy kernel resident on the chip at once
-uint32_t batch_persistent_blocks(int heavy, int cw, uint32_t waves, int num_cus);
-hipError_t launch_batch_persistent(int heavy, int cw, const BatchTile* tiles, const uint32_t* order, uint32_t n,
+// workgroups of `waves` wavefronts of a class's persistent kernel (reg: LDS
+// chunk width cw = 16 or 32) resident on the chip at once
+uint32_t batch_persistent_blocks(int cls, int cw, uint32_t waves, int num_cus);
+hipError_t launch_batch_persistent(int cls, int cw, const BatchTile* tiles, const uint32_t* order, uint32_t n,
                                    const BatchTask* tasks, char* scratch, uint32_t* counter, uint32_t waves,
                                    uint32_t blocks, hipStream_t st);
 // all of them on one stream: section starts, MT19937 + v = 1, the other GM/GQ, MRG32K3A/LFSR113

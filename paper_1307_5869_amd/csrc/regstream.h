@@ -7,8 +7,9 @@
 // (CW = 32: 128 bytes, 32 u32/f32 or 16 f64 values), parks them in LDS, and
 // the wavefront stores them transposed: in each store instruction the CW/4
 // consecutive lanes of a group write the 16-byte pieces of one chunk (CW = 32:
-// eight whole 128-byte lines per instruction).  Rounds run while every live
-// lane still has a full chunk to write; the rest of each run is stored lane
+// eight whole 128-byte lines per instruction).  Rounds run while any lane
+// still has a full chunk to write (a lane whose run is shorter sits out the
+// later rounds); the rest of each run, fewer than one chunk, is stored lane
 // by lane.
 //
 // regstream_wave() is the wavefront routine shared by the many-stream kernel
@@ -57,42 +58,49 @@ __device__ __forceinline__ void regstream_wave(uint32_t* rows, bool live, const 
     if (kJump && start) G::jump(st, start, ladder);
   }
   typename G::Regs r = G::load(st);
-  // full chunks every live lane can still write (wavefront minimum)
-  uint64_t my_rounds = live ? len / per : ~0ull;
+  // full chunks of this lane, and the most any lane of the wavefront has:
+  // round rd stores the chunks of the lanes with rd < their own count, so
+  // lanes of uneven lengths (the short last section of a task) keep the
+  // transposed stores for all their full chunks
+  const uint64_t my_rounds = (live && coalesce) ? len / per : 0;
+  uint64_t rounds = my_rounds;
   for (int o = 1; o < 64; o <<= 1) {
-    const uint64_t other = __shfl_xor(my_rounds, o);
-    my_rounds = other < my_rounds ? other : my_rounds;
+    const uint64_t other = __shfl_xor(rounds, o);
+    rounds = other > rounds ? other : rounds;
   }
-  const uint64_t rounds = (my_rounds == ~0ull || !coalesce) ? 0 : my_rounds;
   if (rounds) {
     // destination of piece (lane % kPieces) of each source lane's chunk, one
-    // per store instruction; null for dead sources
+    // per store instruction, and that source lane's chunk count
     char* const mine = live ? (char*)out : nullptr;
     char* dst[kPieces];
+    uint64_t src_rounds[kPieces];
 #pragma unroll
     for (int i = 0; i < kPieces; i++) {
       const int src = i * (64 / kPieces) + lane / kPieces;
       char* b = (char*)__shfl((unsigned long long)mine, src);
       dst[i] = b ? b + 16 * (lane % kPieces) : nullptr;
+      src_rounds[i] = __shfl(my_rounds, src);
     }
     uint32_t* row = rows + lane * RegStage<CW>::kRowWords;
     for (uint64_t rd = 0; rd < rounds; rd++) {
+      if (rd < my_rounds) {
 #pragma unroll
-      for (int q = 0; q < kPieces; q++) {
-        uint4 v;
-        if (DT == PRAND_F64) {
-          const double a = G::f64(G::next(r)), b = G::f64(G::next(r));
-          const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
-          v = make_uint4((uint32_t)ua, (uint32_t)(ua >> 32), (uint32_t)ub, (uint32_t)(ub >> 32));
-        } else if (DT == PRAND_F32) {
-          const uint32_t a = G::next(r), b = G::next(r), c = G::next(r), d = G::next(r);
-          v = make_uint4(__float_as_uint((float)(a >> 8) * 0x1p-24f), __float_as_uint((float)(b >> 8) * 0x1p-24f),
-                         __float_as_uint((float)(c >> 8) * 0x1p-24f), __float_as_uint((float)(d >> 8) * 0x1p-24f));
-        } else {
-          const uint32_t a = G::next(r), b = G::next(r), c = G::next(r), d = G::next(r);
-          v = make_uint4(a, b, c, d);
+        for (int q = 0; q < kPieces; q++) {
+          uint4 v;
+          if (DT == PRAND_F64) {
+            const double a = G::f64(G::next(r)), b = G::f64(G::next(r));
+            const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+            v = make_uint4((uint32_t)ua, (uint32_t)(ua >> 32), (uint32_t)ub, (uint32_t)(ub >> 32));
+          } else if (DT == PRAND_F32) {
+            const uint32_t a = G::next(r), b = G::next(r), c = G::next(r), d = G::next(r);
+            v = make_uint4(__float_as_uint((float)(a >> 8) * 0x1p-24f), __float_as_uint((float)(b >> 8) * 0x1p-24f),
+                           __float_as_uint((float)(c >> 8) * 0x1p-24f), __float_as_uint((float)(d >> 8) * 0x1p-24f));
+          } else {
+            const uint32_t a = G::next(r), b = G::next(r), c = G::next(r), d = G::next(r);
+            v = make_uint4(a, b, c, d);
+          }
+          *(uint4*)(row + 4 * q) = v;
         }
-        *(uint4*)(row + 4 * q) = v;
       }
       wave_lds_sync();
       const uint64_t adv = rd * per * es;
@@ -100,13 +108,13 @@ __device__ __forceinline__ void regstream_wave(uint32_t* rows, bool live, const 
       for (int i = 0; i < kPieces; i++) {
         const int src = i * (64 / kPieces) + lane / kPieces;
         const uint4 v = *(const uint4*)(rows + src * RegStage<CW>::kRowWords + 4 * (lane % kPieces));
-        if (dst[i]) *(uint4*)(dst[i] + adv) = v;
+        if (dst[i] && rd < src_rounds[i]) *(uint4*)(dst[i] + adv) = v;
       }
       wave_lds_sync();
     }
   }
   if (live) {
-    for (uint64_t i = rounds * per; i < len; i++) {
+    for (uint64_t i = my_rounds * per; i < len; i++) {
       const uint32_t w = G::next(r);
       put_word<DT>(out, i, w, DT == PRAND_F64 ? G::f64(w) : 0.0);
     }

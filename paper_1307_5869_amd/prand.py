@@ -67,7 +67,7 @@ class BatchConfig(ctypes.Structure):
     """struct prand_batch_config (zeros select the defaults)"""
     _fields_ = [("waves_per_block", ctypes.c_uint32), ("reg_section", ctypes.c_uint32),
                 ("gm_section", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
-                ("lds_chunk_words", ctypes.c_uint32)]
+                ("lds_chunk_words", ctypes.c_uint32), ("overlap", ctypes.c_uint32)]
 
 
 

@@ -59,8 +59,8 @@ def mixed_specs():
     return specs
 
 
-@pytest.mark.parametrize("cfg", [None, (2, 512, 1024, 1, 16), (4, 8192, 16384, 0, 32), (1, 32, 32, 1, 16),
-                                 (4, 2048, 4096, 1, 16)])
+@pytest.mark.parametrize("cfg", [None, (2, 512, 1024, 1, 16, 0), (4, 8192, 16384, 0, 32, 1), (1, 32, 32, 1, 16, 1),
+                                 (4, 2048, 4096, 1, 16, 0), (4, 2048, 4096, 1, 32, 1)])
 def test_batch_matches_oracle(ctx, oracle, cfg):
     tasks, refs = make_tasks(oracle, mixed_specs())
     conf = P.BatchConfig(*cfg) if cfg else None
