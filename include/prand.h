@@ -187,7 +187,12 @@ int prand_generate_array(prand_ctx* ctx, int gen, void* h_state, int dtype, void
    stream): d_out[s * n_per_stream + i] = output i of stream s, for s < count;
    each d_states[s] is advanced by n_per_stream in place.  PRAND_ERANGE when
    n_per_stream > 2^40 or the output exceeds 2^50 bytes.  Asynchronous on
-   `stream`. */
+   `stream`, except that the first MRG32K3A or LFSR113 call with a given
+   section length (a function of count and n_per_stream) builds that length's
+   section-start table (up to 32 KB of device memory, kept until the context
+   is destroyed; a blocking copy), unless `stream` is being captured into a
+   graph: calls under capture, and calls past 64 such lengths per generator,
+   jump every section through the ladder instead (same outputs, more work). */
 int prand_generate_streams(prand_ctx* ctx, int gen, void* d_states, uint32_t count,
                            uint64_t n_per_stream, int dtype, void* d_out, void* stream);
 

@@ -140,24 +140,76 @@ hipError_t launch_jump(prand_ctx* c, int gen, void* states, uint32_t count, cons
   }
 }
 
-// many-stream generation; sin/sout may alias (sections of a stream never
-// straddle a wavefront)
-hipError_t launch_streams(prand_ctx* c, int gen, const void* sin, void* sout, uint32_t count, uint64_t n,
-                          int dtype, void* out, hipStream_t st) {
-  if (gen == PRAND_MRG32K3A || gen == PRAND_LFSR113) {
-    // enough lanes to fill the chip: up to 64 sections per stream, each at
-    // least 64 outputs long, section starts 16-byte aligned
-    int nsec_log2 = 0;
+// The section-start table of MRG32K3A/LFSR113 (k = 0/1) for section length
+// seclen: looked up, or built on the host and uploaded when `may_create`
+// (an allocation and a blocking copy, once per length; not while the stream
+// is being captured, and at most kMaxSectionTables lengths per generator).
+// Null when there is none: the kernel then jumps through the ladder.
+constexpr size_t kMaxSectionTables = 64;
+
+const uint32_t* section_table(prand_ctx* c, int k, uint64_t seclen, hipStream_t st, bool may_create) {
+  std::lock_guard<std::mutex> lk(c->sec_mu);
+  for (const auto& t : c->sec_tabs[k])
+    if (t.first == seclen) return t.second;
+  if (!may_create || c->sec_tabs[k].size() >= kMaxSectionTables) return nullptr;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  const size_t words = (size_t)kSectionTableRows * (k == 0 ? kMrgSectionWords : kLfsrSectionWords);
+  std::vector<uint32_t> h(words);
+  if (k == 0) build_mrg_section_table(seclen, h.data());
+  else build_lfsr_section_table(seclen, h.data());
+  uint32_t* d = nullptr;
+  if (hipMalloc((void**)&d, words * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (hipMemcpy(d, h.data(), words * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(d);
+    return nullptr;
+  }
+  c->sec_tabs[k].push_back({seclen, d});
+  return d;
+}
+
+// sections per stream (log2) and section length of the many-stream
+// MRG32K3A/LFSR113 kernel: up to 64 sections per stream, section starts
+// 16-byte aligned.  With a section-start table a start costs one matrix
+// application, so streams are cut into as many sections of at least 256
+// outputs as fit in 2^22 lanes (more, shorter sections measured faster: the
+// 64 runs of a wavefront then lie close together in the output); with ladder
+// jumps a start costs one application per set bit of its distance, so the
+// cut stops at 2^19 lanes and sections of at least 64 outputs.
+void section_plan(uint32_t count, uint64_t n, bool table, int& nsec_log2, uint64_t& seclen) {
+  nsec_log2 = 0;
+  if (table) {
+    while (nsec_log2 < 6 && ((uint64_t)count << (nsec_log2 + 1)) <= (1ull << 22) && (n >> (nsec_log2 + 1)) >= 256)
+      nsec_log2++;
+  } else {
     while (nsec_log2 < 6 && ((uint64_t)count << nsec_log2) < (1ull << 19) && (n >> (nsec_log2 + 1)) >= 64)
       nsec_log2++;
-    uint64_t seclen = (n + (1ull << nsec_log2) - 1) >> nsec_log2;
-    seclen = (seclen + 3) & ~3ull;
-    if (seclen == 0) seclen = 4;
+  }
+  seclen = (n + (1ull << nsec_log2) - 1) >> nsec_log2;
+  seclen = (seclen + 3) & ~3ull;
+  if (seclen == 0) seclen = 4;
+}
+
+// many-stream generation; sin/sout may alias (sections of a stream never
+// straddle a wavefront).  may_alloc: a section-start table may be built.
+hipError_t launch_streams(prand_ctx* c, int gen, const void* sin, void* sout, uint32_t count, uint64_t n,
+                          int dtype, void* out, hipStream_t st, bool may_alloc) {
+  if (gen == PRAND_MRG32K3A || gen == PRAND_LFSR113) {
+    const int k = gen == PRAND_MRG32K3A ? 0 : 1;
+    int nsec_log2;
+    uint64_t seclen;
+    section_plan(count, n, true, nsec_log2, seclen);
+    const uint32_t* tab = nsec_log2 ? section_table(c, k, seclen, st, may_alloc) : nullptr;
+    if (!tab) section_plan(count, n, false, nsec_log2, seclen);
     if (gen == PRAND_MRG32K3A)
       return launch_mrg_generate(c->T, (const MrgState*)sin, (MrgState*)sout, count, n, nsec_log2, seclen, dtype,
-                                 out, st);
+                                 out, tab, st);
     return launch_lfsr_generate(c->T, (const LfsrState*)sin, (LfsrState*)sout, count, n, nsec_log2, seclen, dtype,
-                                out, st);
+                                out, tab, st);
   }
   if (gen == PRAND_MT19937) {
     if (sin != sout) {
@@ -263,13 +315,14 @@ int prand::generate_host_state(prand_ctx* c, int gen, void* h_state, int dtype, 
   js.per_stream = 1;
   if (e == hipSuccess) e = launch_jump(c, gen, d_states, (uint32_t)nst, js, d_base, st);
   if (e == hipSuccess && full)
-    e = launch_streams(c, gen, d_states, d_states, (uint32_t)full, seclen, dtype, d_out, st);
+    e = launch_streams(c, gen, d_states, d_states, (uint32_t)full, seclen, dtype, d_out, st, !scratch);
   if (e == hipSuccess && part) {
     void* sp = (char*)d_states + full * sb;
-    e = launch_streams(c, gen, sp, sp, 1, part, dtype, (char*)d_out + full * seclen * es, st);
+    e = launch_streams(c, gen, sp, sp, 1, part, dtype, (char*)d_out + full * seclen * es, st, !scratch);
   }
   void* last = (char*)d_states + nb * sb;
-  if (e == hipSuccess) e = launch_streams(c, gen, last, last, 1, n - T, dtype, (char*)d_out + T * es, st);
+  if (e == hipSuccess)
+    e = launch_streams(c, gen, last, last, 1, n - T, dtype, (char*)d_out + T * es, st, !scratch);
   if (e == hipSuccess) e = hipMemcpyAsync(h_state, last, sb, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (!scratch) {
@@ -379,6 +432,8 @@ int prand_ctx_destroy(prand_ctx* c) {
   (void)hipFree(c->T.mtinv);
   (void)hipFree(c->T.defaults);
   (void)hipFree(c->scratch);
+  for (auto& v : c->sec_tabs)
+    for (auto& t : v) (void)hipFree(t.second);
   delete c;
   return PRAND_OK;
 }
@@ -526,7 +581,7 @@ int prand_generate_streams(prand_ctx* c, int gen, void* d_states, uint32_t count
   if (n > (1ull << 40) || (unsigned __int128)count * n * elem_bytes(dtype) > ((unsigned __int128)1 << 50))
     return PRAND_ERANGE;
   DeviceGuard g(c->device);
-  hipError_t e = launch_streams(c, gen, d_states, d_states, count, n, dtype, d_out, (hipStream_t)stream);
+  hipError_t e = launch_streams(c, gen, d_states, d_states, count, n, dtype, d_out, (hipStream_t)stream, true);
   return e == hipSuccess ? PRAND_OK : hipfail(c, e);
 }
 

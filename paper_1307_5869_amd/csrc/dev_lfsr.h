@@ -65,6 +65,31 @@ struct LfsrGen {
     return o;
   }
   __device__ static void jump(LfsrState& st, uint64_t d, const uint32_t* ladder) { jump_state(ladder, st.z, &d, 1); }
+  // one jump matrix per component (columns of T_c^d), 4 x 32 words, 16-byte
+  // aligned: the columns come in as 16-byte loads, and column j joins the
+  // result through bit j of the word spread to a mask (one sign-extending
+  // bit-field extract) and one three-input op r ^ (mask & column)
+  static constexpr int kSectionWords = 128;
+  __device__ static void apply(LfsrState& st, const uint32_t* M) {
+    const uint4* m4 = (const uint4*)M;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const uint32_t v = st.z[c];
+      uint32_t r = 0;
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        const uint4 col = m4[c * 8 + q];
+        const uint32_t cw[4] = {col.x, col.y, col.z, col.w};
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int j = 4 * q + t;
+          const uint32_t mask = (uint32_t)((int32_t)(v << (31 - j)) >> 31);
+          r = __builtin_amdgcn_bitop3_b32(r, mask, cw[t], 0x78);
+        }
+      }
+      st.z[c] = r;
+    }
+  }
   __device__ static uint32_t next(Regs& r) { return step(r); }
   __device__ static double f64(uint32_t w) { return (double)w * 0x1p-32; }
 };

@@ -115,6 +115,12 @@ struct MrgGen {
     return o;
   }
   __device__ static void jump(MrgState& st, uint64_t d, const uint32_t* ladder) { jump_state(ladder, st.x, st.y, &d, 1); }
+  // one jump matrix pair (A^d mod m1, B^d mod m2), 18 words
+  static constexpr int kSectionWords = 18;
+  __device__ static void apply(MrgState& st, const uint32_t* M) {
+    mat3_apply<209u>(M, st.x);
+    mat3_apply<22853u>(M + 9, st.y);
+  }
   __device__ static uint32_t next(Regs& r) { return step(r); }
   __device__ static double f64(uint32_t z) { return (double)z * kNorm; }
 };

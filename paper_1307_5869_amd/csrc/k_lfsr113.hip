@@ -41,10 +41,12 @@ __global__ void __launch_bounds__(256) lfsr_jump_kernel(LfsrState* __restrict__ 
 
 }  // namespace
 
+static_assert(LfsrGen::kSectionWords == kLfsrSectionWords, "section-start table row size");
+
 hipError_t launch_lfsr_generate(const DeviceTables& T, const LfsrState* sin, LfsrState* sout, uint32_t count,
                                 uint64_t n, int nsec_log2, uint64_t seclen, int dtype, void* out,
-                                hipStream_t st) {
-  return launch_regstream<LfsrGen>(sin, sout, count, n, nsec_log2, seclen, dtype, out, T.lfsr, st);
+                                const uint32_t* sectab, hipStream_t st) {
+  return launch_regstream<LfsrGen>(sin, sout, count, n, nsec_log2, seclen, dtype, out, T.lfsr, sectab, st);
 }
 
 hipError_t launch_lfsr_jump(const DeviceTables& T, LfsrState* states, uint32_t count, const JumpSpec& js,

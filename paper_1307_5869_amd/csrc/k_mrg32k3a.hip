@@ -1,12 +1,11 @@
 // MRG32K3A on gfx950: X_{n+1} = A X_n mod m1, Y_{n+1} = B Y_n mod m2 (paper,
 // section on jumping ahead for MRG32K3A), output z = (x - y) mod m1 in
 // [1, m1].  One lane owns one (stream, section) pair and keeps the six state
-// words in registers (the store path is shared, see regstream.h).  The recurrence runs in exact double arithmetic: every
-// product is an integer below 2^53, so fma + floor(p / m) with a +-1
-// correction gives the exact residue at full FP64 rate (gfx950 issues FP64
-// FMA at the FP32 rate, integer 32x32 multiplies at a quarter of it).
+// words in registers (the store path is shared, see regstream.h); the
+// recurrence runs in exact double arithmetic on centred residues (dev_mrg.h).
 // Jumps apply A^(2^b), B^(2^b) from the context ladder for each set bit b of
-// the distance (binary decomposition, O(log n)).
+// the distance (binary decomposition, O(log n)); the sections of the
+// many-stream kernel start from one application of a section-start table.
 #include "dev_mrg.h"
 #include "regstream.h"
 
@@ -46,10 +45,12 @@ __global__ void __launch_bounds__(256) mrg_jump_kernel(MrgState* __restrict__ st
 
 }  // namespace
 
+static_assert(MrgGen::kSectionWords == kMrgSectionWords, "section-start table row size");
+
 hipError_t launch_mrg_generate(const DeviceTables& T, const MrgState* sin, MrgState* sout, uint32_t count,
                                uint64_t n, int nsec_log2, uint64_t seclen, int dtype, void* out,
-                               hipStream_t st) {
-  return launch_regstream<MrgGen>(sin, sout, count, n, nsec_log2, seclen, dtype, out, T.mrg, st);
+                               const uint32_t* sectab, hipStream_t st) {
+  return launch_regstream<MrgGen>(sin, sout, count, n, nsec_log2, seclen, dtype, out, T.mrg, sectab, st);
 }
 
 hipError_t launch_mrg_jump(const DeviceTables& T, MrgState* states, uint32_t count, const JumpSpec& js,

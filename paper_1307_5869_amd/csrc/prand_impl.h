@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <cstdint>
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "prand.h"
 
@@ -113,15 +115,16 @@ struct JumpSpec {
   const void* mt_top = nullptr;
 };
 
+// sectab: the section-start table of seclen, or null (ladder jumps)
 hipError_t launch_mrg_generate(const DeviceTables& T, const MrgState* sin, MrgState* sout, uint32_t count,
                                uint64_t n, int nsec_log2, uint64_t seclen, int dtype, void* out,
-                               hipStream_t st);
+                               const uint32_t* sectab, hipStream_t st);
 hipError_t launch_mrg_jump(const DeviceTables& T, MrgState* states, uint32_t count, const JumpSpec& js,
                            const MrgState* base, hipStream_t st);
 
 hipError_t launch_lfsr_generate(const DeviceTables& T, const LfsrState* sin, LfsrState* sout, uint32_t count,
                                 uint64_t n, int nsec_log2, uint64_t seclen, int dtype, void* out,
-                                hipStream_t st);
+                                const uint32_t* sectab, hipStream_t st);
 hipError_t launch_lfsr_jump(const DeviceTables& T, LfsrState* states, uint32_t count, const JumpSpec& js,
                             const LfsrState* base, hipStream_t st);
 
@@ -145,6 +148,16 @@ struct HostTables {
 };
 void build_mrg_ladder(uint32_t* out);
 void build_lfsr_ladder(uint32_t* out);
+// Section-start tables of the many-stream MRG32K3A/LFSR113 kernels: for a
+// section length L, row j - 1 (j = 1 .. kSectionTableRows) holds the jump by
+// j L (MRG32K3A: A^(jL) mod m1 then B^(jL) mod m2, 18 words; LFSR113: the
+// columns of T_c^(jL) for c = 0..3, 128 words), so section j of a stream
+// starts from one matrix application instead of one per set bit of j L.
+constexpr int kSectionTableRows = 63;
+constexpr int kMrgSectionWords = 18;
+constexpr int kLfsrSectionWords = 128;
+void build_mrg_section_table(uint64_t seclen, uint32_t* out);
+void build_lfsr_section_table(uint64_t seclen, uint32_t* out);
 void build_gm_ladders(uint64_t* out);
 
 // the calling thread's current device is set to `dev` for the guard's life
@@ -173,6 +186,10 @@ struct prand_ctx {
   std::mutex mu;          // guards mt_ready and the host-call scratch
   void* scratch = nullptr;
   int last_hip = 0;
+  // section-start tables by section length, [0] MRG32K3A, [1] LFSR113
+  // (built on first use, immutable afterwards, freed with the context)
+  std::mutex sec_mu;
+  std::vector<std::pair<uint64_t, uint32_t*>> sec_tabs[2];
 };
 
 namespace prand {

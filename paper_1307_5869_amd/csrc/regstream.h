@@ -36,18 +36,21 @@ __device__ __forceinline__ void put_word(void* out, uint64_t i, uint32_t w, doub
 }
 
 // One lane's section: live lanes start from *in (jumped `start` outputs
-// ahead), write `len` values at `out` (element pointer of the run) and, when
+// ahead: by the jump matrix sec_mat when it is given, else through the
+// ladder), write `len` values at `out` (element pointer of the run) and, when
 // `sout` is set, store the advanced state there.  `coalesce`: every run start
 // is 16-byte aligned (transposed stores allowed).  All 64 lanes must call.
 // kJump = false: the caller guarantees start == 0 (no jump code is built).
 //
 // G: State, Regs, static load(State) -> Regs, static save(Regs) -> State,
 // static jump(State&, uint64_t distance, const uint32_t* ladder),
+// static apply(State&, const uint32_t* jump matrix),
 // static next(Regs&) -> uint32_t word, static f64(uint32_t) -> double.
 template <class G, int DT, int CW, bool kJump = true>
 __device__ __forceinline__ void regstream_wave(uint32_t* rows, bool live, const typename G::State* in, uint64_t start,
                                                uint64_t len, void* out, typename G::State* sout, bool coalesce,
-                                               const uint32_t* __restrict__ ladder) {
+                                               const uint32_t* __restrict__ ladder,
+                                               const uint32_t* __restrict__ sec_mat = nullptr) {
   constexpr int kPieces = CW / 4;                            // 16-byte pieces per chunk
   constexpr int per = (DT == PRAND_F64) ? CW / 2 : CW;        // values per chunk
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
@@ -55,7 +58,8 @@ __device__ __forceinline__ void regstream_wave(uint32_t* rows, bool live, const 
   typename G::State st = {};
   if (live) {
     st = *in;
-    if (kJump && start) G::jump(st, start, ladder);
+    if (kJump && sec_mat) G::apply(st, sec_mat);
+    else if (kJump && start) G::jump(st, start, ladder);
   }
   typename G::Regs r = G::load(st);
   // full chunks of this lane, and the most any lane of the wavefront has:
@@ -126,11 +130,13 @@ __device__ __forceinline__ void regstream_wave(uint32_t* rows, bool live, const 
 // gid >> nsec_log2; the sections of a stream cover
 // [j * seclen, min((j + 1) * seclen, n)) and sit in one wavefront (nsec <= 64),
 // so the state read of every section precedes the write-back of the last.
+// With sectab (the section-start table of seclen), section j > 0 starts from
+// row j - 1 of it, else from ladder jumps.
 template <class G, int DT, int CW>
 __global__ void __launch_bounds__(256) regstream_kernel(const typename G::State* sin, typename G::State* sout,
                                                         uint32_t count, uint64_t n, int nsec_log2, uint64_t seclen,
                                                         void* __restrict__ out, const uint32_t* __restrict__ ladder,
-                                                        int coalesce) {
+                                                        const uint32_t* __restrict__ sectab, int coalesce) {
   __shared__ __align__(16) uint32_t stage[4][RegStage<CW>::kWaveWords];
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t nsec = 1ull << nsec_log2;
@@ -141,8 +147,9 @@ __global__ void __launch_bounds__(256) regstream_kernel(const typename G::State*
   const uint64_t len = live ? ((j == jlast) ? n - start : seclen) : 0;
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
   void* o = (char*)out + (s * n + start) * es;
+  const uint32_t* sec_mat = (sectab && j) ? sectab + (j - 1) * G::kSectionWords : nullptr;
   regstream_wave<G, DT, CW>(stage[threadIdx.x >> 6], live, sin + (live ? s : 0), start, len, o,
-                            (live && j == jlast) ? sout + s : nullptr, coalesce != 0, ladder);
+                            (live && j == jlast) ? sout + s : nullptr, coalesce != 0, ladder, sec_mat);
 }
 
 // CW of the register-state kernels: 32 unless PRAND_REG_CHUNK_WORDS=16
@@ -158,7 +165,7 @@ inline int regstream_chunk_words() {
 template <class G, int CW>
 hipError_t launch_regstream_cw(const typename G::State* sin, typename G::State* sout, uint32_t count, uint64_t n,
                                int nsec_log2, uint64_t seclen, int dtype, void* out, const uint32_t* ladder,
-                               hipStream_t st) {
+                               const uint32_t* sectab, hipStream_t st) {
   const uint64_t lanes = (uint64_t)count << nsec_log2;
   const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
   // transposed 16-byte stores need every section start 16-byte aligned
@@ -167,15 +174,15 @@ hipError_t launch_regstream_cw(const typename G::State* sin, typename G::State* 
   switch (dtype) {
     case PRAND_U32:
       hipLaunchKernelGGL((regstream_kernel<G, PRAND_U32, CW>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
-                         nsec_log2, seclen, out, ladder, coalesce);
+                         nsec_log2, seclen, out, ladder, sectab, coalesce);
       break;
     case PRAND_F32:
       hipLaunchKernelGGL((regstream_kernel<G, PRAND_F32, CW>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
-                         nsec_log2, seclen, out, ladder, coalesce);
+                         nsec_log2, seclen, out, ladder, sectab, coalesce);
       break;
     default:
       hipLaunchKernelGGL((regstream_kernel<G, PRAND_F64, CW>), dim3(blocks), dim3(256), 0, st, sin, sout, count, n,
-                         nsec_log2, seclen, out, ladder, coalesce);
+                         nsec_log2, seclen, out, ladder, sectab, coalesce);
       break;
   }
   return hipGetLastError();
@@ -184,10 +191,10 @@ hipError_t launch_regstream_cw(const typename G::State* sin, typename G::State* 
 template <class G>
 hipError_t launch_regstream(const typename G::State* sin, typename G::State* sout, uint32_t count, uint64_t n,
                             int nsec_log2, uint64_t seclen, int dtype, void* out, const uint32_t* ladder,
-                            hipStream_t st) {
+                            const uint32_t* sectab, hipStream_t st) {
   if (regstream_chunk_words() == 16)
-    return launch_regstream_cw<G, 16>(sin, sout, count, n, nsec_log2, seclen, dtype, out, ladder, st);
-  return launch_regstream_cw<G, 32>(sin, sout, count, n, nsec_log2, seclen, dtype, out, ladder, st);
+    return launch_regstream_cw<G, 16>(sin, sout, count, n, nsec_log2, seclen, dtype, out, ladder, sectab, st);
+  return launch_regstream_cw<G, 32>(sin, sout, count, n, nsec_log2, seclen, dtype, out, ladder, sectab, st);
 }
 
 }  // namespace prand

@@ -40,6 +40,47 @@ void build_mrg_ladder(uint32_t* out) {
   }
 }
 
+namespace {
+void mat3_mul(const uint64_t* a, const uint64_t* b, uint64_t* r, uint64_t m) {
+  uint64_t t[9];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      u128 acc = 0;
+      for (int k = 0; k < 3; k++) acc += (u128)a[3 * i + k] * b[3 * k + j];
+      t[3 * i + j] = (uint64_t)(acc % m);
+    }
+  std::memcpy(r, t, sizeof t);
+}
+// a^e mod m for a 3x3 matrix
+void mat3_pow(const uint64_t* a, uint64_t e, uint64_t* r, uint64_t m) {
+  uint64_t p[9], acc[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  std::memcpy(p, a, sizeof p);
+  for (; e; e >>= 1) {
+    if (e & 1) mat3_mul(acc, p, acc, m);
+    mat3_sqr(p, p, m);
+  }
+  std::memcpy(r, acc, sizeof acc);
+}
+}  // namespace
+
+void build_mrg_section_table(uint64_t seclen, uint32_t* out) {
+  const uint64_t A[9] = {0, kMrgA12, kMrgM1 - kMrgA13n, 1, 0, 0, 0, 1, 0};
+  const uint64_t B[9] = {kMrgA21, 0, kMrgM2 - kMrgA23n, 1, 0, 0, 0, 1, 0};
+  uint64_t SA[9], SB[9], MA[9], MB[9];
+  mat3_pow(A, seclen, SA, kMrgM1);
+  mat3_pow(B, seclen, SB, kMrgM2);
+  std::memcpy(MA, SA, sizeof MA);
+  std::memcpy(MB, SB, sizeof MB);
+  for (int j = 1; j < kSectionTableRows + 1; j++) {
+    for (int i = 0; i < 9; i++) {
+      out[(j - 1) * 18 + i] = (uint32_t)MA[i];
+      out[(j - 1) * 18 + 9 + i] = (uint32_t)MB[i];
+    }
+    mat3_mul(SA, MA, MA, kMrgM1);
+    mat3_mul(SB, MB, MB, kMrgM2);
+  }
+}
+
 // ----------------------------------------------------------------- LFSR113
 namespace {
 constexpr int kLfP[4] = {31, 29, 28, 25};
@@ -70,6 +111,32 @@ void build_lfsr_ladder(uint32_t* out) {
       uint32_t sq[32];
       for (int j = 0; j < 32; j++) sq[j] = f2_apply(cols, cols[j]);
       std::memcpy(cols, sq, sizeof sq);
+    }
+  }
+}
+
+void build_lfsr_section_table(uint64_t seclen, uint32_t* out) {
+  for (int c = 0; c < 4; c++) {
+    // S = T_c^seclen by squaring; columns of the composition P o Q are P
+    // applied to the columns of Q
+    uint32_t p[32], s[32], m[32], t[32];
+    for (int j = 0; j < 32; j++) {
+      p[j] = lfsr_word_step(1u << j, c);
+      s[j] = 1u << j;
+    }
+    for (uint64_t e = seclen; e; e >>= 1) {
+      if (e & 1) {
+        for (int j = 0; j < 32; j++) t[j] = f2_apply(p, s[j]);
+        std::memcpy(s, t, sizeof t);
+      }
+      for (int j = 0; j < 32; j++) t[j] = f2_apply(p, p[j]);
+      std::memcpy(p, t, sizeof t);
+    }
+    std::memcpy(m, s, sizeof m);
+    for (int j = 1; j < kSectionTableRows + 1; j++) {
+      std::memcpy(out + ((size_t)(j - 1) * 4 + c) * 32, m, sizeof m);
+      for (int i = 0; i < 32; i++) t[i] = f2_apply(s, m[i]);
+      std::memcpy(m, t, sizeof t);
     }
   }
 }

@@ -62,7 +62,8 @@ def test_seed_and_default_match_oracle(ctx, oracle, gen):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("gen", GENS)
-@pytest.mark.parametrize("count,n", [(1, 1), (3, 3), (37, 1000), (5, 4101), (64, 257), (33, 4132), (130, 8192)])
+@pytest.mark.parametrize("count,n", [(1, 1), (3, 3), (37, 1000), (5, 4101), (64, 257), (33, 4132), (130, 8192),
+                                     (7, 20000)])
 def test_generate_streams(ctx, oracle, gen, dtype, count, n):
     states = [oracle.seed(gen, 1000 + 7 * i) for i in range(count)]
     got, got_states = gpu_generate_streams(ctx, gen, states, n, dtype)
@@ -244,3 +245,39 @@ def test_mrg32k3a_block_split_4096_streams_full(ctx, oracle):
         s2 = st.copy()
         assert np.array_equal(U[k], oracle.generate(gen, st, n)), k
         assert np.array_equal(F[k], oracle.generate(gen, s2, n, P.F64)), k
+
+
+@pytest.mark.parametrize("gen", [P.MRG32K3A, P.LFSR113])
+def test_generate_streams_captured_then_eager(ctx, oracle, gen):
+    """Many-stream generation captured into a HIP graph with a section length
+    no earlier call used (no section-start table may be built under capture:
+    the sections jump through the ladder), replayed three times with eager
+    work and synchronisations between the replays; then the same call made
+    eagerly (which builds and uses the table).  Every replay and the eager
+    call continue each stream exactly as the oracle does."""
+    count, n = 9, 64 * 331 + 5
+    states = [oracle.init_stream(gen, 0, 1000 + i) for i in range(count)]
+    d = to_dev(states)
+    out = torch.empty(count * n, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ctx.generate_streams(gen, d, count, n, P.U32, out, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.fill_(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        ref = np.concatenate([oracle.generate(gen, st, n) for st in states])
+        np.testing.assert_array_equal(out_np(out, P.U32), ref, err_msg=f"replay {rep}")
+        got = from_dev(d, gen)
+        for i in range(count):
+            assert np.array_equal(got[i], states[i]), (rep, i)
+    del g
+    ctx.generate_streams(gen, d, count, n, P.U32, out)
+    torch.cuda.synchronize()
+    ref = np.concatenate([oracle.generate(gen, st, n) for st in states])
+    np.testing.assert_array_equal(out_np(out, P.U32), ref, err_msg="eager after capture")
