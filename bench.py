@@ -179,21 +179,28 @@ def main():
         b.synchronize()
         write_probe = {"bytes": out.numel() * 4, "ms": round(a.elapsed_time(b), 4),
                        "GBs": out.numel() * 4 / (a.elapsed_time(b) * 1e-3) / 1e9}
-        # outside the timed region: every dtype for every generator, one launch each
+        # outside the timed region: every dtype for every generator, five
+        # launches each (the states advance from launch to launch); median,
+        # fastest and slowest launch
         big = torch.empty(S * N * 2, dtype=torch.int32, device=dev)
         for g in gens:
             ctx.init_streams_dev(g, P.SEQ_DEFAULT, None, ids[g], S, states, stream)
             r = {}
             for dt, name in ((P.U32, "u32"), (P.F32, "f32"), (P.F64, "f64")):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                ctx.generate_streams(g, states, S, N, dt, big, stream)
-                b.record(stream)
-                b.synchronize()
-                ms = a.elapsed_time(b)
+                evs = []
+                for _ in range(5):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    ctx.generate_streams(g, states, S, N, dt, big, stream)
+                    b.record(stream)
+                    evs.append((a, b))
+                evs[-1][1].synchronize()
+                t = sorted(a.elapsed_time(b) for a, b in evs)
+                ms = t[len(t) // 2]
                 es = 8 if dt == P.F64 else 4
-                r[name] = {"ms": round(ms, 4), "numbers_per_s": S * N / (ms * 1e-3),
-                           "write_GBs": S * N * es / (ms * 1e-3) / 1e9}
+                r[name] = {"ms": round(ms, 4), "ms_min": round(t[0], 4), "ms_max": round(t[-1], 4),
+                           "numbers_per_s": S * N / (ms * 1e-3), "write_GBs": S * N * es / (ms * 1e-3) / 1e9,
+                           "hbm_frac": S * N * es / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
             extra[P.NAMES[g]] = r
         del big
 

@@ -70,6 +70,77 @@ __device__ __forceinline__ void twist_phase(uint32_t* mt, int j0, int j1, int of
   }
 }
 
+// A twist phase out of place: words j = j0 + lane + 64 k (k < K, j < j1) of
+// the new block N from the old block O.  Phase one (kFirst) reads O[j + 397];
+// the later phases read N[j - 227], renewed by an earlier phase; word 623
+// pairs with N[0].  Nothing the phase reads is written by it.
+template <int K, bool kFirst>
+__device__ __forceinline__ void twist_phase_oop(const uint32_t* O, uint32_t* N, int j0, int j1) {
+  const int lane = threadIdx.x & 63;
+  uint32_t a[K], b[K], c[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int j = j0 + lane + 64 * k;
+    if (j < j1) {
+      a[k] = O[j];
+      b[k] = j == 623 ? N[0] : O[j + 1];
+      c[k] = kFirst ? O[j + 397] : N[j - 227];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int j = j0 + lane + 64 * k;
+    if (j < j1) N[j] = recur(a[k], b[k], c[k]);
+  }
+}
+
+// the block after O, written to N (three out-of-place phases)
+__device__ __forceinline__ void twist_oop(const uint32_t* O, uint32_t* N) {
+  twist_phase_oop<4, true>(O, N, 0, 227);
+  wave_lds_sync();
+  twist_phase_oop<4, false>(O, N, 227, 454);
+  wave_lds_sync();
+  twist_phase_oop<3, false>(O, N, 454, 624);
+  wave_lds_sync();
+}
+
+template <int DT>
+__device__ __forceinline__ void put4(char* out, int q, uint4 w) {
+  const uint32_t t0 = temper(w.x), t1 = temper(w.y), t2 = temper(w.z), t3 = temper(w.w);
+  if (DT == PRAND_U32) {
+    *(uint4*)(out + 16 * q) = make_uint4(t0, t1, t2, t3);
+  } else if (DT == PRAND_F32) {
+    *(uint4*)(out + 16 * q) = make_uint4(__float_as_uint((float)(t0 >> 8) * 0x1p-24f),
+                                         __float_as_uint((float)(t1 >> 8) * 0x1p-24f),
+                                         __float_as_uint((float)(t2 >> 8) * 0x1p-24f),
+                                         __float_as_uint((float)(t3 >> 8) * 0x1p-24f));
+  } else {
+    const double d0 = (double)t0 * 0x1p-32, d1 = (double)t1 * 0x1p-32;
+    const double d2 = (double)t2 * 0x1p-32, d3 = (double)t3 * 0x1p-32;
+    *(double2*)(out + 32 * q) = make_double2(d0, d1);
+    *(double2*)(out + 32 * q + 16) = make_double2(d2, d3);
+  }
+}
+
+// Two consecutive blocks A then B written out as 16-byte pieces (312 pieces
+// of four words, five per lane): 1248 words, 39 whole 128-byte lines when
+// `out` is line-aligned.  out 16-byte aligned; A, B 16-byte aligned LDS.
+template <int DT>
+__device__ __forceinline__ void write_pair(const uint32_t* A, const uint32_t* B, char* out) {
+  const int lane = threadIdx.x & 63;
+  uint4 w[5];
+#pragma unroll
+  for (int r = 0; r < 5; r++) {
+    const int q = lane + 64 * r;
+    if (q < 312) w[r] = q < 156 ? *(const uint4*)(A + 4 * q) : *(const uint4*)(B + 4 * (q - 156));
+  }
+#pragma unroll
+  for (int r = 0; r < 5; r++) {
+    const int q = lane + 64 * r;
+    if (q < 312) put4<DT>(out, q, w[r]);
+  }
+}
+
 // A whole renewed block written out as 16-byte pieces: lane l tempers the
 // words 4q .. 4q + 3 for q = l, l + 64, l + 128 (q < 156) and stores them at
 // out + 16 q (u32/f32) or out + 32 q (f64, two pieces).  `out` is 16-byte
@@ -86,21 +157,7 @@ __device__ __forceinline__ void write_block(const uint32_t* mt, char* out) {
 #pragma unroll
   for (int r = 0; r < 3; r++) {
     const int q = lane + 64 * r;
-    if (q >= 156) continue;
-    const uint32_t t0 = temper(w[r].x), t1 = temper(w[r].y), t2 = temper(w[r].z), t3 = temper(w[r].w);
-    if (DT == PRAND_U32) {
-      *(uint4*)(out + 16 * q) = make_uint4(t0, t1, t2, t3);
-    } else if (DT == PRAND_F32) {
-      *(uint4*)(out + 16 * q) = make_uint4(__float_as_uint((float)(t0 >> 8) * 0x1p-24f),
-                                           __float_as_uint((float)(t1 >> 8) * 0x1p-24f),
-                                           __float_as_uint((float)(t2 >> 8) * 0x1p-24f),
-                                           __float_as_uint((float)(t3 >> 8) * 0x1p-24f));
-    } else {
-      const double d0 = (double)t0 * 0x1p-32, d1 = (double)t1 * 0x1p-32;
-      const double d2 = (double)t2 * 0x1p-32, d3 = (double)t3 * 0x1p-32;
-      *(double2*)(out + 32 * q) = make_double2(d0, d1);
-      *(double2*)(out + 32 * q + 16) = make_double2(d2, d3);
-    }
+    if (q < 156) put4<DT>(out, q, w[r]);
   }
 }
 
@@ -113,9 +170,13 @@ __device__ __forceinline__ void write_block(const uint32_t* mt, char* out) {
 // aligned is twisted first (one piece per phase) and then tempered and
 // written out from LDS as 16-byte pieces (one vector store per four words
 // instead of four); a partial block tempers and stores renewed words
-// straight from registers.  The LDS block is private to the wavefront
-// (wavefront-level ordering only).
-template <int DT>
+// straight from registers.  kPairs (mt then holds 1248 words): while two
+// whole blocks remain, the first is twisted from mt into mt + 624 and the
+// second back into mt, and the two are written out together (1248 words:
+// whole 128-byte lines, where a single block ends in the middle of one;
+// measured about 5 % faster for 65536 streams).  The LDS block is private to
+// the wavefront (wavefront-level ordering only).
+template <int DT, bool kPairs = false>
 __device__ __forceinline__ void gen_wave(uint32_t* mt, const MtState* in, MtState* sout, uint64_t n, void* out) {
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
   const int lane = threadIdx.x & 63;
@@ -131,6 +192,15 @@ __device__ __forceinline__ void gen_wave(uint32_t* mt, const MtState* in, MtStat
   const bool vec = (((uintptr_t)out + pos * es) & 15) == 0;
   while (pos < n) {
     const uint64_t left = n - pos;
+    if (kPairs && vec && left >= 1248) {
+      twist_oop(mt, mt + 624);
+      twist_oop(mt + 624, mt);
+      write_pair<DT>(mt + 624, mt, (char*)out + pos * es);
+      wave_lds_sync();
+      pos += 1248;
+      idx = 624;
+      continue;
+    }
     const int want = left < 624 ? (int)left : 624;
     if (vec && want == 624) {
       twist_phase<DT, 4, false>(mt, 0, 227, 397, 0, 0, nullptr);

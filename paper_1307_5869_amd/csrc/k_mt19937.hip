@@ -3,9 +3,8 @@
 // Generation: one wavefront per stream, the 624-word state in LDS.  A twist
 // renews the block in three dependency phases (words 0..226 read old words
 // 397..623; 227..453 read words renewed in phase one; 454..623 read phase two
-// and word 0), each phase parallel across the 64 lanes; every renewed word is
-// tempered and stored straight from registers, so consecutive lanes write
-// consecutive addresses.
+// and word 0), each phase parallel across the 64 lanes; whole blocks are
+// written out two at a time from LDS as 16-byte pieces (dev_mt.h).
 //
 // Jump-ahead (paper, section on MT19937 jump-ahead, equation g_v):
 // A^v Y = g_v(A) Y = sum_i a_i A^(i-1) Y with g_v = x^v mod phi.  A^(i-1) Y is
@@ -33,14 +32,19 @@ namespace {
 using namespace mt;
 
 
+// Workgroup b (one wavefront) takes stream (b % 8) * (G / 8) + b / 8 for
+// b < 8 (G / 8), G = count, else stream b: consecutive workgroups go to the
+// eight XCDs in turn, so each XCD's L2 writes one contiguous eighth of the
+// output (measured about 2 % faster than stream b).
 template <int DT>
 __global__ void __launch_bounds__(64) mt_generate_kernel(MtState* states, uint32_t count, uint64_t n,
                                                          void* __restrict__ out) {
-  __shared__ __align__(16) uint32_t mt[624];
-  const uint32_t s = blockIdx.x;
+  __shared__ __align__(16) uint32_t mt[2 * 624];
+  const uint32_t b = blockIdx.x, per = count / 8;
+  const uint32_t s = b < 8 * per ? (b % 8) * per + b / 8 : b;
   if (s >= count) return;
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
-  gen_wave<DT>(mt, states + s, states + s, n, (char*)out + (uint64_t)s * n * es);
+  gen_wave<DT, true>(mt, states + s, states + s, n, (char*)out + (uint64_t)s * n * es);
 }
 
 // ------------------------------------------------------------------ jump
