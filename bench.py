@@ -179,14 +179,15 @@ def main():
         b.synchronize()
         write_probe = {"bytes": out.numel() * 4, "ms": round(a.elapsed_time(b), 4),
                        "GBs": out.numel() * 4 / (a.elapsed_time(b) * 1e-3) / 1e9}
-        # outside the timed region: every dtype for every generator, five
-        # launches each (the states advance from launch to launch); median,
-        # fastest and slowest launch
+        # outside the timed region: every dtype for every generator, one
+        # untimed launch and then five timed ones (the states advance from
+        # launch to launch); median, fastest and slowest launch
         big = torch.empty(S * N * 2, dtype=torch.int32, device=dev)
         for g in gens:
             ctx.init_streams_dev(g, P.SEQ_DEFAULT, None, ids[g], S, states, stream)
             r = {}
             for dt, name in ((P.U32, "u32"), (P.F32, "f32"), (P.F64, "f64")):
+                ctx.generate_streams(g, states, S, N, dt, big, stream)
                 evs = []
                 for _ in range(5):
                     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

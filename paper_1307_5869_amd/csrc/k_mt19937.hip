@@ -80,8 +80,9 @@ __device__ __forceinline__ void extend(uint32_t* ring, int& gen_hi, int upto, in
 // t = 10 l + r.  For the coefficients i0 .. i0 + 9 of a group it holds the
 // sequence words seq[i0 + 10 l + k] (cur) and seq[i0 + 10 + 10 l + k] (nxt),
 // k < 10: coefficient i0 + u adds seq[i0 + u + 10 l + r], which is
-// cur[u + r] or nxt[u + r - 10].  Groups come in pairs that swap the roles
-// of two register windows, so no window is ever copied.
+// cur[u + r] or nxt[u + r - 10].  Three register windows rotate over the
+// groups: while a group runs, the window the group after next starts with
+// is read from LDS (pf), so no group waits for its own LDS reads.
 //
 // The coefficient bits are uniform across the wavefront, so the scan over
 // them is scalar branching.  Each bit is tested once; a set bit waits for the
@@ -92,11 +93,12 @@ __device__ __forceinline__ void extend(uint32_t* ring, int& gen_hi, int upto, in
 // with the structurizer told to leave uniform regions alone, so every test is
 // one scalar compare and branch.
 __device__ __forceinline__ void group(uint32_t* ring, uint32_t i0, uint32_t bits, int lane, uint32_t (&acc)[kPer],
-                                      const uint32_t (&cur)[kPer], uint32_t (&nxt)[kPer]) {
-  // i0 + 10 + 10 lane is even, so the window is read in 8-byte pairs
-  const uint32_t* src = ring + ((i0 + kPer + kPer * lane) & (kMask & ~1));   // + k < kRing + kMirror
+                                      const uint32_t (&cur)[kPer], const uint32_t (&nxt)[kPer],
+                                      uint32_t (&pf)[kPer]) {
+  // i0 + 20 + 10 lane is even, so the window is read in 8-byte pairs
+  const uint32_t* src = ring + ((i0 + 2 * kPer + kPer * lane) & (kMask & ~1));   // + k < kRing + kMirror
 #pragma unroll
-  for (int k = 0; k < kPer; k++) nxt[k] = src[k];
+  for (int k = 0; k < kPer; k++) pf[k] = src[k];
 #define MT_W2(k) (((k) < kPer) ? cur[(k)] : nxt[(k) - kPer])
 #define MT_BIT(u) ((bits >> (u)) & 1u)
 #define MT_PAIR(p, q)                                                                              \
@@ -110,33 +112,59 @@ __device__ __forceinline__ void group(uint32_t* ring, uint32_t i0, uint32_t bits
 #undef MT_W2
 }
 
+// Coefficients are scanned 60 at a time (six groups); the three polynomial
+// words a step needs are read one step ahead (scalar loads; the last step's
+// third word is past the polynomial and reads as zero).  Measured against
+// two groups per step without read-ahead: 2.5 % faster; the same with the
+// words read through the vector path, which keeps their wait apart from the
+// window reads: no faster.
+constexpr uint32_t kStep = 6 * kPer;
+constexpr int kStepReach = 720;   // a step at i1 reads sequence words below i1 + 710
+
+__device__ __forceinline__ uint32_t poly_word(const uint32_t* __restrict__ poly, uint32_t w) {
+  const uint32_t v = poly[w < 623u ? w : 623u];
+  return w < 624 ? v : 0u;
+}
+
 __device__ __forceinline__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, int lane) {
   int gen_hi = 624;
-  extend(ring, gen_hi, 680, lane);
-  uint32_t acc[kPer], wa[kPer], wb[kPer];
+  extend(ring, gen_hi, kStepReach, lane);
+  uint32_t acc[kPer], wa[kPer], wb[kPer], wc[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; r++) {
     acc[r] = 0;
     wa[r] = ring[kPer * lane + r];
+    wb[r] = ring[kPer + kPer * lane + r];
   }
-  // two groups (20 coefficients) per 64-bit load of the polynomial: bits
-  // i1 .. i1 + 19 lie in the words i1 / 32 and i1 / 32 + 1 (i1 <= 19920, so
-  // both exist).  A pair of groups at i1 reads sequence words below
-  // i1 + 660; the ring is extended 227 words at a time and every pair that
-  // its words allow runs before the next extension (near the end the
-  // sequence stops at kSeqLen: the words past it meet only coefficients at
-  // or above 19937, which are zero, or outputs t >= 624, which are dropped).
+  // bits i1 .. i1 + 59 lie in the words i1 / 32 .. i1 / 32 + 2 (the last
+  // step's third word is past the polynomial and reads as zero).  The ring
+  // is extended 227 words at a time and every step that its words allow runs
+  // before the next extension (near the end the sequence stops at kSeqLen:
+  // the words past it meet only coefficients at or above 19937, which are
+  // zero, or outputs t >= 624, which are dropped).
   uint32_t i1 = 0;
+  uint32_t n0 = poly_word(poly, 0), n1 = poly_word(poly, 1), n2 = poly_word(poly, 2);
   while (i1 < (uint32_t)kDeg) {
-    extend(ring, gen_hi, (int)i1 + 680, lane);
-    const uint32_t lim = (gen_hi >= kSeqLen) ? (uint32_t)kDeg : (uint32_t)(gen_hi - 660);
+    extend(ring, gen_hi, (int)i1 + kStepReach, lane);
+    const uint32_t lim = (gen_hi >= kSeqLen) ? (uint32_t)kDeg : (uint32_t)(gen_hi - kStepReach);
     do {
-      const uint32_t w = i1 >> 5, sh = i1 & 31;
-      const uint64_t pair = (uint64_t)poly[w] | ((uint64_t)poly[w + 1] << 32);
-      const uint32_t bits = (uint32_t)(pair >> sh);
-      group(ring, i1, bits & ((1u << kPer) - 1), lane, acc, wa, wb);
-      group(ring, i1 + kPer, (bits >> kPer) & ((1u << kPer) - 1), lane, acc, wb, wa);
-      i1 += 2 * kPer;
+      const uint32_t p0 = n0, p1 = n1, p2 = n2;
+      const uint32_t wn = (i1 + kStep) >> 5;
+      n0 = poly_word(poly, wn);
+      n1 = poly_word(poly, wn + 1);
+      n2 = poly_word(poly, wn + 2);
+      const uint32_t sh = i1 & 31;
+      const uint32_t b0 = (uint32_t)((((uint64_t)p1 << 32) | p0) >> sh);   // bits i1 .. i1 + 31
+      const uint32_t b1 = (uint32_t)((((uint64_t)p2 << 32) | p1) >> sh);   // bits i1 + 32 .. i1 + 63
+      const uint64_t b = ((uint64_t)b1 << 32) | b0;
+      constexpr uint32_t m = (1u << kPer) - 1;
+      group(ring, i1, (uint32_t)b & m, lane, acc, wa, wb, wc);
+      group(ring, i1 + kPer, (uint32_t)(b >> kPer) & m, lane, acc, wb, wc, wa);
+      group(ring, i1 + 2 * kPer, (uint32_t)(b >> (2 * kPer)) & m, lane, acc, wc, wa, wb);
+      group(ring, i1 + 3 * kPer, (uint32_t)(b >> (3 * kPer)) & m, lane, acc, wa, wb, wc);
+      group(ring, i1 + 4 * kPer, (uint32_t)(b >> (4 * kPer)) & m, lane, acc, wb, wc, wa);
+      group(ring, i1 + 5 * kPer, (uint32_t)(b >> (5 * kPer)) & m, lane, acc, wc, wa, wb);
+      i1 += kStep;
     } while (i1 <= lim && i1 < (uint32_t)kDeg);
   }
   __syncthreads();
