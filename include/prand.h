@@ -359,6 +359,35 @@ double prand_server_clock(const prand_server* server);
    everything, including unreleased outputs. */
 int prand_server_destroy(prand_server* server);
 
+/* ---- CPU SIMD generation (section "Generation with SSE") ----------------
+   Host-only functions, no context and no GPU: the paper's
+   rng_get_sse_state_ / rng_sse_generate_.  A SIMD state continues a plain
+   state blob of any generator on the CPU with vector instructions (x86-64
+   AVX2 and FMA, checked at run time; without them, or when the environment
+   variable PRAND_SIMD_DISABLE is set to a non-zero value as the state is
+   made, the same state runs plain scalar code).  It holds a buffer of the
+   next outputs: MT19937 one 624-word block, LFSR113 eight lanes and
+   MRG32K3A four lanes of 512 consecutive outputs each (the lanes are the
+   stream cut into runs that start from jumps, so the outputs are in
+   sequence order), GM/GQ 1024 ensemble steps (GQ58.3: 128 blocks of 9
+   words).  The outputs are exactly those of the plain state.  The blob is
+   caller-allocated, prand_simd_state_bytes() bytes, any alignment; it may
+   be copied.  A state must not be used by two threads at once. */
+size_t prand_simd_state_bytes(void);
+/* rng_get_sse_state_: make *simd_state continue the plain state blob h_state
+   of generator gen (h_state is read, not changed).  PRAND_EINVAL for a bad
+   generator or a null pointer. */
+int prand_get_simd_state(int gen, const void* h_state, void* simd_state);
+/* rng_sse_generate_: the next 32-bit output (0 for a blob that is not a
+   SIMD state). */
+uint32_t prand_simd_next(void* simd_state);
+/* The next n outputs into h_out as dtype (u32, f32 or f64, the maps of the
+   device calls); PRAND_EINVAL for a bad state, dtype or null h_out. */
+int prand_simd_fill(void* simd_state, int dtype, void* h_out, uint64_t n);
+/* 1 when the state runs the vector code, 0 the scalar code, PRAND_EINVAL
+   for a blob that is not a SIMD state. */
+int prand_simd_vectorized(const void* simd_state);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,8 +34,12 @@ def sources():
 
 # pure host sources (no HIP): the host compiler, with the x86 carry-less multiply
 HOST_CXX = os.environ.get("CXX", "g++")
-HOST_SOURCES = {"mt_poly.cpp"}
-HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-mpclmul", "-msse4.1", "-pthread", "-I", CSRC]
+HOST_SOURCES = {"mt_poly.cpp", "simd_host.cpp"}
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-mpclmul", "-msse4.1", "-pthread", "-I", CSRC, "-I", INCLUDE]
+# the CPU SIMD realizations: AVX2/FMA only inside functions that carry the
+# target attribute (chosen at run time); no contraction of the exact FP64
+# reductions
+HOST_SOURCE_FLAGS = {"simd_host.cpp": ["-O3", "-ffp-contract=off"]}
 
 
 # per-source extra device flags: the MT19937 jump kernel scans jump
@@ -47,7 +51,7 @@ SOURCE_FLAGS = {"k_mt19937.hip": ["-mllvm", "-structurizecfg-skip-uniform-region
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if os.path.basename(src) in HOST_SOURCES:
-        cmd = [HOST_CXX] + HOST_FLAGS + ["-c", src, "-o", obj]
+        cmd = [HOST_CXX] + HOST_FLAGS + HOST_SOURCE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     else:
         cmd = [HIPCC] + FLAGS + SOURCE_FLAGS.get(os.path.basename(src), []) + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

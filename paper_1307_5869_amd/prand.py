@@ -54,6 +54,11 @@ _SIGNATURES = {
     "prand_server_get_stats": (_i32, [_vp, _vp]),
     "prand_server_clock": (ctypes.c_double, [_vp]),
     "prand_server_destroy": (_i32, [_vp]),
+    "prand_simd_state_bytes": (_sz, []),
+    "prand_get_simd_state": (_i32, [_i32, _vp, _vp]),
+    "prand_simd_next": (_u32, [_vp]),
+    "prand_simd_fill": (_i32, [_vp, _i32, _vp, _u64]),
+    "prand_simd_vectorized": (_i32, [_vp]),
 }
 
 
@@ -181,6 +186,28 @@ def independence_limit(gen, variant=SEQ_DEFAULT):
     a, b = ctypes.c_double(), ctypes.c_double()
     _chk(load().prand_independence_limit(gen, variant, ctypes.byref(a), ctypes.byref(b)), "independence_limit")
     return a.value, b.value
+
+
+class SimdState:
+    """A CPU SIMD state (prand_get_simd_state) continuing a plain host state
+    blob; next() and fill() are prand_simd_next / prand_simd_fill."""
+
+    def __init__(self, gen, state):
+        lib = load()
+        self.blob = np.zeros(lib.prand_simd_state_bytes(), dtype=np.uint8)
+        _chk(lib.prand_get_simd_state(gen, _ptr(np.ascontiguousarray(state)), _ptr(self.blob)), "get_simd_state")
+
+    def next(self):
+        return load().prand_simd_next(_ptr(self.blob))
+
+    def fill(self, dtype, n):
+        out = np.empty(n, dtype={U32: np.uint32, F32: np.float32, F64: np.float64}[dtype])
+        _chk(load().prand_simd_fill(_ptr(self.blob), dtype, _ptr(out), n), "simd_fill")
+        return out
+
+    @property
+    def vectorized(self):
+        return bool(load().prand_simd_vectorized(_ptr(self.blob)))
 
 
 class Context:
