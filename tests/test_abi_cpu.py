@@ -24,7 +24,7 @@ def lib():
 def declared_functions():
     text = open(HEADER).read()
     # declarations start a line with their return type
-    pat = r"^(?:int|size_t|double|const char\*)\s+(prand_[a-z0-9_]+)\s*\("
+    pat = r"^(?:int|size_t|double|uint32_t|const char\*)\s+(prand_[a-z0-9_]+)\s*\("
     return sorted(set(re.findall(pat, text, flags=re.M)))
 
 
