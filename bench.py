@@ -226,6 +226,7 @@ def main():
     log("serving done; CPU baseline")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(gens, S, N)
+    simd = None if args.no_cpu_baseline else cpu_simd(ctx, gens)
 
     line = {
         "metric": "uniform numbers/sec per generator (bit-exact); batched vs plain; serve p99 ms",
@@ -253,9 +254,30 @@ def main():
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,
+        "cpu_simd": simd,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def cpu_simd(ctx, gens):
+    """The library's CPU SIMD generation (prand_simd_fill), one host thread
+    per generator, u32: a state from block splitting (stream 1 of the
+    default state), 2^24 words (MT19937, MRG32K3A, LFSR113) or 2^21 (GM/GQ)
+    after a warm-up fill.  Context, not the baseline: the baseline is the
+    oracle."""
+    res = {}
+    isa = None
+    for g in gens:
+        st = ctx.init_stream(g, P.SEQ_DEFAULT, 1)
+        s = P.SimdState(g, st)
+        isa = "avx2" if s.vectorized else "scalar"
+        n = 1 << (24 if g <= P.LFSR113 else 21)
+        s.fill(P.U32, 4096)
+        t = time.perf_counter()
+        s.fill(P.U32, n)
+        res[P.NAMES[g]] = n / (time.perf_counter() - t)
+    return {"unit": "numbers/s", "threads": 1, "isa": isa, "per_generator": res, "host": host_cpu()}
 
 
 def recorded_traffic(kernel):

@@ -101,7 +101,43 @@ def build_test_kernels(verbose=False):
     return built
 
 
+# Fortran: the binding module (include/prand.f90) and the test-side
+# programs tests/fortran/*.f90 -> tests/fortran/bin/<name>, linked against
+# libprand.so (found through an rpath relative to the program)
+FC = os.environ.get("FC", "/opt/rocm/bin/amdflang")
+FORTRAN_TESTS = os.path.join(ROOT, "tests", "fortran")
+
+
+def build_fortran(verbose=False):
+    mod_dir = os.path.join(BUILD, "fortran")
+    bin_dir = os.path.join(FORTRAN_TESTS, "bin")
+    os.makedirs(mod_dir, exist_ok=True)
+    os.makedirs(bin_dir, exist_ok=True)
+    mod_obj = os.path.join(mod_dir, "prand_mod.o")
+    cmd = [FC, "-O2", "-J", mod_dir, "-c", os.path.join(INCLUDE, "prand.f90"), "-o", mod_obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"Fortran module failed:\n{r.stdout}\n{r.stderr}")
+    built = []
+    rpath = "-Wl,-rpath," + "$ORIGIN/" + os.path.relpath(HERE, bin_dir)
+    for f in sorted(os.listdir(FORTRAN_TESTS)):
+        if not f.endswith(".f90"):
+            continue
+        exe = os.path.join(bin_dir, f[:-4])
+        cmd = [FC, "-O2", "-I", mod_dir, os.path.join(FORTRAN_TESTS, f), mod_obj, "-L", HERE, "-lprand", rpath,
+               "-o", exe + ".tmp"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"Fortran build failed for {f}:\n{r.stdout}\n{r.stderr}")
+        os.replace(exe + ".tmp", exe)
+        built.append(exe)
+        if verbose:
+            print("built", exe)
+    return built
+
+
 if __name__ == "__main__":
     build(verbose=True)
     build_test_kernels(verbose=True)
+    build_fortran(verbose=True)
     sys.exit(0)
