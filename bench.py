@@ -266,6 +266,8 @@ def cpu_simd(ctx, gens):
     default state), 2^24 words (MT19937, MRG32K3A, LFSR113) or 2^21 (GM/GQ)
     after a warm-up fill.  Context, not the baseline: the baseline is the
     oracle."""
+    from paper_1307_5869_amd import prand as P
+
     res = {}
     isa = None
     for g in gens:
