@@ -80,7 +80,7 @@ double per_output_cost(int gen) {
 double chip_cost(int gen, int dtype) {
   static const double t[PRAND_NUM_GENERATORS][2] = {
       {0.95, 1.80}, {0.97, 1.66}, {1.03, 1.70}, {6.46, 6.53}, {7.33, 7.40}, {7.31, 7.37},
-      {4.16, 6.43}, {10.67, 10.61}, {7.28, 7.42}, {4.08, 5.70}, {3.47, 5.86}};
+      {4.00, 4.60}, {10.67, 10.61}, {7.28, 7.42}, {4.40, 6.70}, {2.60, 3.20}};
   return t[gen][dtype == PRAND_F64 ? 1 : 0];
 }
 

@@ -12,11 +12,11 @@
 // section's state sits: a GQ58.3 state consumed `off` words of its block, so
 // the section's outputs are frame outputs off .. off + len - 1.  Every lane
 // of a wavefront steps in lockstep from such a boundary, so all lanes make
-// the same number of outputs per step.  Outputs go to a per-lane ring of 16
-// words in LDS; every 8 words the wavefront stores them transposed: in each
-// store instruction two consecutive lanes write the 16-byte pieces of one
-// lane's 32-byte run (whole pieces that lie inside the section and are
-// 16-byte aligned; the others word by word).
+// the same number of outputs per step.  Outputs go to a per-lane ring in LDS;
+// every F words (16 in the many-stream kernel) the wavefront stores them
+// transposed: in each store instruction F / 4 consecutive lanes write the
+// 16-byte pieces of one lane's 4F-byte run (whole pieces that lie inside the
+// section and are 16-byte aligned; the others word by word).
 //
 // Composite moduli: a wavefront with an element that has not collapsed (a
 // section within n0 steps of a state that had not) first runs exact mod-g
@@ -40,12 +40,21 @@ struct LaneShape {
   static constexpr int S = (G == 6) ? 12 : 8;
 };
 
-// LDS per wavefront: a 16-word ring per lane in rows of 20 words (16-byte
-// aligned; the exact steps of a composite start use up to 18 words of the
-// row).  5 KB per wavefront leaves room for 8 wavefronts per SIMD.
-constexpr int kLaneRing = 16;
-constexpr int kLaneRow = 20;
-constexpr int kLaneWaveWords = 64 * kLaneRow;
+// LDS per wavefront: a ring of 2F words per lane in rows of 2F + 4 words
+// (16-byte aligned; the exact steps of a composite start use up to 18 words
+// of the row), flushed F words at a time.  The many-stream kernels use
+// F = 16 (64-byte runs per lane, 9 KB per wavefront: with 4-wavefront
+// workgroups 4 per CU); the batched kernels, which share the CUs with the
+// other classes, F = 8 (32-byte runs, 5 KB per wavefront).
+template <int F>
+struct LaneRing {
+  static constexpr int kFlush = F;
+  static constexpr int kRing = 2 * F;
+  static constexpr int kRow = 2 * F + 4;
+  static constexpr int kWaveWords = 64 * kRow;
+};
+constexpr int kLaneFlushWide = 16;
+constexpr int kLaneFlushNarrow = 8;
 
 template <int G>
 struct FastPair {
@@ -135,26 +144,28 @@ __device__ __forceinline__ uint64_t lane_step(const T (&cur)[LaneShape<G>::S], T
 }
 
 // Store ring words [flushed, flushed + nw) of every lane of the wavefront
-// (nw <= 8, flushed a multiple of 8): in store instruction i, lanes 2j and
-// 2j + 1 write the two 16-byte pieces of lane 32 i + j's run.  mine: the
+// (nw <= F, flushed a multiple of F): in store instruction i, the P = F / 4
+// lanes P j .. P j + P - 1 write the 16-byte pieces of lane (64 / P) i + j's
+// run.  mine: the
 // lane's section output (null for a dead lane); the ring starts at frame
 // output f0; the section holds frame outputs [off0, total).  (Kernels here
 // make no calls: a call would keep every value live across it in extra
 // registers.)
-template <int DT>
+template <int DT, int F>
 __device__ __forceinline__ void lane_flush(const uint32_t* rows, uint32_t flushed, uint32_t nw, uint64_t f0, char* mine,
                                         uint64_t off0, uint64_t total) {
   constexpr int kw = (DT == PRAND_F64) ? 2 : 1;
   constexpr int es = 4 * kw;
   const int lane = threadIdx.x & 63;
   wave_lds_sync();
+  constexpr int P = F / 4;   // 16-byte pieces per run
 #pragma unroll
-  for (int i = 0; i < 2; i++) {
-    const int src = i * 32 + (lane >> 1);
-    const uint32_t pw = flushed + 4 * (lane & 1);   // first ring word of the piece
+  for (int i = 0; i < P; i++) {
+    const int src = i * (64 / P) + lane / P;
+    const uint32_t pw = flushed + 4 * (lane % P);   // first ring word of the piece
     char* const o = (char*)__shfl((unsigned long long)mine, src);
     const uint64_t so = __shfl(off0, src), st = __shfl(total, src);
-    const uint32_t* r = rows + src * kLaneRow + (pw & (kLaneRing - 1));
+    const uint32_t* r = rows + src * LaneRing<F>::kRow + (pw & (LaneRing<F>::kRing - 1));
     if (o && pw < flushed + nw) {
       const uint64_t fo = f0 + pw / kw;   // frame output of the piece's first word
       char* const d = o + (fo - so) * es;
@@ -174,7 +185,7 @@ __device__ __forceinline__ void lane_flush(const uint32_t* rows, uint32_t flushe
   wave_lds_sync();
 }
 
-template <int G, int DT, bool kJump>
+template <int G, int DT, bool kJump, int FW = kLaneFlushWide>
 __device__ __forceinline__ void gmlane_wave(uint32_t* rows, bool live, const GmState* in, uint64_t start,
                                             uint64_t len, void* out, GmState* sout,
                                             const uint64_t* __restrict__ ladder) {
@@ -183,7 +194,7 @@ __device__ __forceinline__ void gmlane_wave(uint32_t* rows, bool live, const GmS
   constexpr int S = LaneShape<G>::S;
   constexpr int kw = (DT == PRAND_F64) ? 2 : 1;   // ring words per output
   const int lane = threadIdx.x & 63;
-  uint32_t* row = rows + lane * kLaneRow;
+  uint32_t* row = rows + lane * LaneRing<FW>::kRow;
 
   // start values: jumped sections in the fast representation; the others
   // exact in *in (converted below)
@@ -266,7 +277,7 @@ __device__ __forceinline__ void gmlane_wave(uint32_t* rows, bool live, const GmS
   constexpr int K = (kGmParams[G].n0 + 1) & ~1;
   constexpr int KW = (G == 6) ? (K * 36 + 31) / 32 : K;   // words the K steps make
   static_assert(G != 6 || K == 16, "GQ58.3: 16 exact steps make whole words");
-  static_assert(KW <= kLaneRow, "exact steps fit the LDS row");
+  static_assert(KW <= LaneRing<FW>::kRow, "exact steps fit the LDS row");
   bool coll = true;
   if (!jumped && live) {
 #pragma unroll
@@ -341,7 +352,7 @@ __device__ __forceinline__ void gmlane_wave(uint32_t* rows, bool live, const GmS
   uint32_t appended = 0, flushed = 0;   // ring words (ring index = counter % 32)
   char* const mine = live ? (char*)out : nullptr;
   auto put_ring = [&](uint32_t w) {
-    const uint32_t at = appended & (kLaneRing - 1);
+    const uint32_t at = appended & (LaneRing<FW>::kRing - 1);
     if (DT == PRAND_F64) {
       const uint64_t u = __double_as_longlong((double)w * 0x1p-32);
       *(uint2*)(row + at) = make_uint2((uint32_t)u, (uint32_t)(u >> 32));
@@ -354,18 +365,18 @@ __device__ __forceinline__ void gmlane_wave(uint32_t* rows, bool live, const GmS
     f++;
   };
   // at most 6 ring words per pair: a flush after every pair keeps at most
-  // 13 words in the ring
+  // FW + 5 words in the ring
   for (; p < pairs; p++) {
     outputs(lane_step<G, false>(fa, fb), put_ring);
     if (++steps == save_at) save_fast(fb, fa);
     outputs(lane_step<G, false>(fb, fa), put_ring);
     if (++steps == save_at) save_fast(fa, fb);
-    if (appended - flushed >= 8) {
-      lane_flush<DT>(rows, flushed, 8, f0, mine, off0, total);
-      flushed += 8;
+    if (appended - flushed >= (uint32_t)FW) {
+      lane_flush<DT, FW>(rows, flushed, FW, f0, mine, off0, total);
+      flushed += FW;
     }
   }
-  if (appended != flushed) lane_flush<DT>(rows, flushed, appended - flushed, f0, mine, off0, total);
+  if (appended != flushed) lane_flush<DT, FW>(rows, flushed, appended - flushed, f0, mine, off0, total);
   // a final state reached at step 0 (a GQ58.3 section within its first
   // block, or an empty one) is the start state; it is written last, since
   // sout may be another section's input: start values again from *in

@@ -208,7 +208,8 @@ __device__ __forceinline__ void gen_gm(const BatchTile& tl, const BatchTask& tk,
   const int gi = (threadIdx.x & 63) / (64 / groups);
   const GmState* in = (const GmState*)(scratch + tl.starts) + (s.live ? gi : 0);
   GmState* sout = s.last ? (GmState*)tk.state_out : nullptr;
-  if constexpr (groups == 64) gm::gmlane_wave<G, DT, false>(rows, s.live, in, 0, s.len, o, sout, nullptr);
+  if constexpr (groups == 64)
+    gm::gmlane_wave<G, DT, false, gm::kLaneFlushNarrow>(rows, s.live, in, 0, s.len, o, sout, nullptr);
   else gm::gen32_wave<G, DT, false>(s.live, in, 0, tl.len32, o, sout, nullptr);
 }
 
@@ -238,7 +239,7 @@ template <int S>
 __global__ void __launch_bounds__(256) batch_gm_kernel(const BatchTile* __restrict__ tiles, uint32_t ntiles,
                                                        const BatchTask* __restrict__ tasks, const char* scratch) {
   static_assert(S == 1 || S == 2, "lane-per-section shapes only");
-  __shared__ __align__(16) uint32_t lds[4][gm::kLaneWaveWords];
+  __shared__ __align__(16) uint32_t lds[4][gm::LaneRing<gm::kLaneFlushNarrow>::kWaveWords];
   const uint32_t t = wave_index();
   if (t >= ntiles) return;
   uint32_t* rows = lds[(threadIdx.x >> 6) & 3];
@@ -382,7 +383,7 @@ __global__ void __launch_bounds__(256) batch_heavy_kernel(const BatchTile* __res
                                                           const uint32_t* __restrict__ order, uint32_t n,
                                                           const BatchTask* __restrict__ tasks, char* scratch,
                                                           uint32_t* counter) {
-  __shared__ __align__(16) uint32_t lds[4][gm::kLaneWaveWords];
+  __shared__ __align__(16) uint32_t lds[4][gm::LaneRing<gm::kLaneFlushNarrow>::kWaveWords];
   uint32_t* rows = lds[(threadIdx.x >> 6) & 3];
   for (;;) {
     const uint32_t k = next_tile(counter);

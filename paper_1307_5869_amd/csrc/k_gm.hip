@@ -48,7 +48,7 @@ template <int G, int DT>
 __global__ void __launch_bounds__(256) gm_lane_kernel(const GmState* sin, GmState* sout, uint32_t count, uint64_t n,
                                                       int nsec_log2, uint64_t seclen, void* __restrict__ out,
                                                       const uint64_t* __restrict__ ladder) {
-  __shared__ __align__(16) uint32_t stage[4][kLaneWaveWords];
+  __shared__ __align__(16) uint32_t stage[4][LaneRing<kLaneFlushWide>::kWaveWords];
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t nsec = 1ull << nsec_log2;
   const uint64_t jlast = (n == 0) ? 0 : (n - 1) / seclen;
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(256) gm_lane_kernel(const GmState* sin, GmStat
   const uint64_t len = live ? ((j == jlast) ? n - start : seclen) : 0;
   constexpr int es = (DT == PRAND_F64) ? 8 : 4;
   void* o = (char*)out + (live ? (s * n + start) * es : 0);
-  gmlane_wave<G, DT, true>(stage[threadIdx.x >> 6], live, sin + (live ? s : 0), start, len, o,
+  gmlane_wave<G, DT, true, kLaneFlushWide>(stage[threadIdx.x >> 6], live, sin + (live ? s : 0), start, len, o,
                            (live && j == jlast) ? sout + s : nullptr, ladder);
 }
 
