@@ -42,16 +42,18 @@ struct LaneShape {
 
 // LDS per wavefront: a ring of 2F words per lane in rows of 2F + 4 words
 // (16-byte aligned; the exact steps of a composite start use up to 18 words
-// of the row), flushed F words at a time.  The many-stream kernels use
-// F = 16 (64-byte runs per lane, 9 KB per wavefront: with 4-wavefront
-// workgroups 4 per CU); the batched kernels, which share the CUs with the
-// other classes, F = 8 (32-byte runs, 5 KB per wavefront).
+// of the row), flushed F words at a time (F = 32: a 48-word ring).  The
+// many-stream kernels use F = 16 (64-byte runs per lane, 9 KB per
+// wavefront: with 4-wavefront workgroups 4 per CU), F = 32 for GQ58.3
+// (whole 128-byte lines, 13 KB); the batched kernels, which share the CUs
+// with the other classes, F = 8 (32-byte runs, 5 KB per wavefront).
 template <int F>
 struct LaneRing {
   static constexpr int kFlush = F;
-  static constexpr int kRing = 2 * F;
-  static constexpr int kRow = 2 * F + 4;
+  static constexpr int kRing = (F == 32) ? 48 : 2 * F;   // holds F + 5 words between flushes
+  static constexpr int kRow = kRing + 4;
   static constexpr int kWaveWords = 64 * kRow;
+  __device__ static uint32_t slot(uint32_t w) { return (kRing & (kRing - 1)) ? w % kRing : w & (kRing - 1); }
 };
 constexpr int kLaneFlushWide = 16;
 constexpr int kLaneFlushNarrow = 8;
@@ -165,7 +167,7 @@ __device__ __forceinline__ void lane_flush(const uint32_t* rows, uint32_t flushe
     const uint32_t pw = flushed + 4 * (lane % P);   // first ring word of the piece
     char* const o = (char*)__shfl((unsigned long long)mine, src);
     const uint64_t so = __shfl(off0, src), st = __shfl(total, src);
-    const uint32_t* r = rows + src * LaneRing<F>::kRow + (pw & (LaneRing<F>::kRing - 1));
+    const uint32_t* r = rows + src * LaneRing<F>::kRow + LaneRing<F>::slot(pw);
     if (o && pw < flushed + nw) {
       const uint64_t fo = f0 + pw / kw;   // frame output of the piece's first word
       char* const d = o + (fo - so) * es;
@@ -352,7 +354,7 @@ __device__ __forceinline__ void gmlane_wave(uint32_t* rows, bool live, const GmS
   uint32_t appended = 0, flushed = 0;   // ring words (ring index = counter % 32)
   char* const mine = live ? (char*)out : nullptr;
   auto put_ring = [&](uint32_t w) {
-    const uint32_t at = appended & (LaneRing<FW>::kRing - 1);
+    const uint32_t at = LaneRing<FW>::slot(appended);
     if (DT == PRAND_F64) {
       const uint64_t u = __double_as_longlong((double)w * 0x1p-32);
       *(uint2*)(row + at) = make_uint2((uint32_t)u, (uint32_t)(u >> 32));
