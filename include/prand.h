@@ -227,7 +227,8 @@ int prand_generate_noalloc(prand_ctx* ctx, int gen, void* h_state, int dtype, vo
  * their tile lists longest first, every wavefront taking the next tile from
  * its class's device counter -- one after another, each with as many
  * wavefronts as the chip holds, or side by side, each with a share of the
- * chip sized by its work (prand_batch_config.overlap).
+ * chip sized by its work, or the MRG32K3A/LFSR113 class first and then the
+ * other two side by side (prand_batch_config.overlap).
  * ------------------------------------------------------------------------ */
 typedef struct prand_task {
   int32_t gen;           /* enum prand_gen */
@@ -246,8 +247,10 @@ typedef struct prand_batch_config {
   uint32_t use_graph;      /* 1: capture the launch in a HIP graph and replay it */
   uint32_t lds_chunk_words; /* LDS staging of MRG32K3A/LFSR113 lanes, 16 or 32 words (0: 32):
                                5 or 9 KB per wavefront of their kernel */
-  uint32_t overlap;        /* 1: the three class kernels run side by side, each class's share of
-                              the chip sized by its work; 0: one after another */
+  uint32_t overlap;        /* 0: the three class kernels run one after another; 1: side by side,
+                              each class's share of the chip sized by its work; 2: the
+                              MRG32K3A/LFSR113 class first with the whole chip, then the other
+                              two side by side */
 } prand_batch_config;
 
 typedef struct prand_batch prand_batch;

@@ -91,7 +91,7 @@ void fill_defaults(prand_batch_config& c) {
   if (!c.reg_section) c.reg_section = 2048;
   if (!c.gm_section) c.gm_section = 4096;
   c.lds_chunk_words = c.lds_chunk_words == 16 ? 16 : 32;
-  c.overlap = c.overlap ? 1 : 0;
+  c.overlap = c.overlap > 2 ? 2 : c.overlap;
   c.waves_per_block = c.waves_per_block >= 4 ? 4 : (c.waves_per_block >= 2 ? 2 : 1);
   c.reg_section = (uint32_t)std::max<uint64_t>(32, round_up(c.reg_section, 32));
   c.gm_section = std::max<uint32_t>(32, c.gm_section);
@@ -283,10 +283,12 @@ void free_batch(prand_batch* b) {
 // section jumped to its start (and the MT19937 section starts, when a task
 // is long enough to have sections); then the three persistent kernels run,
 // either one after another on stream a, each with the whole chip's worth of
-// workgroups, or side by side -- heavy and reg on two forked streams, each
-// with the share of the chip its work takes, light on stream a with the
-// whole chip's worth (those that do not fit at first are dispatched as the
-// other two classes' wavefronts finish) -- and the forks join back into a.
+// workgroups (mode 0), or side by side -- heavy and reg on two forked
+// streams, each with the share of the chip its work takes, light on stream a
+// with the whole chip's worth (those that do not fit at first are
+// dispatched as the other two classes' wavefronts finish) -- and the forks
+// join back into a (mode 1), or reg first with the whole chip and then heavy
+// beside light (mode 2).
 hipError_t enqueue_persistent(prand_batch* b, hipStream_t a) {
   const DeviceTables& T = b->ctx->T;
   const uint32_t w = b->cfg.waves_per_block;
@@ -303,9 +305,16 @@ hipError_t enqueue_persistent(prand_batch* b, hipStream_t a) {
                                     b->d_scratch, b->d_counters + cls, w, b->blocks_cls[cls], a);
     return e;
   }
+  // mode 2: the reg class first, alone, with the whole chip (its work is a
+  // few percent of a mixed batch, and beside many light wavefronts a small
+  // share of it runs behind), then heavy and light side by side
+  const bool reg_first = b->cfg.overlap == 2;
+  if (reg_first && e == hipSuccess)
+    e = launch_batch_persistent(kClassReg, cw, b->d_tiles, b->d_order + b->off_cls[kClassReg], b->n_cls[kClassReg],
+                                b->d_tasks, b->d_scratch, b->d_counters + kClassReg, w, b->blocks_cls[kClassReg], a);
   if (e == hipSuccess) e = hipEventRecord(b->ev[0], a);
   const int side_cls[2] = {kClassHeavy, kClassReg};
-  for (int i = 0; i < 2 && e == hipSuccess; i++) {
+  for (int i = 0; i < (reg_first ? 1 : 2) && e == hipSuccess; i++) {
     const int cls = side_cls[i];
     e = hipStreamWaitEvent(b->side[i], b->ev[0], 0);
     if (e == hipSuccess)
@@ -317,7 +326,7 @@ hipError_t enqueue_persistent(prand_batch* b, hipStream_t a) {
     e = launch_batch_persistent(kClassLight, cw, b->d_tiles, b->d_order + b->off_cls[kClassLight],
                                 b->n_cls[kClassLight], b->d_tasks, b->d_scratch, b->d_counters + kClassLight, w,
                                 b->blocks_cls[kClassLight], a);
-  for (int i = 0; i < 2 && e == hipSuccess; i++) e = hipStreamWaitEvent(a, b->ev[1 + i], 0);
+  for (int i = 0; i < (reg_first ? 1 : 2) && e == hipSuccess; i++) e = hipStreamWaitEvent(a, b->ev[1 + i], 0);
   return e;
 }
 
@@ -416,8 +425,12 @@ int prand_batch_create(prand_ctx* c, const prand_task* h_tasks, uint32_t ntasks,
     // light class gets the whole chip's worth and the forked classes the
     // share their work takes of the batch's (a tenth more, so that they
     // rather finish before the light class than after it)
-    const double share =
-        (!conf.overlap || cls == kClassLight || all <= 0) ? 1.0 : std::min(1.0, 1.1 * plan.cost[cls] / all);
+    // (mode 2: the reg class runs alone first, so the heavy class's share is
+    // of the work of heavy and light)
+    const double rest = conf.overlap == 2 ? plan.cost[kClassHeavy] + plan.cost[kClassLight] : all;
+    const double share = (!conf.overlap || cls == kClassLight || rest <= 0 || (conf.overlap == 2 && cls == kClassReg))
+                             ? 1.0
+                             : std::min(1.0, 1.1 * plan.cost[cls] / rest);
     b->blocks_cls[cls] = std::max<uint32_t>(1, (uint32_t)std::ceil(share * full));
   }
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_order, std::max<size_t>(1, total_order) * 4);
@@ -504,8 +517,8 @@ int prand_batch_autotune(prand_ctx* c, const prand_task* h_tasks, uint32_t ntask
   // 9 KB per wavefront, which sets how many light wavefronts a CU holds)
   const uint32_t cws[] = {16, 32};
   const uint32_t regs[] = {2048, 8192};
-  const uint32_t gms[] = {4096, 16384};
-  const uint32_t ovs[] = {0, 1};
+  const uint32_t gms[] = {16384};
+  const uint32_t ovs[] = {0, 1, 2};
   for (uint32_t ov : ovs)
    for (uint32_t cw : cws)
     for (uint32_t r : regs)
@@ -520,13 +533,21 @@ int prand_batch_autotune(prand_ctx* c, const prand_task* h_tasks, uint32_t ntask
           if (st) (void)hipStreamDestroy(st);
           return rc;
         }
-        rc = prand_batch_launch(b, st);   // warm-up (and graph capture)
-        if (!rc) e = hipEventRecord(a, st);
-        for (int i = 0; i < 3 && !rc && e == hipSuccess; i++) rc = prand_batch_launch(b, st);
-        if (!rc && e == hipSuccess) e = hipEventRecord(z, st);
-        if (!rc && e == hipSuccess) e = hipEventSynchronize(z);
+        // warm-up (and graph capture), then three timed launches scored by
+        // the slowest: a configuration whose classes sometimes finish far
+        // apart (a launch-to-launch spread of 10 % was seen) loses to a
+        // steadier one
+        rc = prand_batch_launch(b, st);
         float ms = 0;
-        if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, a, z);
+        for (int i = 0; i < 3 && !rc && e == hipSuccess; i++) {
+          e = hipEventRecord(a, st);
+          if (e == hipSuccess) rc = prand_batch_launch(b, st);
+          if (!rc && e == hipSuccess) e = hipEventRecord(z, st);
+          if (!rc && e == hipSuccess) e = hipEventSynchronize(z);
+          float one = 0;
+          if (!rc && e == hipSuccess) e = hipEventElapsedTime(&one, a, z);
+          ms = std::max(ms, one);
+        }
         prand_batch_destroy(b);
         if (rc) {
           e = hipErrorUnknown;

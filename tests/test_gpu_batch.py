@@ -60,7 +60,8 @@ def mixed_specs():
 
 
 @pytest.mark.parametrize("cfg", [None, (2, 512, 1024, 1, 16, 0), (4, 8192, 16384, 0, 32, 1), (1, 32, 32, 1, 16, 1),
-                                 (4, 2048, 4096, 1, 16, 0), (4, 2048, 4096, 1, 32, 1)])
+                                 (4, 2048, 4096, 1, 16, 0), (4, 2048, 4096, 1, 32, 1), (4, 8192, 16384, 1, 16, 2),
+                                 (2, 512, 1024, 0, 32, 2)])
 def test_batch_matches_oracle(ctx, oracle, cfg):
     tasks, refs = make_tasks(oracle, mixed_specs())
     conf = P.BatchConfig(*cfg) if cfg else None
