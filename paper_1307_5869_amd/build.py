@@ -44,8 +44,12 @@ HOST_SOURCE_FLAGS = {"simd_host.cpp": ["-O3", "-ffp-contract=off"]}
 
 # per-source extra device flags: the MT19937 jump kernel scans jump
 # coefficients with uniform branches joined by gotos; left unstructured they
-# compile to one scalar compare and branch per coefficient
-SOURCE_FLAGS = {"k_mt19937.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"]}
+# compile to one scalar compare and branch per coefficient.  Without hoisting
+# of common code the test of the next bit, which both successors of a test
+# make, stays a plain compare and branch in each (hoisted, it is carried as
+# a lane mask and costs three more scalar instructions per group).
+SOURCE_FLAGS = {"k_mt19937.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions",
+                                  "-mllvm", "-simplifycfg-hoist-common=false"]}
 
 
 def _compile(src):
