@@ -108,17 +108,17 @@ template <int DT>
 __device__ __forceinline__ void put4(char* out, int q, uint4 w) {
   const uint32_t t0 = temper(w.x), t1 = temper(w.y), t2 = temper(w.z), t3 = temper(w.w);
   if (DT == PRAND_U32) {
-    *(uint4*)(out + 16 * q) = make_uint4(t0, t1, t2, t3);
+    store_out16<DT>(out + 16 * q, make_uint4(t0, t1, t2, t3));
   } else if (DT == PRAND_F32) {
-    *(uint4*)(out + 16 * q) = make_uint4(__float_as_uint((float)(t0 >> 8) * 0x1p-24f),
+    store_out16<DT>(out + 16 * q, make_uint4(__float_as_uint((float)(t0 >> 8) * 0x1p-24f),
                                          __float_as_uint((float)(t1 >> 8) * 0x1p-24f),
                                          __float_as_uint((float)(t2 >> 8) * 0x1p-24f),
-                                         __float_as_uint((float)(t3 >> 8) * 0x1p-24f));
+                                         __float_as_uint((float)(t3 >> 8) * 0x1p-24f)));
   } else {
-    const double d0 = (double)t0 * 0x1p-32, d1 = (double)t1 * 0x1p-32;
-    const double d2 = (double)t2 * 0x1p-32, d3 = (double)t3 * 0x1p-32;
-    *(double2*)(out + 32 * q) = make_double2(d0, d1);
-    *(double2*)(out + 32 * q + 16) = make_double2(d2, d3);
+    const uint64_t d0 = __double_as_longlong((double)t0 * 0x1p-32), d1 = __double_as_longlong((double)t1 * 0x1p-32);
+    const uint64_t d2 = __double_as_longlong((double)t2 * 0x1p-32), d3 = __double_as_longlong((double)t3 * 0x1p-32);
+    store_out16<DT>(out + 32 * q, make_uint4((uint32_t)d0, (uint32_t)(d0 >> 32), (uint32_t)d1, (uint32_t)(d1 >> 32)));
+    store_out16<DT>(out + 32 * q + 16, make_uint4((uint32_t)d2, (uint32_t)(d2 >> 32), (uint32_t)d3, (uint32_t)(d3 >> 32)));
   }
 }
 
