@@ -101,15 +101,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // 16-byte output store of the bulk generators.  u32/f32 outputs are marked
-// non-temporal (the kernel that writes them never reads them back); f64
-// outputs stay plain.  Measured against plain stores, in alternation on one
+// non-temporal (the kernel that writes them never reads them back) when the
+// caller's store instructions cover whole 128-byte lines (kLines); f64
+// outputs and partial-line pieces stay plain.  Measured against plain stores, in alternation on one
 // box: MT19937 u32 0.912 -> 0.861 ms per 2^30 words, LFSR113 u32 0.82 ->
 // 0.81 ms, MRG32K3A within noise; in f64 non-temporal stores were slower
 // (MRG32K3A and LFSR113 by 4 %, and MT19937, whose two stores per lane each
 // cover half of every 32-byte piece, took twice as long).
-template <int DT>
+template <int DT, bool kLines = true>
 __device__ __forceinline__ void store_out16(void* p, uint4 v) {
-  if (DT == PRAND_F64) {
+  if (DT == PRAND_F64 || !kLines) {
     *(uint4*)p = v;
   } else {
     typedef unsigned int U4 __attribute__((ext_vector_type(4)));

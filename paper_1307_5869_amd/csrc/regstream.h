@@ -112,7 +112,7 @@ __device__ __forceinline__ void regstream_wave(uint32_t* rows, bool live, const 
       for (int i = 0; i < kPieces; i++) {
         const int src = i * (64 / kPieces) + lane / kPieces;
         const uint4 v = *(const uint4*)(rows + src * RegStage<CW>::kRowWords + 4 * (lane % kPieces));
-        if (dst[i] && rd < src_rounds[i]) store_out16<DT>(dst[i] + adv, v);
+        if (dst[i] && rd < src_rounds[i]) store_out16<DT, (CW >= 32)>(dst[i] + adv, v);
       }
       wave_lds_sync();
     }
