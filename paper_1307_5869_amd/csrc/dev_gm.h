@@ -46,27 +46,45 @@ __device__ __forceinline__ T pin(T v) {
 template <int G>
 struct Eng;
 
-// The v = 1 ensembles keep each element in a redundant range [0, g + d)
-// (GM29 and GQ58.1: shifted by a constant c, the stored value congruent to
-// x + c), so no step pays for a final conditional subtraction; the digit is
-// read off the redundant value with two compares, and from_fast returns the
-// exact value.  The bounds below hold for every input in the range.
+// GM29, GM31, GM61 and GQ58.1 keep each element in a redundant range
+// [0, g + d) (GM29 and GQ58.1: shifted by a constant c, the stored value
+// congruent to x + c), so no step pays for a final conditional subtraction;
+// the digit is read off the redundant value with two compares, and from_fast
+// returns the exact value.  The bounds below hold for every input in the
+// range.  GM19 (g < 2^20) keeps a centred residue in FP32 instead.
 
-// GM19: g = 2^19 - 1, k = 15, q = 28; z in [0, g + 71].
-// t = 15 zc + 56 g - 28 zp < 71 g + 1066 < 2^26, and t - floor(t / 2^19) g =
-// (t mod 2^19) + floor(t / 2^19) <= g + 70; all multiplies 24-bit
+// GM19: g = 2^19 - 1, k = 15, q = 28.  Each element is held as its centred
+// residue r in [-(g - 1) / 2, (g - 1) / 2], an integer-valued float, and a
+// step is exact FP32 arithmetic (one multiply and three FMAs, all issued at
+// gfx950's fast rate, where the 24-bit integer multiply-adds issue at the
+// slow one):
+//  * t = 15 zc - 28 zp: |t| <= 43 (g - 1) / 2 < 2^24, so the product 28 zp
+//    and the FMA sum are exact;
+//  * k = rint(t / g) from one FMA with the rounding constant 1.5 2^23: 1/g
+//    rounded to FP32 is 2^-19 (1 + 2^-19), within 2^-38 relative of 1/g, so
+//    t/g is evaluated within 2^-33, while t/g (g odd) is never closer than
+//    1/(2g) > 2^-20 to a half-integer: k is the exact nearest integer;
+//  * r = t - k g is exact (k g < 2^24) and lies in the centred range again.
+// The digit floor(2 x / g) of x = r mod g (x = r, or r + g for r < 0) is 1
+// exactly when r < 0.
 template <>
 struct Eng<0> {
   static constexpr bool kComposite = false;
-  using F = uint32_t;
+  using F = float;
   static constexpr uint32_t g = 524287u;
-  __device__ static F to_fast(uint64_t x) { return (F)x; }
-  __device__ static uint64_t from_fast(F z) { return z >= g ? z - g : z; }
-  __device__ static F step(F zc, F zp) {
-    const uint32_t t = __umul24(15u, zc) + (uint32_t)pin(__mul24((int)zp, -28) + (int)(56u * g));
-    return t + (uint32_t)__mul24((int)(t >> 19), -(int)g);
+  static constexpr float kInvG = 1.0f / 524287.0f;   // RN(1/g) = 2^-19 (1 + 2^-19)
+  static constexpr float kRound = 12582912.0f;       // 1.5 2^23: FMA result rounded to an integer
+  __device__ static F to_fast(uint64_t x) { return (float)((int)x - (x > (g - 1) / 2 ? (int)g : 0)); }
+  __device__ static uint64_t from_fast(F z) {
+    const int r = (int)z;
+    return (uint64_t)(r < 0 ? r + (int)g : r);
   }
-  __device__ static bool digit(F z) { return (z >= (1u << 18)) & (z < g); }
+  __device__ static F step(F zc, F zp) {
+    const float t = __builtin_fmaf(15.0f, zc, -28.0f * zp);
+    const float k = __builtin_fmaf(t, kInvG, kRound) - kRound;
+    return __builtin_fmaf(-k, (float)g, t);
+  }
+  __device__ static bool digit(F z) { return z < 0.0f; }
 };
 
 // GM29: g = 2^29 - 3, k = 4, q = 2; z in [0, g + 19], z = x - 38 (mod g).

@@ -12,14 +12,15 @@
 // in that lane (dev_gmlane.h); a stream is cut into up to 64 sections that
 // start by jumps.
 //
-// Arithmetic is exact: special-form reductions (2^19-1, 2^29-3, 2^61-1,
-// 2^51-129) in integers.  For g = p 2^t (GM55: t = 4, GQ58: t = 29) the even
+// Arithmetic is exact: special-form reductions (2^29-3, 2^31-1, 2^61-1,
+// 2^51-129) in integers; GM19 (2^19-1) in FP32 FMAs on centred residues,
+// every value an integer below 2^24 (dev_gm.h).  For g = p 2^t (GM55: t = 4, GQ58: t = 29) the even
 // k and q kill the 2-adic part within n0 steps; from then on x = 2^t y with y
 // following the same recurrence mod p and the digit equal to
 // floor(2^v y / p), so the kernels run exact mod-g steps only until every
 // element of the wavefront has collapsed and then switch to the mod-p
-// recurrence.  In the steady state an element is held as a redundant
-// residue (congruent to the exact value, possibly shifted by a constant, in
+// recurrence.  In the steady state an element (GM19 aside) is held as a
+// redundant residue (congruent to the exact value, possibly shifted by a constant, in
 // a range a little wider than the modulus), so no step needs a final
 // conditional subtraction; digits are read off that form and states are
 // written back exact.

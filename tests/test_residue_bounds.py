@@ -10,9 +10,14 @@ and boundary inputs: the sum and its pieces fit the widths the kernels use,
 the result stays in [0, zmax], it is congruent to k x - q x_prev (mod m), and
 the digit equals floor(2^v x / m) of the exact value.  The v = 3/4 digit
 formula is also checked on every value within 64 of each place where either
-the exact digit or one of the formula's shifts changes."""
+the exact digit or one of the formula's shifts changes.
+
+GM19 instead keeps a centred residue in FP32 and steps it with FMAs: that
+form is checked exhaustively over every product sum its inputs can give,
+with the FP32 roundings emulated exactly in integers."""
 import random
 
+import numpy as np
 import pytest
 
 M32 = (1 << 32) - 1
@@ -22,13 +27,6 @@ M64 = (1 << 64) - 1
 def fits(x, bits):
     assert 0 <= x < (1 << bits), (x, bits)
     return x
-
-
-def gm19_step(zc, zp):
-    g = (1 << 19) - 1
-    a = fits(56 * g - 28 * zp, 32)              # signed 24-bit multiply-add, non-negative
-    t = fits(15 * zc + a, 26)
-    return t - (t >> 19) * g
 
 
 def gm29_step(zc, zp):
@@ -97,7 +95,6 @@ def gm55_digit(z):
 
 FORMS = [
     # name, m, k, q, v, shift (exact = z + shift), zmax, step, digit
-    ("GM19", P19, 15, 28, 1, 0, P19 + 71, gm19_step, v1_digit(1 << 18, P19)),
     ("GM29", P29, 4, 2, 1, 38, P29 + 19, gm29_step, v1_digit((P29 + 1) // 2 - 38, P29 - 38)),
     ("GM31", P31, 11, 14, 1, 0, P31 + 39, gm31_step, v1_digit(1 << 30, P31)),
     ("GM61", P61, 24, 74, 1, 0, (1 << 61) + 98 * (1 << 32) - 1, gm61_step, v1_digit(1 << 60, P61)),
@@ -177,7 +174,6 @@ def test_worst_case_bounds():
     """Every fold's largest possible result over all stored inputs in
     [0, zmax] stays within zmax (the product sums are largest at zp = 0)."""
     z = {f[0]: f[6] for f in FORMS}
-    assert fold_max(15 * z["GM19"] + 56 * P19, 19, 1) <= z["GM19"]
     assert fold_max(2 * z["GM29"] + P29 + 19, 28, 3, 2) <= z["GM29"]
     assert fold_max(11 * z["GM31"] + 14 * 2 * P31, 31, 1) <= z["GM31"]
     u1 = z["GQ58.1"] + 6 * (P29 + 205)
@@ -193,3 +189,70 @@ def test_worst_case_bounds():
     a_max = 98 * M32 + (b_max >> 29)
     r_max = (((a_max >> 32) + (1 << 29) - 1) << 32) | M32
     assert b_max < 1 << 38 and r_max <= z["GM61"] and 2 * P61 - z["GM61"] > 0
+
+
+# ---------------------------------------------------------------- GM19, FP32
+# The kernel's GM19 step on centred residues r in [-(g-1)/2, (g-1)/2] held as
+# floats: t = fma(15, zc, -28 zp); K = fma(t, RN(1/g), 1.5 2^23); k = K -
+# 1.5 2^23; r = fma(-k, g, t); digit = (r < 0).
+G19 = P19
+HALF19 = (G19 - 1) // 2
+ROUND = 3 << 22          # 1.5 2^23
+INV_NUM = (1 << 19) + 1  # RN_f32(1/g) = INV_NUM / 2^38 (pinned below)
+
+
+def test_gm19_f32_inverse_constant():
+    """the float nearest 1/g is 2^-19 (1 + 2^-19), within 2^-38 relative"""
+    inv = np.float32(1.0) / np.float32(G19)
+    assert float(inv) == INV_NUM / 2.0 ** 38
+    assert abs(float(inv) * G19 - 1.0) < 2.0 ** -37
+
+
+def gm19_f32_from_t(t):
+    """The kernel's step from the product sum t (int64 array), every FP32
+    operation emulated exactly: returns (k, r, digit)."""
+    # t = 15 zc - 28 zp and the product 28 zp are exact FP32 values
+    assert np.all(np.abs(t) < 1 << 24)
+    # K = RN_f32(t / 2^38 * INV_NUM + ROUND): the exact value lies in
+    # [2^23, 2^24), where FP32 spacing is 1, so K is that value rounded to
+    # the nearest integer, ties to even
+    num = t * INV_NUM + (ROUND << 38)
+    q, rem = num >> 38, num & ((1 << 38) - 1)
+    assert np.all((q >= 1 << 23) & (q + 1 < 1 << 24))
+    half = 1 << 37
+    K = q + (rem > half) + ((rem == half) & (q & 1))
+    k = K - ROUND                       # exact: integers below 2^24
+    assert np.all(np.abs(k * G19) < 1 << 24)
+    r = t - k * G19                     # fma(-k, g, t): exact
+    return k, r, r < 0
+
+
+def test_gm19_f32_step_exhaustive():
+    """Every product sum t of two centred residues: k is the nearest integer
+    to t / g, r = t - k g is the centred residue of t, and the digit read off
+    its sign is floor(2 x / g) of x = t mod g."""
+    tmax = 15 * HALF19 + 28 * HALF19
+    for lo in range(-tmax, tmax + 1, 1 << 22):
+        t = np.arange(lo, min(lo + (1 << 22), tmax + 1), dtype=np.int64)
+        k, r, digit = gm19_f32_from_t(t)
+        assert np.array_equal(k, (2 * t + G19) // (2 * G19))   # nearest: t/g is never a half-integer
+        assert np.all(np.abs(r) <= HALF19)
+        x = np.mod(t, G19)
+        assert np.array_equal(np.mod(r, G19), x)
+        assert np.array_equal(digit, (2 * x) // G19 == 1)
+
+
+def test_gm19_f32_runs_and_conversions():
+    """Runs from exact states through the kernel's conversions and steps."""
+    rnd = random.Random(19)
+    for x0 in [0, 1, HALF19, HALF19 + 1, G19 - 1] + [rnd.randrange(G19) for _ in range(40)]:
+        xc, xp = x0, rnd.randrange(G19)
+        zc = xc - (G19 if xc > HALF19 else 0)      # to_fast
+        zp = xp - (G19 if xp > HALF19 else 0)
+        for _ in range(300):
+            t = np.array([15 * zc - 28 * zp], dtype=np.int64)
+            _, r, digit = gm19_f32_from_t(t)
+            x = (15 * xc - 28 * xp) % G19
+            assert int(r[0]) % G19 == x and bool(digit[0]) == ((2 * x) // G19 == 1)
+            zp, zc, xp, xc = zc, int(r[0]), xc, x
+        assert (zc + G19 if zc < 0 else zc) == xc     # from_fast
