@@ -73,6 +73,28 @@ def test_generate_streams(ctx, oracle, gen, dtype, count, n):
         assert np.array_equal(got_states[i], st), f"state {i}"
 
 
+def test_gm19_states_at_the_centred_range_edges(ctx, oracle):
+    """GM19 steps on centred residues in [-(g-1)/2, (g-1)/2]: states whose
+    elements sit where the conversion into that form changes side (and at
+    the ends of [0, g)), in every dtype, with a ragged last block."""
+    g = (1 << 19) - 1
+    edge = [0, 1, 2, (g - 1) // 2 - 1, (g - 1) // 2, (g + 1) // 2, (g + 1) // 2 + 1, g - 2, g - 1]
+    rng = np.random.default_rng(19)
+    states = []
+    for i in range(40):
+        st = oracle.seed(P.GM19, 500 + i).copy()
+        st.view(np.uint64)[:64] = rng.choice(edge, 64)   # xc[32], xp[32]
+        states.append(st)
+    n = 3000
+    for dtype in DTYPES:
+        got, got_states = gpu_generate_streams(ctx, P.GM19, [st.copy() for st in states], n, dtype)
+        for i, st in enumerate(states):
+            ref_state = st.copy()
+            ref = oracle.generate(P.GM19, ref_state, n, dtype)
+            np.testing.assert_array_equal(got[i * n:(i + 1) * n], ref, err_msg=f"stream {i}")
+            assert np.array_equal(got_states[i], ref_state), f"state {i}"
+
+
 @pytest.mark.parametrize("gen", GENS)
 def test_generate_in_pieces_continues_the_stream(ctx, oracle, gen):
     states = [oracle.seed(gen, 77 + i) for i in range(6)]
