@@ -64,6 +64,15 @@ constexpr double kLimits[PRAND_NUM_GENERATORS][4][2] = {
     /* GQ58.4   */ {{0, 0}, {3e8, 8e7}, {3e6, 8e9}, {3e4, 8e11}},
 };
 
+// the byte tables are built for each generator's default block exponent
+constexpr int default_block_log2(int gen) { return kBlockLog2[gen][0] >= 0 ? kBlockLog2[gen][0] : kBlockLog2[gen][1]; }
+constexpr bool byte_tables_match() {
+  for (int g = 0; g < 8; g++)
+    if (kGmByteE[g] != default_block_log2(PRAND_GM19 + g)) return false;
+  return kLfsrByteE == default_block_log2(PRAND_LFSR113);
+}
+static_assert(byte_tables_match(), "byte tables built for another block exponent");
+
 int block_log2(int gen, int variant) {
   if (!valid_gen(gen) || variant < PRAND_SEQ_DEFAULT || variant > PRAND_SEQ_LONG) return PRAND_EINVAL;
   if (variant == PRAND_SEQ_DEFAULT) {
@@ -391,9 +400,14 @@ int prand_ctx_create(prand_ctx** out, int hip_device) {
   build_mrg_ladder(H->mrg);
   build_lfsr_ladder(H->lfsr);
   build_gm_ladders(H->gm);
+  build_gm_byte_tables(H->gmbyte, H->gmneg);
+  build_lfsr_byte_table(H->lfsrbyte);
   hipError_t e = upload(&c->T.mrg, H->mrg, sizeof(H->mrg) / sizeof(H->mrg[0]));
   if (e == hipSuccess) e = upload(&c->T.lfsr, H->lfsr, sizeof(H->lfsr) / sizeof(H->lfsr[0]));
   if (e == hipSuccess) e = upload(&c->T.gm, H->gm, sizeof(H->gm) / sizeof(H->gm[0]));
+  if (e == hipSuccess) e = upload(&c->T.gmbyte, H->gmbyte, sizeof(H->gmbyte) / sizeof(H->gmbyte[0]));
+  if (e == hipSuccess) e = upload(&c->T.gmneg, H->gmneg, sizeof(H->gmneg) / sizeof(H->gmneg[0]));
+  if (e == hipSuccess) e = upload(&c->T.lfsrbyte, H->lfsrbyte, sizeof(H->lfsrbyte) / sizeof(H->lfsrbyte[0]));
   delete H;
   if (e == hipSuccess) e = hipMalloc(&c->T.defaults, kDefaultStride * PRAND_NUM_GENERATORS);
   if (e == hipSuccess) e = hipMalloc(&c->scratch, kScratch);
@@ -424,6 +438,9 @@ int prand_ctx_destroy(prand_ctx* c) {
   (void)hipFree(c->T.mrg);
   (void)hipFree(c->T.lfsr);
   (void)hipFree(c->T.gm);
+  (void)hipFree(c->T.gmbyte);
+  (void)hipFree(c->T.gmneg);
+  (void)hipFree(c->T.lfsrbyte);
   (void)hipFree(c->T.mt);
   (void)hipFree(c->T.mtdiglo);
   (void)hipFree(c->T.mtdig8hi);

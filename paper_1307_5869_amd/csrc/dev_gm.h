@@ -442,6 +442,44 @@ __device__ __forceinline__ void jump_steps_elem(uint64_t& xc, uint64_t& xp, uint
   }
 }
 
+// Block splitting with the default variant: move (xc, xp) id 2^e steps on,
+// e = kGmByteE[G], with one byte-table matrix per nonzero byte of id (tab:
+// this generator's [8][256][4] slice).  Composite moduli first collapse (n0
+// exact steps, unless already collapsed) and then also take M^(-n0) (neg),
+// so the total stays id 2^e steps; id = 0 leaves the element as it is.
+template <int G>
+__device__ __forceinline__ void jump_bytes_elem(uint64_t& xc, uint64_t& xp, uint64_t id,
+                                                const uint64_t* __restrict__ tab, const uint64_t* __restrict__ neg) {
+  using E = Eng<G>;
+  if (!id) return;
+  int pe;
+  uint64_t pc;
+  prime_form(G, pe, pc);
+  const uint64_t p = kGmParams[G].p;
+  bool back = false;
+  if constexpr (E::kComposite) {
+    if (!(E::collapsed(xc) && E::collapsed(xp))) {
+      for (int i = 0; i < kGmParams[G].n0; i++) { const uint64_t nx = E::slow_step(xc, xp); xp = xc; xc = nx; }
+      back = true;
+    }
+  }
+  constexpr int t = kGmParams[G].t;   // 2-adic exponent of the modulus (0: prime)
+  uint64_t yc = xc >> t, yp = xp >> t;
+  auto apply = [&](const uint64_t* M) {
+    const uint64_t nc = mulsum_mod<G>(M[0], yc, M[1], yp, pe, pc, p);
+    const uint64_t np = mulsum_mod<G>(M[2], yc, M[3], yp, pe, pc, p);
+    yc = nc;
+    yp = np;
+  };
+  for (int j = 0; j < 8; j++) {
+    const uint32_t d = (uint32_t)(id >> (8 * j)) & 255u;
+    if (d) apply(tab + ((size_t)j * 256 + d) * 4);
+  }
+  if (back) apply(neg);
+  xc = yc << t;
+  xp = yp << t;
+}
+
 // GQ58.3: a distance of N words from word offset `off` inside an 8-step
 // block: (off + N) = 9 B + rem; N becomes 8 B ensemble steps, *new_off = rem.
 __device__ __forceinline__ void gq3_words_to_steps(uint64_t* N, uint32_t off, uint32_t* new_off) {

@@ -73,13 +73,17 @@ __global__ void __launch_bounds__(256) gm_lane_kernel(const GmState* sin, GmStat
 }
 
 // One lane per element slot (32 per stream): states[s] = base (or states[s])
-// jumped by the stream's distance; GQ58.3 distances count words.
+// jumped by the stream's distance; GQ58.3 distances count words.  Block
+// splitting with the default block exponent takes the byte tables (at most
+// eight matrices per stream), other distances the ladder (one per set bit).
 template <int G>
 __global__ void __launch_bounds__(256) gm_jump_kernel(GmState* __restrict__ states, uint32_t count,
                                                       const uint64_t* __restrict__ dist, int nlimbs, int per_stream,
                                                       const uint64_t* __restrict__ ids, int block_e,
                                                       const GmState* __restrict__ base,
-                                                      const uint64_t* __restrict__ ladder) {
+                                                      const uint64_t* __restrict__ ladder,
+                                                      const uint64_t* __restrict__ bytetab,
+                                                      const uint64_t* __restrict__ neg) {
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t s = gid >> 5;
   if (s >= count) return;
@@ -87,6 +91,15 @@ __global__ void __launch_bounds__(256) gm_jump_kernel(GmState* __restrict__ stat
   const GmState* src = base ? base : states + s;
   uint64_t xc = src->xc[e], xp = src->xp[e];
   const uint32_t off = src->off;
+  if (ids && bytetab && block_e == kGmByteE[G]) {
+    // whole blocks: the offset inside a GQ58.3 block is kept
+    if (e < kGmParams[G].s) jump_bytes_elem<G>(xc, xp, ids[s], bytetab, neg);
+    GmState* dst = states + s;
+    dst->xc[e] = xc;
+    dst->xp[e] = xp;
+    if (e == 0) { dst->off = (G == 6) ? off : 0; dst->pad = 0; }
+    return;
+  }
   uint64_t N[kMaxLimbs + 1];
   for (int l = 0; l <= kMaxLimbs; l++) N[l] = 0;
   if (ids) {
@@ -153,7 +166,8 @@ hipError_t launch_jump_g(const DeviceTables& T, GmState* states, uint32_t count,
   const uint64_t lanes = (uint64_t)count * 32;
   const uint32_t blocks = (uint32_t)((lanes + 255) / 256);
   hipLaunchKernelGGL(gm_jump_kernel<G>, dim3(blocks), dim3(256), 0, st, states, count, js.dist, js.nlimbs,
-                     js.per_stream, js.ids, js.block_e, base, T.gm);
+                     js.per_stream, js.ids, js.block_e, base, T.gm,
+                     T.gmbyte ? T.gmbyte + (size_t)G * 8 * 256 * 4 : nullptr, T.gmneg ? T.gmneg + (size_t)G * 4 : nullptr);
   return hipGetLastError();
 }
 

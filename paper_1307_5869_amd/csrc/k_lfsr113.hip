@@ -17,10 +17,22 @@ __global__ void __launch_bounds__(256) lfsr_jump_kernel(LfsrState* __restrict__ 
                                                         const uint64_t* __restrict__ dist, int nlimbs,
                                                         int per_stream, const uint64_t* __restrict__ ids,
                                                         int block_e, const LfsrState* __restrict__ base,
-                                                        const uint32_t* __restrict__ ladder) {
+                                                        const uint32_t* __restrict__ ladder,
+                                                        const uint32_t* __restrict__ bytetab) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   LfsrState st = base ? *base : states[i];
+  if (ids && bytetab && block_e == kLfsrByteE) {
+    // block splitting with the default block exponent: one byte-table matrix
+    // per nonzero byte of the id
+    const uint64_t id = ids[i];
+    for (int j = 0; j < 8; j++) {
+      const uint32_t d = (uint32_t)(id >> (8 * j)) & 255u;
+      if (d) LfsrGen::apply(st, bytetab + ((size_t)j * 256 + d) * kLfsrSectionWords);
+    }
+    states[i] = st;
+    return;
+  }
   uint64_t limbs[kMaxLimbs];
   int nl;
   if (ids) {
@@ -53,7 +65,7 @@ hipError_t launch_lfsr_jump(const DeviceTables& T, LfsrState* states, uint32_t c
                             const LfsrState* base, hipStream_t st) {
   const uint32_t blocks = (count + 255) / 256;
   hipLaunchKernelGGL(lfsr_jump_kernel, dim3(blocks), dim3(256), 0, st, states, count, js.dist, js.nlimbs,
-                     js.per_stream, js.ids, js.block_e, base, T.lfsr);
+                     js.per_stream, js.ids, js.block_e, base, T.lfsr, T.lfsrbyte);
   return hipGetLastError();
 }
 

@@ -68,11 +68,22 @@ constexpr GmParams kGmParams[8] = {
 };
 inline bool is_gm(int gen) { return gen >= PRAND_GM19 && gen <= PRAND_GQ58X4; }
 
+// Byte tables for block splitting with each generator's default variant:
+// the stream of id starts id 2^e steps on (e = kGmByteE[G], kLfsrByteE, the
+// default block exponents), applied as one matrix per nonzero byte d_j of
+// id (id = sum d_j 2^(8 j)): entry [j][d] is the jump by d 2^(e + 8 j), so a
+// stream costs at most 8 matrix applications instead of one per set bit.
+constexpr int kGmByteE[8] = {23, 27, 27, 34, 34, 27, 27, 27};
+constexpr int kLfsrByteE = 34;
+
 // ---- device-resident jump tables (built once per context) ----
 struct DeviceTables {
   uint32_t* mrg = nullptr;    // [kLadder][18]: A^(2^b) mod m1 (row major), B^(2^b) mod m2
   uint32_t* lfsr = nullptr;   // [kLadder][4][32]: columns of T_c^(2^b)
   uint64_t* gm = nullptr;     // [8][kLadder][4]: (a b; c d) = M^(2^b) mod p
+  uint64_t* gmbyte = nullptr;   // [8][8][256][4]: M^(d 2^(kGmByteE[G] + 8 j)) mod p
+  uint64_t* gmneg = nullptr;    // [8][4]: M^(-n0) mod p (composite moduli; identity otherwise)
+  uint32_t* lfsrbyte = nullptr; // [8][256][4][32]: columns of T_c^(d 2^(kLfsrByteE + 8 j))
   uint32_t* mt = nullptr;     // [kLadder][624]: bits of x^(2^b) mod phi (19937 used)
   uint32_t* mtdiglo = nullptr;  // [3][65536][624]: x^(d 2^(kMtDigitE + 16k)) mod phi
   uint32_t* mtdig8hi = nullptr; // [2][256][624]: x^(d 2^(kMtDigitE + 48 + 8j)) mod phi
@@ -165,6 +176,9 @@ struct HostTables {
   uint32_t mrg[kLadder * 18];
   uint32_t lfsr[kLadder * 4 * 32];
   uint64_t gm[8 * kLadder * 4];
+  uint64_t gmbyte[8 * 8 * 256 * 4];
+  uint64_t gmneg[8 * 4];
+  uint32_t lfsrbyte[8 * 256 * 128];
 };
 void build_mrg_ladder(uint32_t* out);
 void build_lfsr_ladder(uint32_t* out);
@@ -179,6 +193,8 @@ constexpr int kLfsrSectionWords = 128;
 void build_mrg_section_table(uint64_t seclen, uint32_t* out);
 void build_lfsr_section_table(uint64_t seclen, uint32_t* out);
 void build_gm_ladders(uint64_t* out);
+void build_gm_byte_tables(uint64_t* out, uint64_t* neg);
+void build_lfsr_byte_table(uint32_t* out);
 
 // the calling thread's current device is set to `dev` for the guard's life
 struct DeviceGuard {

@@ -115,6 +115,31 @@ void build_lfsr_ladder(uint32_t* out) {
   }
 }
 
+// columns of T_c^(d 2^(kLfsrByteE + 8 j)) for every byte position j and
+// value d (row [j][d], 128 words, the layout of the section tables)
+void build_lfsr_byte_table(uint32_t* out) {
+  for (int c = 0; c < 4; c++) {
+    uint32_t b[32], t[32], m[32];
+    for (int j = 0; j < 32; j++) b[j] = lfsr_word_step(1u << j, c);
+    for (int i = 0; i < kLfsrByteE; i++) {   // b = T_c^(2^e)
+      for (int j = 0; j < 32; j++) t[j] = f2_apply(b, b[j]);
+      std::memcpy(b, t, sizeof t);
+    }
+    for (int pos = 0; pos < 8; pos++) {
+      for (int j = 0; j < 32; j++) m[j] = 1u << j;   // d = 0: identity
+      for (int d = 0; d < 256; d++) {
+        std::memcpy(out + (((size_t)pos * 256 + d) * 4 + c) * 32, m, sizeof m);
+        for (int j = 0; j < 32; j++) t[j] = f2_apply(b, m[j]);
+        std::memcpy(m, t, sizeof t);
+      }
+      for (int i = 0; i < 8; i++) {   // b = b^256 for the next byte
+        for (int j = 0; j < 32; j++) t[j] = f2_apply(b, b[j]);
+        std::memcpy(b, t, sizeof t);
+      }
+    }
+  }
+}
+
 void build_lfsr_section_table(uint64_t seclen, uint32_t* out) {
   for (int c = 0; c < 4; c++) {
     // S = T_c^seclen by squaring; columns of the composition P o Q are P
@@ -142,6 +167,55 @@ void build_lfsr_section_table(uint64_t seclen, uint32_t* out) {
 }
 
 // ------------------------------------------------------------------- GM/GQ
+namespace {
+struct Mat2 {
+  uint64_t a, b, c, d;
+};
+Mat2 mat2_mul(const Mat2& x, const Mat2& y, uint64_t p) {
+  return Mat2{(uint64_t)(((u128)x.a * y.a + (u128)x.b * y.c) % p), (uint64_t)(((u128)x.a * y.b + (u128)x.b * y.d) % p),
+              (uint64_t)(((u128)x.c * y.a + (u128)x.d * y.c) % p), (uint64_t)(((u128)x.c * y.b + (u128)x.d * y.d) % p)};
+}
+uint64_t pow_mod(uint64_t x, uint64_t e, uint64_t p) {
+  uint64_t r = 1 % p;
+  for (; e; e >>= 1) {
+    if (e & 1) r = (uint64_t)((u128)r * x % p);
+    x = (uint64_t)((u128)x * x % p);
+  }
+  return r;
+}
+}  // namespace
+
+// out [8][8][256][4]: M^(d 2^(kGmByteE[g] + 8 j)) mod p; neg [8][4]: M^(-n0)
+// mod p (the inverse of M^n0 through the adjugate and det^(p-2), p prime),
+// the identity where n0 = 0
+void build_gm_byte_tables(uint64_t* out, uint64_t* neg) {
+  for (int g = 0; g < 8; g++) {
+    const GmParams& P = kGmParams[g];
+    const uint64_t p = P.p;
+    const Mat2 m{P.k % p, (p - P.q % p) % p, 1, 0};
+    Mat2 b = m;
+    for (int i = 0; i < kGmByteE[g]; i++) b = mat2_mul(b, b, p);
+    for (int pos = 0; pos < 8; pos++) {
+      Mat2 t{1, 0, 0, 1};
+      for (int d = 0; d < 256; d++) {
+        uint64_t* o = out + (((size_t)g * 8 + pos) * 256 + d) * 4;
+        o[0] = t.a; o[1] = t.b; o[2] = t.c; o[3] = t.d;
+        t = mat2_mul(t, b, p);
+      }
+      for (int i = 0; i < 8; i++) b = mat2_mul(b, b, p);
+    }
+    Mat2 f{1, 0, 0, 1};
+    for (int i = 0; i < P.n0; i++) f = mat2_mul(f, m, p);
+    const uint64_t det = (uint64_t)(((u128)f.a * f.d + (u128)(p - f.b) * f.c) % p);
+    const uint64_t inv = pow_mod(det, p - 2, p);
+    uint64_t* o = neg + (size_t)g * 4;
+    o[0] = (uint64_t)((u128)f.d * inv % p);
+    o[1] = (uint64_t)((u128)((p - f.b) % p) * inv % p);
+    o[2] = (uint64_t)((u128)((p - f.c) % p) * inv % p);
+    o[3] = (uint64_t)((u128)f.a * inv % p);
+  }
+}
+
 void build_gm_ladders(uint64_t* out) {
   for (int g = 0; g < 8; g++) {
     const GmParams& P = kGmParams[g];

@@ -193,6 +193,22 @@ def test_init_streams_match_oracle(ctx, oracle, gen):
             ctx.init_stream(gen, v, 1)
 
 
+@pytest.mark.parametrize("gen", GENS[1:])
+def test_init_streams_byte_tables(ctx, oracle, gen):
+    """Default-variant block splitting through the byte tables (one matrix
+    per nonzero byte of the id): ids with one byte set at every position and
+    edge values, mixed and random ids, from the default state."""
+    ids = [d << (8 * j) for j in range(8) for d in (1, 2, 127, 128, 255)]
+    rng = np.random.default_rng(1307)
+    ids += [int(x) for x in rng.integers(0, 2**63, 8, dtype=np.int64)] + [2**63, 2**63 + 1, 0x00FF00FF00FF00FF]
+    t = torch.tensor(np.array(ids, dtype=np.uint64).view(np.int64), device="cuda")
+    d = torch.empty(len(ids) * P.state_bytes(gen), dtype=torch.uint8, device="cuda")
+    ctx.init_streams_dev(gen, P.SEQ_DEFAULT, None, t, len(ids), d)
+    torch.cuda.synchronize()
+    for sid, st in zip(ids, from_dev(d, gen)):
+        assert np.array_equal(st, oracle.init_stream(gen, P.SEQ_DEFAULT, sid)), hex(sid)
+
+
 @pytest.mark.parametrize("consumed", [0, 100])
 @pytest.mark.parametrize("gen", GENS)
 def test_init_streams_from_explicit_base(ctx, oracle, gen, consumed):
