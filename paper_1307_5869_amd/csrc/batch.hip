@@ -64,7 +64,7 @@ double per_output_cost(int gen) {
     case PRAND_MT19937: return 0.35;   // 64 lanes share one stream
     case PRAND_MRG32K3A: return 32;
     case PRAND_LFSR113: return 27;
-    case PRAND_GM19:
+    case PRAND_GM19: return 6;
     case PRAND_GM29: return 11;
     case PRAND_GM31: return 16;
     case PRAND_GM61: return 24;
@@ -79,8 +79,8 @@ double per_output_cost(int gen) {
 // class of tiles holds, from which the side-by-side launch sizes its share
 double chip_cost(int gen, int dtype) {
   static const double t[PRAND_NUM_GENERATORS][2] = {
-      {0.95, 1.80}, {0.97, 1.66}, {1.03, 1.70}, {6.46, 6.53}, {7.33, 7.40}, {7.31, 7.37},
-      {4.00, 4.60}, {10.67, 10.61}, {7.28, 7.42}, {4.40, 6.70}, {2.60, 3.20}};
+      {0.89, 1.77}, {0.94, 1.59}, {0.84, 1.61}, {3.93, 4.03}, {7.31, 7.38}, {7.31, 7.35},
+      {3.72, 4.26}, {10.55, 10.61}, {7.30, 7.40}, {4.05, 5.17}, {2.52, 3.05}};
   return t[gen][dtype == PRAND_F64 ? 1 : 0];
 }
 
