@@ -83,6 +83,19 @@ module prand
       integer(c_int), value :: gen, nlimbs
       integer(c_int) :: prand_skipahead
     end function
+    function prand_seed_host(gen, seed, h_state) bind(C, name="prand_seed_host")
+      import :: c_int, c_int64_t, c_ptr
+      type(c_ptr), value :: h_state
+      integer(c_int), value :: gen
+      integer(c_int64_t), value :: seed
+      integer(c_int) :: prand_seed_host
+    end function
+    function prand_init_default_host(gen, h_state) bind(C, name="prand_init_default_host")
+      import :: c_int, c_ptr
+      type(c_ptr), value :: h_state
+      integer(c_int), value :: gen
+      integer(c_int) :: prand_init_default_host
+    end function
     function prand_init_stream(ctx, gen, variant, id, h_state) bind(C, name="prand_init_stream")
       import :: c_int, c_int64_t, c_ptr
       type(c_ptr), value :: ctx, h_state

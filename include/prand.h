@@ -132,6 +132,15 @@ int prand_init_default(prand_ctx* ctx, int gen, void* h_state);
    output of seed ^ (0x9E3779B97F4A7C15 * (gen + 1)).  Blocks. */
 int prand_seed(prand_ctx* ctx, int gen, uint64_t seed, void* h_state);
 
+/* Host-only forms of prand_seed and prand_init_default (section
+   "Function call interface", "Initialization": rng_init_ and its seeded
+   form are callable from host code): the same states, computed on the CPU
+   by the library's seeding code, with no context and no GPU.  h_state:
+   prand_state_bytes(gen) bytes, written.  PRAND_EINVAL for an unknown
+   generator or a null state. */
+int prand_seed_host(int gen, uint64_t seed, void* h_state);
+int prand_init_default_host(int gen, void* h_state);
+
 /* count states from count seeds, on the device: the seeded form of
    rng_init_, which the paper provides in device code too (section
    "Function call interface", "Initialization").  d_seeds: count uint64;

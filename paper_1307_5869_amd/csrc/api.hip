@@ -73,6 +73,10 @@ constexpr bool byte_tables_match() {
 }
 static_assert(byte_tables_match(), "byte tables built for another block exponent");
 
+// the documented default seed of each generator: MT19937 5489, MRG32K3A and
+// LFSR113 12345, GM/GQ 0
+uint64_t default_seed(int gen) { return gen == PRAND_MT19937 ? 5489 : (gen <= PRAND_LFSR113 ? 12345 : 0); }
+
 int block_log2(int gen, int variant) {
   if (!valid_gen(gen) || variant < PRAND_SEQ_DEFAULT || variant > PRAND_SEQ_LONG) return PRAND_EINVAL;
   if (variant == PRAND_SEQ_DEFAULT) {
@@ -416,7 +420,7 @@ int prand_ctx_create(prand_ctx** out, int hip_device) {
     // default states: the documented default seed of each generator
     uint64_t seeds[PRAND_NUM_GENERATORS];
     for (int gidx = 0; gidx < PRAND_NUM_GENERATORS; gidx++)
-      seeds[gidx] = gidx == PRAND_MT19937 ? 5489 : (gidx <= PRAND_LFSR113 ? 12345 : 0);
+      seeds[gidx] = default_seed(gidx);
     e = hipMemcpy(c->scratch, seeds, sizeof seeds, hipMemcpyHostToDevice);
     for (int gidx = 0; gidx < PRAND_NUM_GENERATORS && e == hipSuccess; gidx++)
       e = launch_seed(gidx, (const uint64_t*)c->scratch + gidx, 1, (char*)c->T.defaults + kDefaultStride * gidx,
@@ -474,6 +478,18 @@ int prand_seed(prand_ctx* c, int gen, uint64_t seed, void* h_state) {
   if (e == hipSuccess) e = launch_seed(gen, d_seed, 1, d_state, nullptr);
   if (e == hipSuccess) e = hipMemcpy(h_state, d_state, state_bytes(gen), hipMemcpyDeviceToHost);
   return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
+int prand_seed_host(int gen, uint64_t seed, void* h_state) {
+  if (!valid_gen(gen) || !h_state) return PRAND_EINVAL;
+  seed_host(gen, seed, h_state);
+  return PRAND_OK;
+}
+
+int prand_init_default_host(int gen, void* h_state) {
+  if (!valid_gen(gen) || !h_state) return PRAND_EINVAL;
+  seed_host(gen, default_seed(gen), h_state);
+  return PRAND_OK;
 }
 
 int prand_init_default(prand_ctx* c, int gen, void* h_state) {

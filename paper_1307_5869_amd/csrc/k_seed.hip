@@ -11,30 +11,31 @@
 //   until below the bound; an MRG triple or a GM element pair that is zero
 //   (mod p) is drawn again; an LFSR word is redrawn until its top p bits are
 //   not all zero.
+// The same functions serve the device kernel and the host-only entry points.
 #include "prand_impl.h"
 
 namespace prand {
 namespace {
 
-__device__ __forceinline__ uint64_t splitmix64(uint64_t& s) {
+__host__ __device__ inline uint64_t splitmix64(uint64_t& s) {
   uint64_t z = (s += 0x9E3779B97F4A7C15ull);
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
-__device__ __forceinline__ uint64_t seed_start(uint64_t seed, int gen) {
+__host__ __device__ inline uint64_t seed_start(uint64_t seed, int gen) {
   uint64_t t = seed ^ (0x9E3779B97F4A7C15ull * (uint64_t)(gen + 1));
   return splitmix64(t);
 }
-__device__ __forceinline__ uint64_t draw_below(uint64_t& s, uint64_t bound) {
-  const int nb = 64 - __clzll((long long)(bound - 1));
+__host__ __device__ inline uint64_t draw_below(uint64_t& s, uint64_t bound) {
+  const int nb = 64 - __builtin_clzll(bound - 1);   // bound >= 2
   for (;;) {
     const uint64_t r = splitmix64(s) >> (64 - nb);
     if (r < bound) return r;
   }
 }
 
-__device__ void seed_mt(MtState* st, uint64_t seed) {
+__host__ __device__ void seed_mt(MtState* st, uint64_t seed) {
   uint32_t* mt = st->mt;
   auto genrand = [&](uint32_t s) {
     mt[0] = s;
@@ -63,7 +64,7 @@ __device__ void seed_mt(MtState* st, uint64_t seed) {
   st->pad[0] = st->pad[1] = st->pad[2] = 0;
 }
 
-__device__ void seed_mrg(MrgState* st, uint64_t seed) {
+__host__ __device__ void seed_mrg(MrgState* st, uint64_t seed) {
   if (seed >= 1 && seed < kMrgM2) {
     for (int i = 0; i < 3; i++) { st->x[i] = (uint32_t)seed; st->y[i] = (uint32_t)seed; }
     return;
@@ -75,7 +76,7 @@ __device__ void seed_mrg(MrgState* st, uint64_t seed) {
   for (int i = 0; i < 3; i++) { st->x[i] = x[i]; st->y[i] = y[i]; }
 }
 
-__device__ void seed_lfsr(LfsrState* st, uint64_t seed) {
+__host__ __device__ void seed_lfsr(LfsrState* st, uint64_t seed) {
   if (seed >= 128 && seed <= 0xFFFFFFFFull) {
     for (int c = 0; c < 4; c++) st->z[c] = (uint32_t)seed;
     return;
@@ -90,7 +91,7 @@ __device__ void seed_lfsr(LfsrState* st, uint64_t seed) {
   }
 }
 
-__device__ void seed_gm(int gen, GmState* st, uint64_t seed) {
+__host__ __device__ void seed_gm(int gen, GmState* st, uint64_t seed) {
   const GmParams& P = kGmParams[gen - PRAND_GM19];
   const uint64_t g = P.p << P.t;
   uint64_t sm = seed_start(seed, gen);
@@ -109,20 +110,32 @@ __device__ void seed_gm(int gen, GmState* st, uint64_t seed) {
   st->pad = 0;
 }
 
+__host__ __device__ void seed_one(int gen, uint64_t seed, void* state) {
+  switch (gen) {
+    case PRAND_MT19937: seed_mt((MtState*)state, seed); break;
+    case PRAND_MRG32K3A: seed_mrg((MrgState*)state, seed); break;
+    case PRAND_LFSR113: seed_lfsr((LfsrState*)state, seed); break;
+    default: seed_gm(gen, (GmState*)state, seed); break;
+  }
+}
+
+__host__ __device__ inline size_t state_size(int gen) {
+  return gen == PRAND_MT19937 ? sizeof(MtState)
+         : gen == PRAND_MRG32K3A ? sizeof(MrgState)
+         : gen == PRAND_LFSR113 ? sizeof(LfsrState)
+                                : sizeof(GmState);
+}
+
 __global__ void __launch_bounds__(256) seed_kernel(int gen, const uint64_t* __restrict__ seeds, uint32_t count,
                                                    void* __restrict__ states) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
-  const uint64_t seed = seeds[i];
-  switch (gen) {
-    case PRAND_MT19937: seed_mt((MtState*)states + i, seed); break;
-    case PRAND_MRG32K3A: seed_mrg((MrgState*)states + i, seed); break;
-    case PRAND_LFSR113: seed_lfsr((LfsrState*)states + i, seed); break;
-    default: seed_gm(gen, (GmState*)states + i, seed); break;
-  }
+  seed_one(gen, seeds[i], (char*)states + (size_t)i * state_size(gen));
 }
 
 }  // namespace
+
+void seed_host(int gen, uint64_t seed, void* h_state) { seed_one(gen, seed, h_state); }
 
 hipError_t launch_seed(int gen, const uint64_t* seeds, uint32_t count, void* states, hipStream_t st) {
   if (count == 0) return hipSuccess;

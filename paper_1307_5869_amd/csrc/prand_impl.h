@@ -170,6 +170,8 @@ hipError_t launch_gm_jump(const DeviceTables& T, int gen, GmState* states, uint3
                           const GmState* base, hipStream_t st);
 
 hipError_t launch_seed(int gen, const uint64_t* seeds, uint32_t count, void* states, hipStream_t st);
+// the same seeding on the host (no GPU): one state blob of `gen`
+void seed_host(int gen, uint64_t seed, void* h_state);
 
 // ---- host-side table construction (context set-up) ----
 struct HostTables {

@@ -33,6 +33,8 @@ _SIGNATURES = {
     "prand_independence_limit": (_i32, [_i32, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "prand_init_default": (_i32, [_vp, _i32, _vp]),
     "prand_seed": (_i32, [_vp, _i32, _u64, _vp]),
+    "prand_seed_host": (_i32, [_i32, _u64, _vp]),
+    "prand_init_default_host": (_i32, [_i32, _vp]),
     "prand_seed_dev": (_i32, [_vp, _i32, _vp, _u32, _vp, _vp]),
     "prand_skipahead": (_i32, [_vp, _i32, _vp, _vp, _i32]),
     "prand_skipahead_dev": (_i32, [_vp, _i32, _vp, _u32, _vp, _i32, _i32, _vp]),
@@ -186,6 +188,20 @@ def independence_limit(gen, variant=SEQ_DEFAULT):
     a, b = ctypes.c_double(), ctypes.c_double()
     _chk(load().prand_independence_limit(gen, variant, ctypes.byref(a), ctypes.byref(b)), "independence_limit")
     return a.value, b.value
+
+
+def seed_host(gen, seed):
+    """prand_seed_host: the seeded state, computed on the CPU (no context)."""
+    st = np.zeros(state_bytes(gen), dtype=np.uint8)
+    _chk(load().prand_seed_host(gen, seed, st.ctypes.data), "seed_host")
+    return st
+
+
+def init_default_host(gen):
+    """prand_init_default_host: the default state, computed on the CPU."""
+    st = np.zeros(state_bytes(gen), dtype=np.uint8)
+    _chk(load().prand_init_default_host(gen, st.ctypes.data), "init_default_host")
+    return st
 
 
 class SimdState:

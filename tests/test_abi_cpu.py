@@ -1,12 +1,15 @@
 """CPU checks of the C ABI: the built library loads, exports every symbol the
 header declares, and its host-only metadata (state sizes, block lengths,
-Table 4 limits, error strings) agrees with the oracle and the paper.  No
-compute call is made here (no GPU in this environment)."""
+Table 4 limits, error strings) and host-only seeding agree with the oracle and
+the paper.  No GPU call is made here (no GPU in this environment)."""
 import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
+
+from paper_1307_5869_amd import prand as P
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "prand.h")
@@ -109,3 +112,27 @@ def test_mt_block_ladder_top_entry_matches_oracle(lib, oracle):
     assert oracle.mt_reduce(as_int(inv) << 1, bitwise=False) == 1
     assert f(10, 3, out, inv) == 0
     assert as_int(out) == oracle.mt_jump_poly(624 << 13)
+
+
+SEEDS = [0, 1, 127, 128, 12345, 2**31 - 1, 2**32 - 1, 2**32, 2**63 + 5, 2**64 - 1, 4294944443, 4294944442]
+
+
+@pytest.mark.parametrize("gen", range(11))
+def test_host_seeding_matches_oracle(oracle, gen):
+    """prand_seed_host / prand_init_default_host: the library's seeding code
+    run on the CPU, no context and no GPU, against the oracle (both
+    branches of every generator's seeding: verbatim seeds and the SplitMix64
+    expansion)."""
+    for s in SEEDS:
+        assert np.array_equal(P.seed_host(gen, s), oracle.seed(gen, s)), (P.NAMES[gen], s)
+    assert np.array_equal(P.init_default_host(gen), oracle.init_default(gen)), P.NAMES[gen]
+
+
+def test_host_seeding_errors(lib):
+    lib = P.load()
+    st = np.zeros(4096, dtype=np.uint8)
+    assert lib.prand_seed_host(11, 1, st.ctypes.data) == P.EINVAL
+    assert lib.prand_seed_host(-1, 1, st.ctypes.data) == P.EINVAL
+    assert lib.prand_seed_host(0, 1, None) == P.EINVAL
+    assert lib.prand_init_default_host(11, st.ctypes.data) == P.EINVAL
+    assert lib.prand_init_default_host(3, None) == P.EINVAL
