@@ -176,7 +176,10 @@ int prand_init_streams_dev(prand_ctx* ctx, int gen, int variant, const void* d_b
    array_[float_|double_], section "Multi-threaded generation"): the array is
    cut into sections that jump to their start and fill in parallel; the
    result equals sequential generation for every n (no divisibility or
-   power-of-two condition).  h_state is advanced by n.  Blocks. */
+   power-of-two condition).  h_state is advanced by n.  The section states
+   live in a device buffer the context keeps between calls (allocated, or
+   grown, only when a call needs more than any earlier one; freed with the
+   context); calls on one context are serialised.  Blocks. */
 int prand_generate(prand_ctx* ctx, int gen, void* h_state, int dtype, void* d_out, uint64_t n,
                    void* stream);
 

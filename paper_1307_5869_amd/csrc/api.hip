@@ -311,10 +311,24 @@ int prand::generate_host_state(prand_ctx* c, int gen, void* h_state, int dtype, 
     d_dist = (uint64_t*)((char*)scratch + dist_off);
     d_states = (char*)scratch + st_off;
   } else {
-    e = hipMalloc(&d_states, nst * sb);
-    if (e == hipSuccess) e = hipMalloc((void**)&d_dist, nst * 8);
-    lk.lock();   // the context's host-call scratch holds the base state
+    // the context's host-call scratch holds the base state; its section
+    // buffer (grown when too small, otherwise reused: no allocation and no
+    // implicit device synchronisation per call) the distances and states
+    lk.lock();
     d_base = c->scratch;
+    const size_t st_off = (nst * 8 + 255) & ~(size_t)255;
+    const size_t need = st_off + nst * sb;
+    if (need > c->sec_buf_bytes) {
+      (void)hipFree(c->sec_buf);
+      c->sec_buf = nullptr;
+      c->sec_buf_bytes = 0;
+      e = hipMalloc(&c->sec_buf, need);
+      if (e == hipSuccess) c->sec_buf_bytes = need;
+    }
+    if (e == hipSuccess) {
+      d_dist = (uint64_t*)c->sec_buf;
+      d_states = (char*)c->sec_buf + st_off;
+    }
   }
   if (e == hipSuccess) e = hipMemcpyAsync(d_base, h_state, sb, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
@@ -338,11 +352,6 @@ int prand::generate_host_state(prand_ctx* c, int gen, void* h_state, int dtype, 
     e = launch_streams(c, gen, last, last, 1, n - T, dtype, (char*)d_out + T * es, st, !scratch);
   if (e == hipSuccess) e = hipMemcpyAsync(h_state, last, sb, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (!scratch) {
-    lk.unlock();
-    (void)hipFree(d_states);
-    (void)hipFree(d_dist);
-  }
   return e == hipSuccess ? PRAND_OK : hipfail(c, e);
 }
 
@@ -453,6 +462,7 @@ int prand_ctx_destroy(prand_ctx* c) {
   (void)hipFree(c->T.mtinv);
   (void)hipFree(c->T.defaults);
   (void)hipFree(c->scratch);
+  (void)hipFree(c->sec_buf);
   for (auto& v : c->sec_tabs)
     for (auto& t : v) (void)hipFree(t.second);
   delete c;

@@ -221,8 +221,12 @@ struct prand_ctx {
   char arch[64] = {0};
   prand::DeviceTables T;
   bool mt_ready = false;
-  std::mutex mu;          // guards mt_ready and the host-call scratch
+  std::mutex mu;          // guards mt_ready, the host-call scratch and the section buffer
   void* scratch = nullptr;
+  // prand_generate's section states and distances, kept between calls and
+  // grown when a call needs more (freed with the context)
+  void* sec_buf = nullptr;
+  size_t sec_buf_bytes = 0;
   int last_hip = 0;
   // section-start tables by section length, [0] MRG32K3A, [1] LFSR113
   // (built on first use, immutable afterwards, freed with the context)
