@@ -291,7 +291,7 @@ def recorded_traffic(kernel):
     import hashlib
     import re
 
-    names = {"MT19937 jump": "mt_jump_kernel"}
+    names = {"MT19937 jump": "mt_jump_kernel<1>"}
     want = names.get(kernel)
     if want is None:
         return None
@@ -537,7 +537,7 @@ def serve_trace(ctx, rate, seconds):
     t_arr, gens, ids, ns, dts = W.serving_requests(rate=rate, seconds=seconds)
     cfg = P.ServerConfig(hbm_budget=64 << 30)
     srv = P.Server(ctx, cfg)
-    lat, numbers, rejected = [], 0, 0
+    lat, tags, numbers, rejected = [], [], 0, 0
     first_t, last_t = None, 0.0
     t0 = srv.clock()
     next_log = 10.0
@@ -546,6 +546,7 @@ def serve_trace(ctx, rate, seconds):
         nonlocal numbers, first_t, last_t
         for c in srv.poll(wait_ms=wait_ms):
             lat.append(c.t_done - (t0 + t_arr[c.tag]))   # from the scheduled arrival
+            tags.append(c.tag)
             numbers += c.n
             first_t = c.t_submit if first_t is None else min(first_t, c.t_submit)
             last_t = max(last_t, c.t_done)
@@ -572,6 +573,20 @@ def serve_trace(ctx, rate, seconds):
     srv.close()
     lat_ms = np.array(lat) * 1e3
     span = last_t - (first_t or 0.0)
+    # where the tail comes from: percentiles per generator and per length decade
+    tg = np.array(tags, dtype=np.int64)
+    by_gen = {}
+    for g in range(P.NUM_GENERATORS):
+        v = lat_ms[gens[tg] == g] if lat else np.array([])
+        if v.size:
+            by_gen[P.NAMES[g]] = {"p50_ms": round(float(np.percentile(v, 50)), 3),
+                                  "p99_ms": round(float(np.percentile(v, 99)), 3)}
+    by_len = {}
+    dec = np.floor(np.log10(np.maximum(ns[tg], 1))).astype(int) if lat else np.array([])
+    for d in sorted(set(dec.tolist())):
+        v = lat_ms[dec == d]
+        by_len[f"1e{d}"] = {"requests": int(v.size), "p50_ms": round(float(np.percentile(v, 50)), 3),
+                            "p99_ms": round(float(np.percentile(v, 99)), 3)}
     offered = float(ns.sum()) / seconds
     return {"requests": int(len(t_arr)), "completed": len(lat), "rejected": rejected, "rate_per_s": rate,
             "seconds": seconds, "offered_numbers_per_s": offered,
@@ -579,6 +594,7 @@ def serve_trace(ctx, rate, seconds):
             "p50_ms": float(np.percentile(lat_ms, 50)) if lat else None,
             "p99_ms": float(np.percentile(lat_ms, 99)) if lat else None,
             "max_ms": float(lat_ms.max()) if lat else None,
+            "by_generator": by_gen, "by_length_decade": by_len,
             "hbm_budget": st["hbm_budget"], "hbm_peak": st["hbm_peak"], "iterations": st["iterations"],
             "gpu_busy_frac": st["gpu_busy_s"] / span if span > 0 else None,
             "workload": "Poisson arrivals, gen and dtype uniform, ids uniform in [0,1e19), n log-uniform [1e3,1e8]"}

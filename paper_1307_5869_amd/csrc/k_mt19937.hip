@@ -21,7 +21,9 @@
 // into an LDS ring, and lane l accumulates outputs t = 10l .. 10l+9 while a
 // register window of 10 sequence words slides over the coefficients, so each
 // coefficient costs one LDS read per lane and set coefficients cost 10
-// three-input XORs per two.
+// three-input XORs per two.  Launches of few streams (stream starts served
+// one request at a time) give each stream a workgroup of 12 or 8 wavefronts
+// that scan separate coefficient ranges and XOR their partial windows.
 #include "dev_mt.h"
 #include "mt_poly.h"
 #include "prand_batch.h"
@@ -48,6 +50,12 @@ __global__ void __launch_bounds__(64) mt_generate_kernel(MtState* states, uint32
 }
 
 // ------------------------------------------------------------------ jump
+// Launches of few streams jump each stream with several wavefronts (12 up to
+// 512 streams, 8 up to 2048; one-stream starts from the default state measured
+// 0.27 and 0.31 ms against 1.28 ms with one wavefront; at 4096 streams the
+// ranges' repeated recurrence runs cost more than the shorter chains save).
+constexpr uint32_t kMtSplit12MaxCount = 512;
+constexpr uint32_t kMtSplit8MaxCount = 2048;
 constexpr int kRing = 1024;                 // LDS ring of sequence words (< 900 live at a time)
 constexpr int kMask = kRing - 1;
 constexpr int kMirror = 16;                 // ring[0..15] repeated after the end
@@ -61,19 +69,48 @@ __device__ __forceinline__ void wait_lds_but3() { __builtin_amdgcn_s_waitcnt(0xC
 
 // Extend the ring to hold seq[0..upto) (227 words per phase).  Words landing
 // in the first kMirror slots are also written after the ring's end, so that
-// kPer consecutive words can be read from any slot without wrapping.
+// kPer consecutive words can be read from any slot without wrapping.  The
+// ring belongs to one wavefront.  kBatched: a phase reads only words of
+// earlier phases (j - 227 and below), so all its reads are issued before its
+// writes, one LDS latency per phase; it takes 12 more registers, so it is
+// used where no scan registers are live (the run up to a range's start).
+template <bool kBatched>
 __device__ __forceinline__ void extend(uint32_t* ring, int& gen_hi, int upto, int lane) {
   if (upto > kSeqLen) upto = kSeqLen;
   while (gen_hi < upto) {
     const int g0 = gen_hi;
     const int g1 = (g0 + 227 < kSeqLen) ? g0 + 227 : kSeqLen;
-    for (int j = g0 + lane; j < g1; j += 64) {
-      const uint32_t v = recur(ring[(j - 624) & kMask], ring[(j - 623) & kMask], ring[(j - 227) & kMask]);
-      const int slot = j & kMask;
-      ring[slot] = v;
-      if (slot < kMirror) ring[slot + kRing] = v;
+    if constexpr (kBatched) {
+      uint32_t x0[4], x1[4], xm[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const int j = g0 + lane + 64 * k;
+        if (j < g1) {
+          x0[k] = ring[(j - 624) & kMask];
+          x1[k] = ring[(j - 623) & kMask];
+          xm[k] = ring[(j - 227) & kMask];
+        }
+      }
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const int j = g0 + lane + 64 * k;
+        if (j < g1) {
+          const uint32_t v = recur(x0[k], x1[k], xm[k]);
+          const int slot = j & kMask;
+          ring[slot] = v;
+          if (slot < kMirror) ring[slot + kRing] = v;
+        }
+      }
+    } else {
+      for (int j = g0 + lane; j < g1; j += 64) {
+        const uint32_t v = recur(ring[(j - 624) & kMask], ring[(j - 623) & kMask], ring[(j - 227) & kMask]);
+        const int slot = j & kMask;
+        ring[slot] = v;
+        if (slot < kMirror) ring[slot + kRing] = v;
+      }
     }
-    __syncthreads();
+    wave_lds_sync();
     gen_hi = g1;
   }
 }
@@ -149,15 +186,25 @@ __device__ __forceinline__ uint32_t poly_word(PolyBuf pb, uint32_t w) {
   return __builtin_amdgcn_raw_buffer_load_b32(pb, off, 0, 0);
 }
 
-__device__ __forceinline__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, int lane) {
+// The sum over the coefficients c0 <= i < c1 of poly into acc (lane l holds
+// outputs t = 10 l + r) for the window ring[0..623]; c0 a multiple of kStep,
+// c1 one too or kDeg.  The ring is extended as far as the range needs; a
+// range that starts later first runs the recurrence up to it.
+__device__ __forceinline__ void scan_range(uint32_t* ring, const uint32_t* __restrict__ poly, int lane, uint32_t c0,
+                                           uint32_t c1, uint32_t (&sum)[kPer]) {
+  uint32_t acc[kPer];   // local: the groups' code is built on a register array
   int gen_hi = 624;
-  extend(ring, gen_hi, kStepReach, lane);
-  uint32_t acc[kPer], wa[kPer], wb[kPer], wc[kPer];
+  extend<true>(ring, gen_hi, (int)c0 + kStepReach, lane);
+  uint32_t wa[kPer], wb[kPer], wc[kPer];
+  // the first two windows, read as group() reads the later ones (an even
+  // slot; words past the ring's end are in its mirror)
+  const uint32_t* w0 = ring + ((c0 + kPer * lane) & (kMask & ~1));
+  const uint32_t* w1 = ring + ((c0 + kPer + kPer * lane) & (kMask & ~1));
 #pragma unroll
   for (int r = 0; r < kPer; r++) {
     acc[r] = 0;
-    wa[r] = ring[kPer * lane + r];
-    wb[r] = ring[kPer + kPer * lane + r];
+    wa[r] = w0[r];
+    wb[r] = w1[r];
   }
   // bits i1 .. i1 + 59 lie in the words i1 / 32 .. i1 / 32 + 2 (the last
   // step's third word is past the polynomial and reads as zero).  The ring
@@ -166,10 +213,10 @@ __device__ __forceinline__ void apply_poly(uint32_t* ring, const uint32_t* __res
   // the words past it meet only coefficients at or above 19937, which are
   // zero, or outputs t >= 624, which are dropped).
   const PolyBuf pb = poly_buffer(poly);
-  uint32_t i1 = 0;
-  uint32_t n0 = poly_word(pb, 0), n1 = poly_word(pb, 1), n2 = poly_word(pb, 2);
-  while (i1 < (uint32_t)kDeg) {
-    extend(ring, gen_hi, (int)i1 + kStepReach, lane);
+  uint32_t i1 = c0;
+  uint32_t n0 = poly_word(pb, c0 >> 5), n1 = poly_word(pb, (c0 >> 5) + 1), n2 = poly_word(pb, (c0 >> 5) + 2);
+  while (i1 < c1) {
+    extend<false>(ring, gen_hi, (int)i1 + kStepReach, lane);
     const uint32_t lim = (gen_hi >= kSeqLen) ? (uint32_t)kDeg : (uint32_t)(gen_hi - kStepReach);
     do {
       const uint32_t p0 = __builtin_amdgcn_readfirstlane(n0), p1 = __builtin_amdgcn_readfirstlane(n1),
@@ -189,13 +236,76 @@ __device__ __forceinline__ void apply_poly(uint32_t* ring, const uint32_t* __res
       group<4 * kPer>(ring, i1 + 4 * kPer, b0, b1, lane, acc, wb, wc, wa);
       group<5 * kPer>(ring, i1 + 5 * kPer, b0, b1, lane, acc, wc, wa, wb);
       i1 += kStep;
-    } while (i1 <= lim && i1 < (uint32_t)kDeg);
+    } while (i1 <= lim && i1 < c1);
   }
+#pragma unroll
+  for (int r = 0; r < kPer; r++) sum[r] = acc[r];
+}
+
+__device__ __forceinline__ void apply_poly(uint32_t* ring, const uint32_t* __restrict__ poly, int lane) {
+  uint32_t acc[kPer];
+  scan_range(ring, poly, lane, 0, (uint32_t)kDeg, acc);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kPer; r++) {
     const int t = kPer * lane + r;
     if (t < 624) ring[t] = (t == 0) ? (acc[r] & kUpper) : acc[r];
+  }
+  __syncthreads();
+}
+
+// apply_poly by kParts wavefronts of one workgroup, for few streams: the
+// coefficients are cut into kParts ranges of kChunk (a multiple of kStep),
+// wavefront w scans range w in its own ring rings[w] (first running the
+// recurrence up to the range's start), and the partial sums, which add up to
+// the whole because g(A) Y is linear in the coefficients, are XORed together
+// through LDS and the result copied into every ring.  A lone stream's
+// polynomial then takes the time of one range plus the recurrence up to it
+// instead of the whole scan (the ranges' recurrence runs are repeated work,
+// which is why many streams keep one wavefront each).
+template <int kParts>
+struct Split {
+  static constexpr uint32_t kChunk = ((kDeg + kParts - 1) / kParts + kStep - 1) / kStep * kStep;
+  static constexpr int kThreads = 64 * kParts;
+  static constexpr int kWords = (624 + kThreads - 1) / kThreads;   // combined words per thread
+  static_assert(kChunk * (kParts - 1) < (uint32_t)kDeg, "every range holds coefficients");
+};
+
+template <int kParts>
+__device__ __forceinline__ void apply_poly_split(uint32_t (*rings)[kRing + kMirror], const uint32_t* __restrict__ poly,
+                                                 int lane, int part) {
+  using S = Split<kParts>;
+  uint32_t* ring = rings[part];
+  const uint32_t c0 = (uint32_t)part * S::kChunk;
+  const uint32_t c1 = c0 + S::kChunk < (uint32_t)kDeg ? c0 + S::kChunk : (uint32_t)kDeg;
+  uint32_t acc[kPer];
+  scan_range(ring, poly, lane, c0, c1, acc);
+  wave_lds_sync();   // the wavefront's reads of its ring are done
+#pragma unroll
+  for (int r = 0; r < kPer; r++) {
+    const int t = kPer * lane + r;
+    if (t < 624) ring[t] = acc[r];
+  }
+  __syncthreads();   // every partial in place
+  uint32_t v[S::kWords];
+#pragma unroll
+  for (int k = 0; k < S::kWords; k++) {
+    const int t = (int)threadIdx.x + S::kThreads * k;
+    v[k] = 0;
+    if (t < 624) {
+#pragma unroll
+      for (int p = 0; p < kParts; p++) v[k] ^= rings[p][t];
+      if (t == 0) v[k] &= kUpper;
+    }
+  }
+  __syncthreads();   // every partial read
+#pragma unroll
+  for (int k = 0; k < S::kWords; k++) {
+    const int t = (int)threadIdx.x + S::kThreads * k;
+    if (t < 624) {
+#pragma unroll
+      for (int p = 0; p < kParts; p++) rings[p][t] = v[k];
+    }
   }
   __syncthreads();
 }
@@ -213,7 +323,10 @@ __device__ __forceinline__ int next_bit(const uint64_t (&N)[kMaxLimbs], int from
   return -1;
 }
 
-__global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ states, uint32_t count,
+// kParts = 1: one wavefront per stream; more: a workgroup of kParts
+// wavefronts per stream, each polynomial applied by apply_poly_split.
+template <int kParts>
+__global__ void __launch_bounds__(64 * kParts) mt_jump_kernel(MtState* __restrict__ states, uint32_t count,
                                                      const uint64_t* __restrict__ dist, int nlimbs, int per_stream,
                                                      const uint64_t* __restrict__ ids, int block_e,
                                                      const MtState* __restrict__ base,
@@ -221,10 +334,19 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
                                                      const uint32_t* __restrict__ ladder,
                                                      const uint32_t* __restrict__ diglo,
                                                      const uint32_t* __restrict__ dig8hi) {
-  __shared__ __align__(16) uint32_t ring[kRing + kMirror];
+  __shared__ __align__(16) uint32_t rings[kParts][kRing + kMirror];
   const uint32_t s = blockIdx.x;
   if (s >= count) return;
-  const int lane = threadIdx.x;
+  // the scan is one long chain of dependent scalar tests and branches: where
+  // its wavefronts share a SIMD with other kernels' (a served stream start
+  // beside generation chunks), the highest wave priority lets the chain
+  // issue first instead of waiting behind the others' VALU work
+  __builtin_amdgcn_s_setprio(3);
+  const int lane = threadIdx.x & 63;
+  // the wavefront's part, uniform across it (its coefficient range is scanned
+  // by scalar branching)
+  const int part = kParts > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
+  uint32_t* ring = rings[part];
   // block splitting from the default state: start from the precomputed
   // state of the id's top 16 bits
   const bool digit_path = ids && block_e == kMtDigitE;
@@ -243,7 +365,7 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
   }
   for (int i = lane; i < 624; i += 64) ring[i] = src->mt[i];
   uint32_t idx = src->idx < 624u ? src->idx : 624u;
-  __syncthreads();
+  wave_lds_sync();
   // the polynomials to apply, in order: for block splitting from a
   // block-aligned state, id * 2^432 with the low 48 bits of id as 16-bit
   // digits and the top 16 bits as two bytes, one table polynomial
@@ -295,8 +417,10 @@ __global__ void __launch_bounds__(64) mt_jump_kernel(MtState* __restrict__ state
       }
     }
     if (!poly) break;
-    apply_poly(ring, poly, lane);
+    if constexpr (kParts > 1) apply_poly_split<kParts>(rings, poly, lane, part);
+    else apply_poly(ring, poly, lane);
   }
+  if (part) return;
   MtState* dst = states + s;
   for (int i = lane; i < 624; i += 64) dst->mt[i] = ring[i];
   if (lane == 0) {
@@ -368,8 +492,15 @@ hipError_t launch_mt_generate(MtState* states, uint32_t count, uint64_t n, int d
 
 hipError_t launch_mt_jump(const DeviceTables& T, MtState* states, uint32_t count, const JumpSpec& js,
                           const MtState* base, hipStream_t st) {
-  hipLaunchKernelGGL(mt_jump_kernel, dim3(count), dim3(64), 0, st, states, count, js.dist, js.nlimbs, js.per_stream,
-                     js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi);
+  if (count <= kMtSplit12MaxCount)
+    hipLaunchKernelGGL(mt_jump_kernel<12>, dim3(count), dim3(64 * 12), 0, st, states, count, js.dist, js.nlimbs,
+                       js.per_stream, js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi);
+  else if (count <= kMtSplit8MaxCount)
+    hipLaunchKernelGGL(mt_jump_kernel<8>, dim3(count), dim3(64 * 8), 0, st, states, count, js.dist, js.nlimbs,
+                       js.per_stream, js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi);
+  else
+    hipLaunchKernelGGL(mt_jump_kernel<1>, dim3(count), dim3(64), 0, st, states, count, js.dist, js.nlimbs,
+                       js.per_stream, js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi);
   return hipGetLastError();
 }
 

@@ -225,6 +225,55 @@ def test_init_streams_from_explicit_base(ctx, oracle, gen, consumed):
         assert np.array_equal(st, oracle.init_stream(gen, 0, sid, base=base)), sid
 
 
+@pytest.mark.parametrize("kind", ["ids", "distances"])
+def test_mt19937_jump_launch_shapes_agree(ctx, oracle, kind):
+    """MT19937 jumps run with 12 or 8 wavefronts per stream (coefficient
+    ranges scanned apart, partial windows XORed) in launches of few streams
+    and with one wavefront per stream in larger ones.  Launches of 300, 1500
+    and 2500 streams over the same inputs (a prefix of one another, one launch
+    of each shape) agree on every shared stream, and sampled streams of each
+    launch, the first, the last and one in between, equal the oracle.  ids:
+    block splitting from the default state (digit tables); distances:
+    per-stream skip-ahead from states at various places in their blocks
+    (ladder polynomials)."""
+    gen, sb = P.MT19937, P.state_bytes(P.MT19937)
+    rng = np.random.default_rng(5869)
+    total = 2500
+    if kind == "ids":
+        ids = rng.integers(0, 2**63, total, dtype=np.int64).astype(np.uint64) * np.uint64(2) + np.uint64(1)
+        ids[:4] = [0, 1, 2**64 - 1, 1 << 48]
+        dev_ids = torch.from_numpy(ids.view(np.int64)).cuda()
+        bases = None
+    else:
+        bases = [oracle.seed(gen, 4000 + i) for i in range(5)]
+        for i, b in enumerate(bases):
+            oracle.generate(gen, b, [0, 1, 300, 623, 624][i])
+        dists = [int(x) >> int(y) for x, y in zip(rng.integers(1, 2**63, total), rng.integers(0, 40, total))]
+        dists[:3] = [0, 1, 624 * 2**12]
+        limbs = torch.from_numpy(np.stack([P.limbs(x)[:2] for x in dists]).view(np.int64)).cuda()
+        start = np.concatenate([bases[i % 5] for i in range(total)])
+    results = {}
+    for count in (300, 1500, 2500):
+        if kind == "ids":
+            d = torch.empty(count * sb, dtype=torch.uint8, device="cuda")
+            ctx.init_streams_dev(gen, P.SEQ_DEFAULT, None, dev_ids, count, d)
+        else:
+            d = torch.from_numpy(start[:count * sb].copy()).cuda()
+            ctx.skipahead_dev(gen, d, count, limbs, 2, True)
+        torch.cuda.synchronize()
+        results[count] = d.cpu().numpy()
+    for count in (300, 1500):
+        assert np.array_equal(results[count], results[2500][:count * sb]), count
+    for count in (300, 1500, 2500):
+        for i in (0, count // 2 + 1, count - 1):
+            got = results[count][i * sb:(i + 1) * sb]
+            if kind == "ids":
+                ref = oracle.init_stream(gen, P.SEQ_DEFAULT, int(ids[i]))
+            else:
+                ref = oracle.skipahead(gen, bases[i % 5].copy(), dists[i])
+            assert np.array_equal(got, ref), (count, i)
+
+
 SECTIONED_N = {0: 3 * 2**18 + 7, 1: 300001, 2: 300001}
 
 
