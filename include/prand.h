@@ -286,7 +286,9 @@ int prand_batch_tiles(const prand_batch* batch, uint32_t* ntiles);
 int prand_batch_destroy(prand_batch* batch);
 
 /* Time candidate configurations on these tasks (their outputs and output
-   states are overwritten) and return the fastest in *best.  When the
+   states are overwritten) and return the fastest in *best: each candidate
+   scored by the slowest of three launches, then the best three re-timed over
+   six launches each and ranked by their mean.  When the
    environment variable PRAND_TUNE_CACHE names a file, results are kept there
    keyed by the device and a signature of the task mix, and reused.  Blocks. */
 int prand_batch_autotune(prand_ctx* ctx, const prand_task* h_tasks, uint32_t ntasks, prand_batch_config* best);
@@ -313,7 +315,7 @@ typedef struct prand_server_config {
   uint64_t min_chunk;       /* smallest per-request share of an iteration (0: 2^16) */
   uint64_t mt_chunk;        /* largest MT19937 chunk per iteration (one wavefront each; 0: 2^20) */
   uint64_t mt_section;      /* MT19937 requests longer than this are cut into up to 64 sections that
-                               start from jumped states and run in parallel (0: 2^22) */
+                               start from jumped states and run in parallel (0: 2^20) */
   uint32_t max_active;      /* requests generating at once (0: 8192) */
   uint32_t max_queue;       /* waiting requests beyond which submissions are rejected (0: 2^20) */
   uint32_t waves_per_block; /* batch kernel shape, as prand_batch_config (0: defaults) */

@@ -131,6 +131,9 @@ struct Req {
 };
 
 constexpr uint32_t kMaxSections = 64;
+// shortest MT19937 section: 624 * 2^kMinSectionLog2 outputs, about 1.3 ms
+// on the one wavefront that generates a section
+constexpr int kMinSectionLog2 = 10;
 
 struct ScatterItem {
   const uint32_t* src;
@@ -224,13 +227,13 @@ void fill_config(prand_server_config& c) {
   if (!c.iter_numbers) c.iter_numbers = 1ull << 28;
   if (!c.min_chunk) c.min_chunk = 1ull << 16;
   if (!c.mt_chunk) c.mt_chunk = 1ull << 20;
-  if (!c.mt_section) c.mt_section = 1ull << 22;
+  if (!c.mt_section) c.mt_section = 1ull << 20;
   if (!c.max_active) c.max_active = 8192;
   if (!c.max_queue) c.max_queue = 1u << 20;
 }
 
 // Sections of a request: MT19937 requests longer than mt_section are cut into
-// at most kMaxSections of 624 * 2^k outputs (k >= 12), so that every section
+// at most kMaxSections of 624 * 2^k outputs (k >= kMinSectionLog2), so that every section
 // starts on a twist-block boundary of the stream (block-splitting states sit
 // on one) and its start distance has few set bits.  A jump yields the
 // canonical state, which differs from the sequentially reached one only in
@@ -238,7 +241,7 @@ void fill_config(prand_server_config& c) {
 // outputs and the last section's final state equal sequential generation.
 uint64_t section_len(const prand_request& r, const prand_server_config& cfg) {
   if (r.gen != PRAND_MT19937 || r.n <= cfg.mt_section) return r.n;
-  uint64_t len = 624ull << 12;
+  uint64_t len = 624ull << kMinSectionLog2;
   while ((r.n + len - 1) / len > kMaxSections) len <<= 1;
   return len;
 }

@@ -124,13 +124,23 @@ def test_serve_long_requests_continue_exactly(ctx, oracle):
 
 def test_serve_long_mt_requests_in_sections(ctx):
     """MT19937 requests above the section threshold are cut into sections of
-    624 * 2^12 words that start from jumped states; outputs and the final
-    state equal one sequential stream."""
+    624 * 2^k words that start from jumped states; outputs and the final
+    state equal one sequential stream.  Both the configured threshold 2^22 and
+    the default (2^20, sections from 624 * 2^10 words)."""
     sec = 624 << 12
     cfg = P.ServerConfig(hbm_budget=1 << 30, mt_section=1 << 22, mt_chunk=1 << 19)
     srv = P.Server(ctx, cfg)
     reqs = [(P.MT19937, 4242, (1 << 22) + 1, P.U32), (P.MT19937, 10**19 - 3, 2 * sec, P.F64),
             (P.MT19937, 7, 3 * sec + 12345, P.F32), (P.MT19937, 1 << 50, 1 << 22, P.U32)]
+    tickets = {srv.submit(g, sid, n, dt): k for k, (g, sid, n, dt) in enumerate(reqs)}
+    got = drain(srv, len(reqs))
+    for t, c in got.items():
+        g, sid, n, dt = reqs[tickets[t]]
+        check_completion(ctx, c, g, sid, n, dt)
+        srv.release(t)
+    srv.close()
+    srv = P.Server(ctx, P.ServerConfig(hbm_budget=1 << 30))
+    reqs = [(P.MT19937, 99, (1 << 20) + 1, P.U32), (P.MT19937, 2**63 + 1, 5 * (624 << 10) - 1, P.F32)]
     tickets = {srv.submit(g, sid, n, dt): k for k, (g, sid, n, dt) in enumerate(reqs)}
     got = drain(srv, len(reqs))
     for t, c in got.items():
