@@ -98,7 +98,11 @@ int prand_last_hip_error(const prand_ctx* ctx);
    call interface for MRG32K3A / MT19937"): matrix powers A^(2^j), B^(2^j) for
    MRG32K3A, 32x32 F2 matrix powers for LFSR113, 2x2 matrix powers for GM/GQ,
    and x^(2^j) mod phi for MT19937 (equation g_v; phi is computed once by
-   Berlekamp-Massey).  *ctx is set to NULL on failure. */
+   Berlekamp-Massey).  The MT19937 tables (656 MB: the ladder, the digit
+   tables of block splitting and the 65536 precomputed top-16-bit states)
+   are built when a call first needs them and are shared by all contexts on
+   the same device, freed with the last of them.  *ctx is set to NULL on
+   failure. */
 int prand_ctx_create(prand_ctx** ctx, int hip_device);
 
 /* Free the context's device tables (rng_free_device_consts_).  NULL is OK. */

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -99,9 +100,62 @@ hipError_t upload(T** dst, const T* src, size_t n) {
   return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
 }
 
+// The MT19937 tables (656 MB, read-only once built) are shared by the
+// contexts of one device: the first context that needs them builds them, the
+// others take references, the last one to go frees them.
+struct MtTables {
+  uint32_t *mt = nullptr, *mtblk = nullptr, *mtinv = nullptr, *mtdiglo = nullptr, *mtdig8hi = nullptr;
+  void* mttop = nullptr;
+  int refs = 0;
+};
+std::mutex g_mt_mu;
+std::map<int, MtTables> g_mt_tables;   // by device
+
+void take_mt_tables(prand_ctx* c, const MtTables& t) {
+  c->T.mt = t.mt;
+  c->T.mtblk = t.mtblk;
+  c->T.mtinv = t.mtinv;
+  c->T.mtdiglo = t.mtdiglo;
+  c->T.mtdig8hi = t.mtdig8hi;
+  c->T.mttop = t.mttop;
+  c->mt_ready = true;
+}
+
+void free_mt_fields(prand_ctx* c) {
+  (void)hipFree(c->T.mt);
+  (void)hipFree(c->T.mtdiglo);
+  (void)hipFree(c->T.mtdig8hi);
+  (void)hipFree(c->T.mttop);
+  (void)hipFree(c->T.mtblk);
+  (void)hipFree(c->T.mtinv);
+}
+
+// a context's share of the tables goes (at destruction; its device current)
+void release_mt_tables(prand_ctx* c) {
+  if (!c->mt_ready) {
+    free_mt_fields(c);   // what a failed build left, if anything
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_mt_mu);
+  auto it = g_mt_tables.find(c->device);
+  if (it != g_mt_tables.end() && --it->second.refs == 0) {
+    free_mt_fields(c);
+    g_mt_tables.erase(it);
+  }
+}
+
 hipError_t ensure_mt(prand_ctx* c) {
   // caller holds c->mu
   if (c->mt_ready) return hipSuccess;
+  std::lock_guard<std::mutex> glk(g_mt_mu);
+  {
+    auto it = g_mt_tables.find(c->device);
+    if (it != g_mt_tables.end()) {
+      it->second.refs++;
+      take_mt_tables(c, it->second);
+      return hipSuccess;
+    }
+  }
   std::vector<uint32_t> mt((size_t)kLadder * 624), dlo((size_t)kMtLoDigits * kMtLoSize * 624),
       d8((size_t)2 * 256 * 624);
   std::vector<uint32_t> blk((size_t)kMtBlkPolys * 624), inv(624);
@@ -132,7 +186,18 @@ hipError_t ensure_mt(prand_ctx* c) {
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   (void)hipFree(d_ids);
-  if (e == hipSuccess) c->mt_ready = true;
+  if (e == hipSuccess) {
+    MtTables t;
+    t.mt = c->T.mt;
+    t.mtblk = c->T.mtblk;
+    t.mtinv = c->T.mtinv;
+    t.mtdiglo = c->T.mtdiglo;
+    t.mtdig8hi = c->T.mtdig8hi;
+    t.mttop = c->T.mttop;
+    t.refs = 1;
+    g_mt_tables[c->device] = t;
+    c->mt_ready = true;
+  }
   return e;
 }
 
@@ -454,12 +519,7 @@ int prand_ctx_destroy(prand_ctx* c) {
   (void)hipFree(c->T.gmbyte);
   (void)hipFree(c->T.gmneg);
   (void)hipFree(c->T.lfsrbyte);
-  (void)hipFree(c->T.mt);
-  (void)hipFree(c->T.mtdiglo);
-  (void)hipFree(c->T.mtdig8hi);
-  (void)hipFree(c->T.mttop);
-  (void)hipFree(c->T.mtblk);
-  (void)hipFree(c->T.mtinv);
+  release_mt_tables(c);
   (void)hipFree(c->T.defaults);
   (void)hipFree(c->scratch);
   (void)hipFree(c->sec_buf);
