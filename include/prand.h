@@ -318,8 +318,9 @@ typedef struct prand_server_config {
   uint64_t iter_numbers;    /* outputs per loop iteration over all requests (0: 2^28) */
   uint64_t min_chunk;       /* smallest per-request share of an iteration (0: 2^16) */
   uint64_t mt_chunk;        /* largest MT19937 chunk per iteration (one wavefront each; 0: 2^20) */
-  uint64_t mt_section;      /* MT19937 requests longer than this are cut into up to 64 sections that
-                               start from jumped states and run in parallel (0: 2^20) */
+  uint64_t mt_section;      /* MT19937 requests longer than this are cut into up to 256 sections of
+                               624 * 2^k outputs (k >= 10) that start from jumped states and run in
+                               parallel (0: 2^20) */
   uint32_t max_active;      /* requests generating at once (0: 8192) */
   uint32_t max_queue;       /* waiting requests beyond which submissions are rejected (0: 2^20) */
   uint32_t waves_per_block; /* batch kernel shape, as prand_batch_config (0: defaults) */

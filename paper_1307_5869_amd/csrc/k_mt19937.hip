@@ -333,7 +333,8 @@ __global__ void __launch_bounds__(64 * kParts) mt_jump_kernel(MtState* __restric
                                                      const MtState* __restrict__ top,
                                                      const uint32_t* __restrict__ ladder,
                                                      const uint32_t* __restrict__ diglo,
-                                                     const uint32_t* __restrict__ dig8hi) {
+                                                     const uint32_t* __restrict__ dig8hi,
+                                                     const uint32_t* __restrict__ blk, int blocks) {
   __shared__ __align__(16) uint32_t rings[kParts][kRing + kMirror];
   const uint32_t s = blockIdx.x;
   if (s >= count) return;
@@ -376,7 +377,19 @@ __global__ void __launch_bounds__(64 * kParts) mt_jump_kernel(MtState* __restric
   // copy of the polynomial code.
   const bool use_digits = digit_path && idx == 624;
   const uint64_t id = ids ? ids[s] : 0;
-  if (!use_digits) {
+  // distances D in whole sections: from a block boundary, and D within the
+  // table, one whole-block polynomial per set bit of D (the state stays on a
+  // boundary); otherwise the distance in outputs, D (624 2^kMtBlkFirst),
+  // through the ladder
+  const bool sec_units = blocks && !ids;
+  const bool use_blocks = sec_units && idx == 624 && (N[0] >> kMtBlkPolys) == 0;
+  if (sec_units && !use_blocks) {
+    constexpr uint64_t kSec = 624ull << kMtBlkFirst;
+    const uint64_t d = N[0];
+    N[0] = d * kSec;
+    N[1] = __umul64hi(d, kSec);
+  }
+  if (!use_digits && !use_blocks) {
     const uint64_t rest = 624 - idx;
     bool small = true;
     for (int l = 1; l < kMaxLimbs; l++) small = small && (N[l] == 0);
@@ -412,7 +425,7 @@ __global__ void __launch_bounds__(64 * kParts) mt_jump_kernel(MtState* __restric
     } else {
       const int b = next_bit(N, pos);
       if (b >= 0) {
-        poly = ladder + (size_t)b * 624;
+        poly = (use_blocks ? blk : ladder) + (size_t)b * 624;
         pos = b + 1;
       }
     }
@@ -492,15 +505,20 @@ hipError_t launch_mt_generate(MtState* states, uint32_t count, uint64_t n, int d
 
 hipError_t launch_mt_jump(const DeviceTables& T, MtState* states, uint32_t count, const JumpSpec& js,
                           const MtState* base, hipStream_t st) {
+  // whole-section distances: one limb per stream
+  if (js.mt_blocks && (js.ids || !js.per_stream || js.nlimbs != 1)) return hipErrorInvalidValue;
   if (count <= kMtSplit12MaxCount)
     hipLaunchKernelGGL(mt_jump_kernel<12>, dim3(count), dim3(64 * 12), 0, st, states, count, js.dist, js.nlimbs,
-                       js.per_stream, js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi);
+                       js.per_stream, js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi,
+                       T.mtblk, js.mt_blocks);
   else if (count <= kMtSplit8MaxCount)
     hipLaunchKernelGGL(mt_jump_kernel<8>, dim3(count), dim3(64 * 8), 0, st, states, count, js.dist, js.nlimbs,
-                       js.per_stream, js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi);
+                       js.per_stream, js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi,
+                       T.mtblk, js.mt_blocks);
   else
     hipLaunchKernelGGL(mt_jump_kernel<1>, dim3(count), dim3(64), 0, st, states, count, js.dist, js.nlimbs,
-                       js.per_stream, js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi);
+                       js.per_stream, js.ids, js.block_e, base, (const MtState*)js.mt_top, T.mt, T.mtdiglo, T.mtdig8hi,
+                       T.mtblk, js.mt_blocks);
   return hipGetLastError();
 }
 

@@ -144,6 +144,11 @@ struct JumpSpec {
   // MT19937 block splitting from the default state: the states of the top
   // 16 bits of an id (DeviceTables::mttop), or null
   const void* mt_top = nullptr;
+  // MT19937, per-stream one-limb distances: counted in whole sections of
+  // 624 2^kMtBlkFirst outputs (jumped by the whole-block table, one
+  // polynomial per set bit, where the state sits on a block boundary and the
+  // distance is below 2^kMtBlkPolys sections; otherwise through the ladder)
+  int mt_blocks = 0;
 };
 
 // sectab: the section-start table of seclen, or null (ladder jumps)

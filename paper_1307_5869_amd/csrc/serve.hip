@@ -130,10 +130,11 @@ struct Req {
   bool complete = false;         // last chunk finished
 };
 
-constexpr uint32_t kMaxSections = 64;
+constexpr uint32_t kMaxSections = 256;
 // shortest MT19937 section: 624 * 2^kMinSectionLog2 outputs, about 1.3 ms
 // on the one wavefront that generates a section
 constexpr int kMinSectionLog2 = 10;
+static_assert(kMinSectionLog2 >= kMtBlkFirst, "sections are whole-block-table units");
 
 struct ScatterItem {
   const uint32_t* src;
@@ -384,8 +385,10 @@ int admit_and_init(prand_server* s, int li) {
       ib.h_items[items].words = sb / 4;
       items++;
     }
+    // section starts in whole sections of 624 2^kMtBlkFirst outputs (every
+    // section length is a multiple of one)
     if (r->secs.size() > 1)
-      for (const Section& q : r->secs) ib.h_dist[dists++] = q.start;
+      for (const Section& q : r->secs) ib.h_dist[dists++] = q.start / kMtSection;
   }
   group_start.push_back(n);
   hipError_t e = hipMemcpyAsync(ib.d_ids, ib.h_ids, n * sizeof(uint64_t), hipMemcpyHostToDevice, L.init_st);
@@ -411,6 +414,7 @@ int admit_and_init(prand_server* s, int li) {
     js.dist = ib.d_dist + d0;
     js.nlimbs = 1;
     js.per_stream = 1;
+    js.mt_blocks = 1;
     e = launch_mt_jump(s->ctx->T, (MtState*)r->secs[0].st[0], (uint32_t)r->secs.size(), js, nullptr, L.init_st);
     d0 += (uint32_t)r->secs.size();
   }

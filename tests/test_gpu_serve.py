@@ -139,8 +139,11 @@ def test_serve_long_mt_requests_in_sections(ctx):
         check_completion(ctx, c, g, sid, n, dt)
         srv.release(t)
     srv.close()
+    # default threshold; the last request takes 150 sections (section starts
+    # from the whole-block table up to section number 149)
     srv = P.Server(ctx, P.ServerConfig(hbm_budget=1 << 30))
-    reqs = [(P.MT19937, 99, (1 << 20) + 1, P.U32), (P.MT19937, 2**63 + 1, 5 * (624 << 10) - 1, P.F32)]
+    reqs = [(P.MT19937, 99, (1 << 20) + 1, P.U32), (P.MT19937, 2**63 + 1, 5 * (624 << 10) - 1, P.F32),
+            (P.MT19937, 31337, 150 * (624 << 10) - 17, P.U32)]
     tickets = {srv.submit(g, sid, n, dt): k for k, (g, sid, n, dt) in enumerate(reqs)}
     got = drain(srv, len(reqs))
     for t, c in got.items():
