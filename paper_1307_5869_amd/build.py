@@ -48,8 +48,11 @@ HOST_SOURCE_FLAGS = {"simd_host.cpp": ["-O3", "-ffp-contract=off"]}
 # of common code the test of the next bit, which both successors of a test
 # make, stays a plain compare and branch in each (hoisted, it is carried as
 # a lane mask and costs three more scalar instructions per group).
+# Tail merging is off so that the repeated tests after each pair of
+# coefficients (mt_pairs.inc) stay in place.
 SOURCE_FLAGS = {"k_mt19937.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions",
-                                  "-mllvm", "-simplifycfg-hoist-common=false"]}
+                                  "-mllvm", "-simplifycfg-hoist-common=false",
+                                  "-mllvm", "-enable-tail-merge=false"]}
 
 
 def _compile(src):

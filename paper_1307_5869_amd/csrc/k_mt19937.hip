@@ -130,9 +130,10 @@ __device__ __forceinline__ void extend(uint32_t* ring, int& gen_hi, int upto, in
 // next set bit of its group and the two are added with one three-input XOR
 // (gfx950 v_bitop3_b32, truth table 0x96) per output word: a group with c set
 // coefficients costs ceil(c / 2) instead of c vector instructions per output
-// word.  The scan is a chain of labels joined by gotos (mt_pairs.inc), built
-// with the structurizer told to leave uniform regions alone, so every test is
-// one scalar compare and branch.
+// word.  The scan is a chain of labels joined by gotos (mt_pairs.inc; after a
+// pair the remaining nothing-pending tests are repeated in place, one taken
+// branch less per pair), built with the structurizer told to leave uniform
+// regions alone, so every test is one scalar compare and branch.
 template <int kOff>
 __device__ __forceinline__ void group(uint32_t* ring, uint32_t i0, uint32_t lo, uint32_t hi, int lane,
                                       uint32_t (&acc)[kPer],
