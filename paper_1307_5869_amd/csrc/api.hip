@@ -570,6 +570,27 @@ int prand_init_default(prand_ctx* c, int gen, void* h_state) {
   return e == hipSuccess ? PRAND_OK : hipfail(c, e);
 }
 
+// Not in the public header (a test hook): jumps `count` MT19937 states by
+// d_sections[i] whole sections of 624 * 2^kMtBlkFirst outputs each, the way
+// the serving loop starts its sections (the whole-block table from a block
+// boundary and below 2^kMtBlkPolys sections, the ladder otherwise).
+int prand_internal_mt_jump_sections(prand_ctx* c, void* d_states, uint32_t count, const uint64_t* d_sections,
+                                    void* stream) {
+  if (!c) return PRAND_EINVAL;
+  if (count == 0) return PRAND_OK;
+  if (!d_states || !d_sections) return PRAND_EINVAL;
+  DeviceGuard g(c->device);
+  int rc = ensure_mt_locked(c, PRAND_MT19937);
+  if (rc) return rc;
+  JumpSpec js;
+  js.dist = d_sections;
+  js.nlimbs = 1;
+  js.per_stream = 1;
+  js.mt_blocks = 1;
+  hipError_t e = launch_mt_jump(c->T, (MtState*)d_states, count, js, nullptr, (hipStream_t)stream);
+  return e == hipSuccess ? PRAND_OK : hipfail(c, e);
+}
+
 int prand_skipahead_dev(prand_ctx* c, int gen, void* d_states, uint32_t count, const uint64_t* d_dist, int nlimbs,
                         int per_stream, void* stream) {
   if (!c || !valid_gen(gen) || nlimbs < 0 || nlimbs > kMaxLimbs) return PRAND_EINVAL;

@@ -368,3 +368,38 @@ def test_generate_streams_captured_then_eager(ctx, oracle, gen):
     torch.cuda.synchronize()
     ref = np.concatenate([oracle.generate(gen, st, n) for st in states])
     np.testing.assert_array_equal(out_np(out, P.U32), ref, err_msg="eager after capture")
+
+
+def test_mt19937_whole_section_jumps(ctx, oracle):
+    """Section starts as the serving loop makes them: each state jumped by a
+    number of whole sections of 624 * 2^10 outputs, through the whole-block
+    table from a block boundary (below 2^22 sections) and through the ladder
+    otherwise (mid-block states, 2^22 sections and more).  Every state equals
+    the oracle's skip-ahead by the same number of outputs, in a launch of 12
+    wavefronts per stream and, repeated, of one wavefront per stream."""
+    import ctypes
+    gen, sb, sec = P.MT19937, P.state_bytes(P.MT19937), 624 << 10
+    lib = P.load()
+    f = lib.prand_internal_mt_jump_sections
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    counts = [0, 1, 2, 3, 5, 149, 255, 2**21 + 3, 2**22 - 1, 2**22, 2**40 + 7]
+    starts, dists = [], []
+    for i, consumed in enumerate([0, 300, 624, 1]):
+        st = oracle.seed(gen, 777 + i)
+        if consumed:
+            oracle.generate(gen, st, consumed)
+        for d in counts:
+            starts.append(st.copy())
+            dists.append(d)
+    n = len(starts)
+    refs = [oracle.skipahead(gen, s.copy(), d * sec) for s, d in zip(starts, dists)]
+    for reps in (1, 3000 // n + 1):
+        count = n * reps
+        d_states = torch.from_numpy(np.concatenate(starts * reps)).cuda()
+        d_secs = torch.tensor(np.array(dists * reps, dtype=np.uint64).view(np.int64), device="cuda")
+        assert f(ctx.handle, d_states.data_ptr(), count, d_secs.data_ptr(), None) == P.OK
+        torch.cuda.synchronize()
+        got = d_states.cpu().numpy()
+        for k in range(count):
+            assert np.array_equal(got[k * sb:(k + 1) * sb], refs[k % n]), (count, k, dists[k % n])
